@@ -1,0 +1,229 @@
+/*
+ * lbm.h -- C ABI of the MI355X lattice Boltzmann engine with the single-node
+ * second-order boundary scheme of Zhao & Yong, "A family of single-node
+ * second-order boundary schemes for the lattice Boltzmann method".
+ *
+ * One time step (paper, Section 2) is
+ *   collision   f'_i(x,t) = f_i(x,t) + Omega_i(x,t)                 Eq. (22a)
+ *   advection   f_i(x+e_i, t+1) = f'_i(x,t)                          Eq. (22b)
+ * with the MRT collision of the Appendix (equilibrium Eq. (42)), and on
+ * every cut link (x_f, i) -- x_f fluid, x_f - e_i solid, wall at
+ * x_b = x_f - gamma e_i, gamma in (0,1] -- the single-node scheme
+ *   f_i(x_f,t+1) = (1-b) f_i(x_f,t) + b [ (1+l-2g)/(1+l) f_ibar(x_f,t)
+ *                 + l/(1+l) f'_i(x_f,t) + (2g-l)/(1+l) f'_ibar(x_f,t)
+ *                 + 2/(1+l) * 3 w_i rho0 e_i.phi(x_b,t) ]                Eq. (213)
+ * (Eq. (210) when b = 1), l = l(gamma) inside the band of Eq. (212).
+ *
+ * Units: lattice units, h = dt = c = 1, c_s^2 = 1/3.
+ * Layout: node index n = x + nx*(y + ny*z), x fastest; 2D lattices have
+ * nz = 1.  Distributions are handled as deviations from the rest state,
+ * delta f_i = f_i - w_i rho0, stored structure-of-arrays [Q][N] on the GPU.
+ *
+ * Conventions for every call:
+ *  - Return value: LBM_OK (0) or a negative LBM_E* code; the message is
+ *    available from lbm_last_error().  No C++ exception crosses the ABI.
+ *  - Host input arrays are copied during the call; the caller keeps them.
+ *    Host output arrays are caller-allocated with the stated sizes.
+ *    Pointers named *_dev are device memory owned by the caller.
+ *  - A handle is not thread-safe; separate handles are independent.
+ *  - lbm_step, lbm_run_checkpointed and lbm_adjoint only enqueue work on the
+ *    handle's stream; calls that return host data synchronise that stream.
+ *    A kernel fault surfaces as LBM_EDEVICE at the next synchronising call.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm lbm_t;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,      /* bad argument value */
+    LBM_EGEOM = -2,       /* solid mask and cut links are inconsistent */
+    LBM_ESTATE = -3,      /* call out of order (e.g. step before geometry) */
+    LBM_ENOMEM = -4,      /* device or host allocation failed */
+    LBM_EDEVICE = -5,     /* HIP runtime error */
+    LBM_ENONFINITE = -6   /* a reduction met a NaN or infinity */
+};
+
+/* lattices: velocity orderings are reported by lbm_lattice_info().
+ * D2Q9 is ordered as in the paper's Appendix; D3Q19 is rest, the six axis
+ * vectors (+x,-x,+y,-y,+z,-z), then the twelve edge vectors. */
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+
+/* precision: FP64 stores and computes delta f in double; FP32 stores and
+ * computes delta f in float.  In both, the per-link coefficients, the
+ * boundary combination, reductions and gradient sums are double. */
+enum { LBM_FP64 = 0, LBM_FP32 = 1 };
+
+/* l(gamma) rules; the first five are the paper's Section 3 choices, ZERO is
+ * Remark (5)'s nonconvex member, MIN = max(0, 2 gamma - 1) is the lower edge
+ * of Eq. (212) and the only convex rule listed that reproduces half-way
+ * bounce-back (Eq. (26)) at gamma = 1/2.  Default: LBM_L_MIN. */
+enum {
+    LBM_L_GAMMA = 0, LBM_L_1P5GAMMA = 1, LBM_L_2GAMMA = 2, LBM_L_GAMMA2 = 3,
+    LBM_L_GAMMA2_PLUS_GAMMA = 4, LBM_L_ZERO = 5, LBM_L_MIN = 6
+};
+
+/* x boundary: y and z are always periodic.
+ * PERIODIC: periodic x.
+ * PRESSURE: periodic x with a density jump drho: a population that crosses
+ *   from x = nx-1 to x = 0 gains w_i*drho, one crossing the other way loses
+ *   w_i*drho (a pressure drop c_s^2*drho per period).
+ * OUTFLOW: column x = 0 must be solid; at x = nx-1 a population moving in
+ *   -x is read from (nx-1, y-e_y, z-e_z) (zero x-gradient). */
+enum { LBM_X_PERIODIC = 0, LBM_X_PRESSURE = 1, LBM_X_OUTFLOW = 2 };
+
+/* objectives for the adjoint: J = mean over steps t in [t_begin, t_end) of
+ * FORCE_X: x component of the momentum-exchange force on the links with the
+ *   given tag during step t -> t+1,
+ *   sum_links (e_ibar)_x (f'_ibar(x_f,t) + f_i(x_f,t+1));
+ * MEAN_UX: mean of u_x(x,t) over the fluid nodes. */
+enum { LBM_OBJ_NONE = 0, LBM_OBJ_FORCE_X = 1, LBM_OBJ_MEAN_UX = 2 };
+
+/* Create a solver.  s: Q relaxation rates in the row order of the lattice's
+ * moment matrix (rows for conserved moments -- density and momentum -- are
+ * ignored because their non-equilibrium part vanishes); each other rate in
+ * (0, 2).  rho0 > 0 is the mean density of Eq. (42).  g: body force per unit
+ * mass (D values) or NULL; it enters the collision as 3 w_i rho0 e_i.g.
+ * Allocates the distribution arrays on the current HIP device.
+ * Errors: EINVAL (lattice, precision, sizes, rates), ENOMEM, EDEVICE. */
+int lbm_create(lbm_t **out, int lattice, int precision, int64_t nx,
+               int64_t ny, int64_t nz, const double *s, double rho0,
+               const double *g);
+
+/* Choose l(gamma) and b of Eq. (213); b in (0, 1].  Must precede
+ * lbm_set_geometry.  Errors: EINVAL, ESTATE (geometry already set). */
+int lbm_set_scheme(lbm_t *h, int l_rule, double b);
+
+/* Choose the x boundary (see above); drho is used by LBM_X_PRESSURE only.
+ * Must precede lbm_set_geometry.  Errors: EINVAL, ESTATE. */
+int lbm_set_x_boundary(lbm_t *h, int kind, double drho);
+
+/* Set the obstacle geometry.
+ * solid: N bytes (1 = solid, 0 = fluid).
+ * n_links cut links (x_f, i), sorted by (node, dir) or not (they are sorted
+ * here): node[k] the fluid node x_f, dir[k] the direction i with x_f - e_i
+ * solid, q[k] = gamma in (0, 1], wall_u[k*D + a] = phi(x_b) (NULL = 0),
+ * tag[k] >= 0 an obstacle label for forces and objectives (NULL = 0).
+ * A fluid direction whose pull source is solid must be listed, once, and a
+ * listed direction must have a solid pull source.  The coefficients of
+ * Eq. (213) are computed here in double and checked against Eq. (212).
+ * Errors: EINVAL (q, rule violates Eq. (212), more than 2^26 links),
+ * EGEOM (inconsistent mask/links, fluid at x = 0 with OUTFLOW), ENOMEM. */
+int lbm_set_geometry(lbm_t *h, const uint8_t *solid, int64_t n_links,
+                     const int64_t *node, const int8_t *dir, const double *q,
+                     const double *wall_u, const int32_t *tag);
+
+/* Replace the per-link gamma and wall velocity of the current geometry (same
+ * links, same order as given to lbm_set_geometry); recomputes coefficients.
+ * Either pointer may be NULL to keep the current values. */
+int lbm_update_links(lbm_t *h, const double *q, const double *wall_u);
+
+/* Initial state f(x,0) = f^eq(rho(x), u(x)) of Eq. (42) at fluid nodes.
+ * rho: N values or NULL (rho0); u: N*D values, u[n*D + a], or NULL (0).
+ * Resets the time counter to 0.  With LBM_X_OUTFLOW, the outlet column's
+ * -x populations are represented through the zero-gradient rule (exact for
+ * x-uniform initial fields there).  Errors: ESTATE, ENOMEM, EDEVICE. */
+int lbm_init(lbm_t *h, const double *rho, const double *u);
+
+/* Initial state given as deviations df[i*N + n] = f_i(n,0) - w_i rho0
+ * (solid entries ignored).  Resets the time counter to 0. */
+int lbm_init_deviation(lbm_t *h, const double *df);
+
+/* Enqueue n >= 0 time steps. */
+int lbm_step(lbm_t *h, int64_t n);
+
+/* Current time (number of steps taken since init or set_state). */
+int64_t lbm_time(const lbm_t *h);
+
+/* Macroscopic fields at the current time t, from f(x,t):
+ * rho[n] = rho0 + sum_i delta f_i, u[n*D + a] = sum_i e_ia f_i / rho0.
+ * Solid nodes get NaN.  Either pointer may be NULL.  Synchronises. */
+int lbm_moments(lbm_t *h, double *rho, double *u);
+
+/* Pre-collision deviations df[i*N + n] = f_i(n,t) - w_i rho0 at the current
+ * time (NaN at solid nodes).  Synchronises. */
+int lbm_get_distribution(lbm_t *h, double *df);
+
+/* Totals at the current time over fluid nodes, summed in double:
+ * mass = sum rho, mom[a] = sum rho0 u_a.  ENONFINITE if either is not
+ * finite.  Synchronises. */
+int lbm_reduce(lbm_t *h, double *mass, double *mom);
+
+/* Momentum-exchange force of the most recent step t-1 -> t on each tag:
+ * force[tag*D + a] = sum over the tag's links of
+ * (e_ibar)_a (f'_ibar(x_f,t-1) + f_i(x_f,t)), absolute (not deviation)
+ * values, for tags 0 .. n_tags-1.  ESTATE before the first step. */
+int lbm_force(lbm_t *h, int32_t n_tags, double *force);
+
+/* Device state: the post-collision array and the link slots; together with
+ * lbm_time() they determine every later step.  dst/src are device buffers
+ * of lbm_state_bytes() bytes owned by the caller. */
+int64_t lbm_state_bytes(const lbm_t *h);
+int lbm_get_state(lbm_t *h, void *dst_dev);
+int lbm_set_state(lbm_t *h, const void *src_dev, int64_t time);
+
+/* Objective of the adjoint (see LBM_OBJ_*); resets its accumulator.  The
+ * accumulation happens during later lbm_step / lbm_run_checkpointed calls
+ * whose steps fall in [t_begin, t_end). */
+int lbm_set_objective(lbm_t *h, int kind, int32_t tag, int64_t t_begin,
+                      int64_t t_end);
+
+/* Value of the objective accumulated so far.  Synchronises. */
+int lbm_objective(lbm_t *h, double *J);
+
+/* Run n steps from the current state keeping a snapshot every `every` steps
+ * in library-owned device memory, so that lbm_adjoint() can later replay
+ * each segment (sqrt(n) checkpointing when every ~ sqrt(n)).  Memory:
+ * (n/every + 1) + (every + 1) states of lbm_state_bytes().  The objective
+ * accumulates as in lbm_step.  Errors: ESTATE, EINVAL, ENOMEM. */
+int lbm_run_checkpointed(lbm_t *h, int64_t n, int64_t every);
+
+/* Reverse sweep over the last lbm_run_checkpointed() run: for each segment
+ * from the last, restore its snapshot, replay it recording every state, and
+ * run the adjoint steps backwards, accumulating in double the gradients of
+ * the objective.  Leaves the forward state at the end of the run. */
+int lbm_adjoint(lbm_t *h);
+
+/* Gradients of J from the last lbm_adjoint(), in double: dq[k] = dJ/dgamma_k
+ * (l follows gamma through the rule), dwall_u[k*D + a] = dJ/dphi_k,a,
+ * dg[a] = dJ/dg_a, ds[k] = dJ/ds_k for the relaxation rates.  Any pointer
+ * may be NULL.  Synchronises. */
+int lbm_grad(lbm_t *h, double *dq, double *dwall_u, double *dg, double *ds);
+
+/* Adjoint state lambda(t0) = dJ/df(x, t0) at the start of the last run,
+ * lam[i*N + n] (0 at solid nodes).  Synchronises. */
+int lbm_get_adjoint(lbm_t *h, double *lam);
+
+/* Use a caller-provided HIP stream (hipStream_t as void*; NULL = the
+ * library's own default-priority stream). */
+int lbm_set_stream(lbm_t *h, void *hip_stream);
+
+/* Lattice tables for cross-checks: Q, D, e[i*D + a], w[i], M[k*Q + i]
+ * (moment matrix).  Any output pointer may be NULL.  No GPU needed. */
+int lbm_lattice_info(int lattice, int32_t *Q, int32_t *D, int8_t *e,
+                     double *w, double *M);
+
+/* Counts after lbm_set_geometry: fluid nodes and cut links. */
+int lbm_counts(const lbm_t *h, int64_t *n_fluid, int64_t *n_links);
+
+/* Average duration in milliseconds of the step kernel over the last
+ * lbm_step() call of n >= 1 steps, from HIP events on the handle's stream
+ * (timing enabled by lbm_set_timing(h, 1)). */
+int lbm_set_timing(lbm_t *h, int on);
+int lbm_last_step_ms(lbm_t *h, double *ms_per_step);
+
+const char *lbm_last_error(const lbm_t *h);
+int lbm_destroy(lbm_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -38,7 +38,11 @@ from . import scheme as _scheme
 class Oracle:
     def __init__(self, geom, s, rho0=1.0, g=None, dp=0.0, l_rule="min",
                  b=1.0, deviation=True, q=None, wall_u=None,
-                 allow_nonconvex=False):
+                 allow_nonconvex=False, nodes=None):
+        """nodes: optional sorted array of global node indices to simulate (a
+        window).  Pull sources outside the window read NaN, so after k steps
+        exactly the nodes at least k pulls away from the window's edge are
+        exact; the full domain is used when nodes is None."""
         lat = _lattice.get(geom.lattice)
         self.lat = lat
         self.Q, self.D = lat.Q, lat.D
@@ -49,7 +53,6 @@ class Oracle:
         self.opp = lat.opp
         self.shape = tuple(geom.shape)
         nx, ny, nz = self.shape
-        self.N = nx * ny * nz
         self.x_bc = geom.x_bc
         self.s = np.asarray(s)
         self.rho0 = rho0
@@ -58,11 +61,19 @@ class Oracle:
         self.deviation = deviation
         self.base = self.w * rho0 if deviation else np.zeros(self.Q)
         self.rho_base = rho0 if deviation else 0.0
-        self.fluid = geom.solid == 0
         self.l_rule, self.b = l_rule, b
+        n_all = nx * ny * nz
+        self.window = nodes is not None
+        self.nodes = (np.arange(n_all, dtype=np.int64) if nodes is None
+                      else np.asarray(nodes, dtype=np.int64))
+        self.N = self.nodes.shape[0]
+        self.fluid = np.asarray(geom.solid)[self.nodes] == 0
+        local = np.full(n_all, self.N, dtype=np.int64) if self.window else None
+        if self.window:
+            local[self.nodes] = np.arange(self.N)
 
         # pull table: node read by direction i at node n, and the seam sign
-        n = np.arange(self.N, dtype=np.int64)
+        n = self.nodes
         x, y, z = n % nx, (n // nx) % ny, n // (nx * ny)
         self.src = np.empty((self.Q, self.N), dtype=np.int64)
         self.seam = np.zeros((self.Q, self.N))
@@ -77,15 +88,21 @@ class Oracle:
                 sx = np.mod(sx, nx)
             sy = np.mod(y - lat.e[i, 1], ny)
             sz = np.mod(z - ez[i], nz)
-            self.src[i] = sx + nx * (sy + ny * sz)
+            src = sx + nx * (sy + ny * sz)
+            self.src[i] = local[src] if self.window else src
 
         # cut links and their coefficients, Eq. (213)
-        self.lk_node = np.asarray(geom.node, dtype=np.int64)
-        self.lk_dir = np.asarray(geom.dir, dtype=np.int64)
+        keep = slice(None)
+        lk_node = np.asarray(geom.node, dtype=np.int64)
+        if self.window:
+            keep = local[lk_node] < self.N
+            lk_node = local[lk_node[keep]]
+        self.lk_node = lk_node
+        self.lk_dir = np.asarray(geom.dir, dtype=np.int64)[keep]
         self.lk_opp = self.opp[self.lk_dir]
-        self.lk_tag = np.asarray(geom.tag, dtype=np.int64)
-        self.q = np.asarray(geom.q if q is None else q)
-        self.wall_u = np.asarray(geom.wall_u if wall_u is None else wall_u)
+        self.lk_tag = np.asarray(geom.tag, dtype=np.int64)[keep]
+        self.q = np.asarray(geom.q if q is None else q)[keep]
+        self.wall_u = np.asarray(geom.wall_u if wall_u is None else wall_u)[keep]
         self.l = _scheme.l_of_gamma(l_rule, self.q)
         if not allow_nonconvex and not np.all(_scheme.convex(self.q, self.l)):
             raise ValueError("l(gamma) violates Eq. (212)")
@@ -95,7 +112,8 @@ class Oracle:
         self.wall_term = 3.0 * self.w[self.lk_dir] * rho0 * (e_l * self.wall_u).sum(1)
         # forcing term per direction
         self.F = 3.0 * self.w * rho0 * (self.e @ self.g)
-        self._check_links()
+        if not self.window:
+            self._check_links()
 
     def _check_links(self):
         """A direction at a fluid node is a cut link exactly when the node it
@@ -139,6 +157,8 @@ class Oracle:
         """Eq. (22b) as a pull over the node table; link directions read a
         solid node here and are overwritten by the boundary scheme."""
         rows = np.arange(self.Q)[:, None]
+        if self.window:     # column N stands for every node outside the window
+            fp = np.concatenate([fp, np.full((self.Q, 1), np.nan, dtype=fp.dtype)], axis=1)
         fn = fp[rows, self.src]
         if self.dp != 0.0:
             fn = fn + self.seam * (self.w * self.dp)[:, None]
@@ -210,3 +230,31 @@ class Oracle:
         out = np.zeros((nt, self.D), dtype=contrib.dtype)
         np.add.at(out, self.lk_tag, contrib)
         return out
+
+
+def box_window(shape, node, radius):
+    """Sorted global indices of the periodic box of half-width `radius`
+    around `node` (clipped to the domain extent in each direction)."""
+    nx, ny, nz = shape
+    x, y, z = node % nx, (node // nx) % ny, node // (nx * ny)
+    axes = []
+    for c, n in ((x, nx), (y, ny), (z, nz)):
+        r = min(radius, (n - 1) // 2)
+        axes.append(np.unique(np.mod(np.arange(c - r, c + r + 1), n)))
+    gx, gy, gz = np.meshgrid(*axes, indexing="ij")
+    return np.unique((gx + nx * (gy + ny * gz)).ravel())
+
+
+def sampled_step_outputs(geom, s, df0, steps, samples, radius=None, **kw):
+    """f(x, steps) - w rho0 at the sampled global nodes, each computed on its
+    own window of half-width steps + 1 from the full initial deviations df0
+    (Q, N).  Returns an array (Q, len(samples))."""
+    r = steps + 1 if radius is None else radius
+    out = np.empty((df0.shape[0], len(samples)))
+    for j, n in enumerate(samples):
+        nodes = box_window(tuple(geom.shape), int(n), r)
+        o = Oracle(geom, s, nodes=nodes, **kw)
+        f = o.run(o.init_deviation(df0[:, nodes]), steps)
+        loc = int(np.searchsorted(nodes, n))
+        out[:, j] = o.as_deviation(f)[:, loc]
+    return out

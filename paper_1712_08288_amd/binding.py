@@ -1,0 +1,298 @@
+"""Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every computation runs in the HIP library `_lib/liblbm.so`; importing this
+module fails loudly when the library has not been built.  Host arrays are
+numpy; device buffers (state snapshots) may be torch tensors, of which only
+the data pointer is used.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "HIP engine library %s is missing; build it with "
+        "`python -m paper_1712_08288_amd.build`" % LIB_PATH)
+
+_lib = C.CDLL(LIB_PATH)
+
+_p = C.c_void_p
+_i = C.c_int
+_i32 = C.c_int32
+_i64 = C.c_int64
+_d = C.c_double
+_dp = C.POINTER(C.c_double)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_create = _sig("lbm_create", _i, [C.POINTER(_p), _i, _i, _i64, _i64, _i64, _dp, _d, _dp])
+_set_scheme = _sig("lbm_set_scheme", _i, [_p, _i, _d])
+_set_xbc = _sig("lbm_set_x_boundary", _i, [_p, _i, _d])
+_set_geometry = _sig("lbm_set_geometry", _i, [_p, _p, _i64, _p, _p, _p, _p, _p])
+_update_links = _sig("lbm_update_links", _i, [_p, _p, _p])
+_init = _sig("lbm_init", _i, [_p, _p, _p])
+_init_dev = _sig("lbm_init_deviation", _i, [_p, _p])
+_step = _sig("lbm_step", _i, [_p, _i64])
+_time = _sig("lbm_time", _i64, [_p])
+_moments = _sig("lbm_moments", _i, [_p, _p, _p])
+_get_dist = _sig("lbm_get_distribution", _i, [_p, _p])
+_reduce = _sig("lbm_reduce", _i, [_p, _p, _p])
+_force = _sig("lbm_force", _i, [_p, _i32, _p])
+_state_bytes = _sig("lbm_state_bytes", _i64, [_p])
+_get_state = _sig("lbm_get_state", _i, [_p, _p])
+_set_state = _sig("lbm_set_state", _i, [_p, _p, _i64])
+_set_obj = _sig("lbm_set_objective", _i, [_p, _i, _i32, _i64, _i64])
+_objective = _sig("lbm_objective", _i, [_p, _p])
+_run_ckpt = _sig("lbm_run_checkpointed", _i, [_p, _i64, _i64])
+_adjoint = _sig("lbm_adjoint", _i, [_p])
+_grad = _sig("lbm_grad", _i, [_p, _p, _p, _p, _p])
+_get_adj = _sig("lbm_get_adjoint", _i, [_p, _p])
+_set_stream = _sig("lbm_set_stream", _i, [_p, _p])
+_lat_info = _sig("lbm_lattice_info", _i, [_i, _p, _p, _p, _p, _p])
+_counts = _sig("lbm_counts", _i, [_p, _p, _p])
+_set_timing = _sig("lbm_set_timing", _i, [_p, _i])
+_last_ms = _sig("lbm_last_step_ms", _i, [_p, _p])
+_last_err = _sig("lbm_last_error", C.c_char_p, [_p])
+_destroy = _sig("lbm_destroy", _i, [_p])
+
+EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_x_boundary",
+            "lbm_set_geometry", "lbm_update_links", "lbm_init",
+            "lbm_init_deviation", "lbm_step", "lbm_time", "lbm_moments",
+            "lbm_get_distribution", "lbm_reduce", "lbm_force",
+            "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
+            "lbm_set_objective", "lbm_objective", "lbm_run_checkpointed",
+            "lbm_adjoint", "lbm_grad", "lbm_get_adjoint", "lbm_set_stream",
+            "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
+            "lbm_last_step_ms", "lbm_last_error", "lbm_destroy"]
+
+LATTICES = {"D2Q9": 0, "D3Q19": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+RULES = {"gamma": 0, "1.5gamma": 1, "2gamma": 2, "gamma2": 3,
+         "gamma2+gamma": 4, "zero": 5, "min": 6}
+X_BC = {"periodic": 0, "pressure": 1, "outflow": 2}
+OBJECTIVES = {"none": 0, "force_x": 1, "mean_ux": 2}
+ERRORS = {-1: "EINVAL", -2: "EGEOM", -3: "ESTATE", -4: "ENOMEM",
+          -5: "EDEVICE", -6: "ENONFINITE"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+        self.name = ERRORS.get(code, "?")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_p)
+
+
+def _f64(a, n=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError("expected %d values, got %d" % (n, a.size))
+    return a
+
+
+def lattice_info(lattice):
+    lat = LATTICES[lattice]
+    Q, D = _i32(), _i32()
+    _lat_info(lat, C.byref(Q), C.byref(D), None, None, None)
+    e = np.zeros((Q.value, D.value), np.int8)
+    w = np.zeros(Q.value)
+    M = np.zeros((Q.value, Q.value))
+    rc = _lat_info(lat, None, None, _ptr(e), _ptr(w), _ptr(M))
+    if rc:
+        raise LBMError(rc, "lattice_info")
+    return e.astype(np.int64), w, M
+
+
+class Solver:
+    """One lattice Boltzmann solver on the current HIP device."""
+
+    def __init__(self, lattice, shape, s, rho0=1.0, g=None, precision="fp64"):
+        self.lattice = lattice
+        self.shape = tuple(int(v) for v in shape)
+        e, w, _ = lattice_info(lattice)
+        self.Q, self.D = e.shape
+        self.N = int(np.prod(self.shape))
+        self.precision = precision
+        s = _f64(s, self.Q)
+        g = _f64(np.zeros(self.D) if g is None else np.asarray(g, float)[: self.D], self.D)
+        h = _p()
+        rc = _create(C.byref(h), LATTICES[lattice], PRECISIONS[precision],
+                     self.shape[0], self.shape[1], self.shape[2],
+                     s.ctypes.data_as(_dp), float(rho0), g.ctypes.data_as(_dp))
+        if rc:
+            raise LBMError(rc, "lbm_create")
+        self._h = h
+        self.rho0 = float(rho0)
+
+    # -- helpers
+    def _chk(self, rc, what):
+        if rc:
+            msg = _last_err(self._h)
+            raise LBMError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- set-up
+    def set_scheme(self, l_rule="min", b=1.0):
+        self._chk(_set_scheme(self._h, RULES[l_rule], float(b)), "set_scheme")
+
+    def set_x_boundary(self, kind="periodic", drho=0.0):
+        self._chk(_set_xbc(self._h, X_BC[kind], float(drho)), "set_x_boundary")
+
+    def set_geometry(self, solid, node, dir, q, wall_u=None, tag=None):
+        solid = np.ascontiguousarray(solid, dtype=np.uint8)
+        node = np.ascontiguousarray(node, dtype=np.int64)
+        dir = np.ascontiguousarray(dir, dtype=np.int8)
+        q = _f64(q, node.size)
+        wall_u = _f64(wall_u, node.size * self.D) if wall_u is not None else None
+        tag = np.ascontiguousarray(tag, dtype=np.int32) if tag is not None else None
+        if solid.size != self.N:
+            raise ValueError("solid mask must have N entries")
+        self._chk(_set_geometry(self._h, _ptr(solid), node.size, _ptr(node),
+                                _ptr(dir), _ptr(q), _ptr(wall_u), _ptr(tag)),
+                  "set_geometry")
+
+    def update_links(self, q=None, wall_u=None):
+        q = _f64(q)
+        wall_u = _f64(wall_u)
+        self._chk(_update_links(self._h, _ptr(q), _ptr(wall_u)), "update_links")
+
+    def counts(self):
+        nf, nl = _i64(), _i64()
+        _counts(self._h, C.byref(nf), C.byref(nl))
+        return nf.value, nl.value
+
+    # -- state
+    def init(self, rho=None, u=None):
+        rho = _f64(rho, self.N)
+        u = _f64(u, self.N * self.D)
+        self._chk(_init(self._h, _ptr(rho), _ptr(u)), "init")
+
+    def init_deviation(self, df):
+        df = _f64(df, self.Q * self.N)
+        self._chk(_init_dev(self._h, _ptr(df)), "init_deviation")
+
+    def step(self, n=1):
+        self._chk(_step(self._h, int(n)), "step")
+
+    @property
+    def time(self):
+        return int(_time(self._h))
+
+    def moments(self):
+        rho = np.empty(self.N)
+        u = np.empty((self.N, self.D))
+        self._chk(_moments(self._h, _ptr(rho), _ptr(u)), "moments")
+        return rho, u
+
+    def distribution(self):
+        df = np.empty((self.Q, self.N))
+        self._chk(_get_dist(self._h, _ptr(df)), "get_distribution")
+        return df
+
+    def reduce(self):
+        m = np.zeros(1)
+        mom = np.zeros(self.D)
+        self._chk(_reduce(self._h, _ptr(m), _ptr(mom)), "reduce")
+        return float(m[0]), mom
+
+    def force(self, n_tags):
+        out = np.zeros((n_tags, self.D))
+        self._chk(_force(self._h, int(n_tags), _ptr(out)), "force")
+        return out
+
+    def state_bytes(self):
+        return int(_state_bytes(self._h))
+
+    def get_state(self, dst_ptr):
+        """dst_ptr: device pointer (int) or a torch tensor of state_bytes()."""
+        ptr = dst_ptr.data_ptr() if hasattr(dst_ptr, "data_ptr") else int(dst_ptr)
+        self._chk(_get_state(self._h, _p(ptr)), "get_state")
+
+    def set_state(self, src_ptr, time):
+        ptr = src_ptr.data_ptr() if hasattr(src_ptr, "data_ptr") else int(src_ptr)
+        self._chk(_set_state(self._h, _p(ptr), int(time)), "set_state")
+
+    def set_stream(self, stream):
+        ptr = getattr(stream, "cuda_stream", stream)
+        self._chk(_set_stream(self._h, _p(ptr) if ptr else None), "set_stream")
+
+    # -- objective and adjoint
+    def set_objective(self, kind, tag=0, t_begin=0, t_end=1):
+        self._chk(_set_obj(self._h, OBJECTIVES[kind], int(tag), int(t_begin),
+                           int(t_end)), "set_objective")
+
+    def objective(self):
+        J = np.zeros(1)
+        self._chk(_objective(self._h, _ptr(J)), "objective")
+        return float(J[0])
+
+    def run_checkpointed(self, n, every):
+        self._chk(_run_ckpt(self._h, int(n), int(every)), "run_checkpointed")
+
+    def adjoint(self):
+        self._chk(_adjoint(self._h), "adjoint")
+
+    def grad(self):
+        nf, nl = self.counts()
+        dq = np.zeros(nl)
+        du = np.zeros((nl, self.D))
+        dg = np.zeros(self.D)
+        ds = np.zeros(self.Q)
+        self._chk(_grad(self._h, _ptr(dq), _ptr(du), _ptr(dg), _ptr(ds)), "grad")
+        return dict(q=dq, wall_u=du, g=dg, s=ds)
+
+    def get_adjoint(self):
+        lam = np.empty((self.Q, self.N))
+        self._chk(_get_adj(self._h, _ptr(lam)), "get_adjoint")
+        return lam
+
+    # -- timing
+    def set_timing(self, on=True):
+        self._chk(_set_timing(self._h, 1 if on else 0), "set_timing")
+
+    def last_step_ms(self):
+        ms = np.zeros(1)
+        self._chk(_last_ms(self._h, _ptr(ms)), "last_step_ms")
+        return float(ms[0])
+
+
+def solver_for(geom, s, rho0=1.0, g=None, precision="fp64", l_rule="min",
+               b=1.0, dp=0.0):
+    """Create a Solver and load a workloads.Geometry-like object into it."""
+    sv = Solver(geom.lattice, geom.shape, s, rho0=rho0, g=g, precision=precision)
+    sv.set_scheme(l_rule, b)
+    sv.set_x_boundary(geom.x_bc, dp)
+    sv.set_geometry(geom.solid, geom.node, geom.dir, geom.q, geom.wall_u, geom.tag)
+    return sv

@@ -1,0 +1,926 @@
+// C ABI of the engine: validation, per-link coefficient set-up in double,
+// device memory, the time loop, checkpointed runs and the reverse sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "engine.hpp"
+#include "lattice.hpp"
+
+using lbe::Engine;
+using lbe::Snapshot;
+
+struct lbm {
+    Engine e;
+};
+
+namespace {
+
+int fail(lbm_t* h, int code, const std::string& msg) {
+    if (h) h->e.err = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                              \
+    do {                                                                             \
+        hipError_t _st = (call);                                                     \
+        if (_st != hipSuccess)                                                       \
+            return fail((h), LBM_EDEVICE,                                            \
+                        std::string(#call) + ": " + hipGetErrorString(_st));         \
+    } while (0)
+
+// ---- lattice tables on the host (the same constexpr definitions) -------------
+int lat_Q(int lattice) { return lattice == 0 ? lbe::D2Q9::Q : lbe::D3Q19::Q; }
+int lat_D(int lattice) { return lattice == 0 ? lbe::D2Q9::D : lbe::D3Q19::D; }
+int lat_e(int lattice, int i, int a) {
+    return lattice == 0 ? lbe::D2Q9::E[i][a] : lbe::D3Q19::E[i][a];
+}
+double lat_w(int lattice, int i) {
+    return lattice == 0 ? lbe::D2Q9::W[i] : lbe::D3Q19::W[i];
+}
+int lat_M(int lattice, int k, int i) {
+    return lattice == 0 ? lbe::TAB<lbe::D2Q9>.M[k][i] : lbe::TAB<lbe::D3Q19>.M[k][i];
+}
+bool lat_conserved(int lattice, int k) {
+    return lattice == 0 ? lbe::D2Q9::conserved(k) : lbe::D3Q19::conserved(k);
+}
+
+// ---- the free parameter l(gamma) (paper, Section 3 and Eq. (212)) ------------
+double l_of(int rule, double g) {
+    switch (rule) {
+        case LBM_L_GAMMA: return g;
+        case LBM_L_1P5GAMMA: return 1.5 * g;
+        case LBM_L_2GAMMA: return 2.0 * g;
+        case LBM_L_GAMMA2: return g * g;
+        case LBM_L_GAMMA2_PLUS_GAMMA: return g * g + g;
+        case LBM_L_ZERO: return 0.0;
+        default: return 2.0 * g - 1.0 > 0.0 ? 2.0 * g - 1.0 : 0.0;
+    }
+}
+double dl_of(int rule, double g) {
+    switch (rule) {
+        case LBM_L_GAMMA: return 1.0;
+        case LBM_L_1P5GAMMA: return 1.5;
+        case LBM_L_2GAMMA: return 2.0;
+        case LBM_L_GAMMA2: return 2.0 * g;
+        case LBM_L_GAMMA2_PLUS_GAMMA: return 2.0 * g + 1.0;
+        case LBM_L_ZERO: return 0.0;
+        default: return 2.0 * g - 1.0 > 0.0 ? 2.0 : 0.0;
+    }
+}
+
+template <class T>
+void free_dev(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void free_snap(Snapshot& s) {
+    if (s.f) (void)hipFree(s.f);
+    if (s.wa) (void)hipFree(s.wa);
+    s.f = s.wa = nullptr;
+}
+
+size_t f_bytes(const Engine& e) { return (size_t)e.Q * (size_t)e.N * e.elem; }
+size_t wa_bytes(const Engine& e) {
+    return (size_t)std::max<int64_t>(e.n_links, 1) * e.elem;
+}
+
+int alloc_snap(lbm_t* h, Snapshot& s) {
+    Engine& e = h->e;
+    if (hipMalloc(&s.f, f_bytes(e)) != hipSuccess) {
+        s.f = nullptr;
+        return fail(h, LBM_ENOMEM, "device allocation of a distribution array failed");
+    }
+    if (hipMalloc(&s.wa, wa_bytes(e)) != hipSuccess) {
+        (void)hipFree(s.f);
+        s.f = nullptr;
+        s.wa = nullptr;
+        return fail(h, LBM_ENOMEM, "device allocation of link slots failed");
+    }
+    return LBM_OK;
+}
+
+int copy_snap(lbm_t* h, const Snapshot& dst, const Snapshot& src) {
+    Engine& e = h->e;
+    HIPCHK(h, hipMemcpyAsync(dst.f, src.f, f_bytes(e), hipMemcpyDeviceToDevice, e.stream));
+    HIPCHK(h, hipMemcpyAsync(dst.wa, src.wa, wa_bytes(e), hipMemcpyDeviceToDevice, e.stream));
+    return LBM_OK;
+}
+
+int ensure_scratch(lbm_t* h, int64_t n_doubles) {
+    Engine& e = h->e;
+    if (e.scratch_len >= n_doubles) return LBM_OK;
+    free_dev(e.d_scratch);
+    if (hipMalloc((void**)&e.d_scratch, (size_t)n_doubles * sizeof(double)) != hipSuccess) {
+        e.d_scratch = nullptr;
+        e.scratch_len = 0;
+        return fail(h, LBM_ENOMEM, "device scratch allocation failed");
+    }
+    e.scratch_len = n_doubles;
+    return LBM_OK;
+}
+
+template <class T>
+int upload(lbm_t* h, T*& dst, const T* src, size_t n) {
+    free_dev(dst);
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (hipMalloc((void**)&dst, bytes) != hipSuccess) {
+        dst = nullptr;
+        return fail(h, LBM_ENOMEM, "device allocation failed");
+    }
+    if (n) HIPCHK(h, hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, h->e.stream));
+    return LBM_OK;
+}
+
+int sync(lbm_t* h) {
+    HIPCHK(h, hipStreamSynchronize(h->e.stream));
+    return LBM_OK;
+}
+
+// pull source of direction i at node (x, y, z), or -1 when it lies outside
+int64_t pull_source(const Engine& e, int64_t x, int64_t y, int64_t z, int i) {
+    int64_t sx = x - lat_e(e.lattice, i, 0);
+    const int64_t sy = ((y - lat_e(e.lattice, i, 1)) % e.ny + e.ny) % e.ny;
+    const int64_t dz = e.D == 3 ? lat_e(e.lattice, i, 2) : 0;
+    const int64_t sz = ((z - dz) % e.nz + e.nz) % e.nz;
+    if (e.xbc == LBM_X_OUTFLOW) {
+        if (sx >= e.nx) sx = e.nx - 1;
+        if (sx < 0) sx = 0;
+    } else {
+        sx = (sx % e.nx + e.nx) % e.nx;
+    }
+    return sx + e.nx * (sy + e.ny * sz);
+}
+
+// Coefficients of Eq. (213) for every (sorted) link, and their gamma
+// derivatives along l = l(gamma).
+int compute_coefficients(lbm_t* h, std::vector<lbe::LinkCoef>& coef,
+                         std::vector<lbe::LinkDeriv>& der, std::vector<double>& c4v) {
+    Engine& e = h->e;
+    const int64_t L = e.n_links;
+    coef.resize(L);
+    der.resize(L);
+    c4v.resize(L);
+    const double b = e.b;
+    for (int64_t k = 0; k < L; ++k) {
+        const double g = e.q_h[k];
+        const int i = e.lk_dir_h[k];
+        const double l = l_of(e.l_rule, g);
+        const double lp = dl_of(e.l_rule, g);
+        const double lo = std::max(0.0, 2.0 * g - 1.0);
+        if (!(l >= lo - 1e-12 && l <= 2.0 * g + 1e-12))
+            return fail(h, LBM_EINVAL,
+                        "l(gamma) outside the convex band max(0,2g-1) <= l <= 2g at link " +
+                            std::to_string(e.perm[k]) + " (gamma = " + std::to_string(g) + ")");
+        const double den = 1.0 + l;
+        const double c1 = b * (1.0 + l - 2.0 * g) / den;
+        const double c2 = b * l / den;
+        const double c3 = b * (2.0 * g - l) / den;
+        const double c4 = b * 2.0 / den;
+        double ephi = 0.0;
+        for (int a = 0; a < e.D; ++a) ephi += lat_e(e.lattice, i, a) * e.wall_u_h[k * e.D + a];
+        const double unit = 3.0 * lat_w(e.lattice, i) * e.rho0 * ephi;
+        coef[k] = {c1, c2, c3, c4 * unit};
+        const double den2 = den * den;
+        const double d1 = b * ((lp - 2.0) * den - (1.0 + l - 2.0 * g) * lp) / den2;
+        const double d2 = b * lp / den2;
+        const double d3 = b * ((2.0 - lp) * den - (2.0 * g - l) * lp) / den2;
+        const double d4 = -2.0 * b * lp / den2;
+        der[k] = {d1, d2, d3, d4 * unit};
+        c4v[k] = c4;
+    }
+    return LBM_OK;
+}
+
+int upload_coefficients(lbm_t* h) {
+    Engine& e = h->e;
+    std::vector<lbe::LinkCoef> coef;
+    std::vector<lbe::LinkDeriv> der;
+    std::vector<double> c4v;
+    int rc = compute_coefficients(h, coef, der, c4v);
+    if (rc) return rc;
+    if ((rc = upload(h, e.d_lkcoef, coef.data(), coef.size()))) return rc;
+    if ((rc = upload(h, e.d_lkderiv, der.data(), der.size()))) return rc;
+    if ((rc = upload(h, e.d_lkc4, c4v.data(), c4v.size()))) return rc;
+    return sync(h);
+}
+
+void free_run(Engine& e) {
+    for (auto& s : e.ckpt) free_snap(s);
+    for (auto& s : e.pool) free_snap(s);
+    e.ckpt.clear();
+    e.pool.clear();
+    for (auto& l : e.lam) {
+        if (l) (void)hipFree(l);
+        l = nullptr;
+    }
+    e.run_t0 = -1;
+    e.run_n = 0;
+    e.run_every = 0;
+}
+
+int zero(lbm_t* h, void* p, size_t bytes) {
+    HIPCHK(h, hipMemsetAsync(p, 0, bytes, h->e.stream));
+    return LBM_OK;
+}
+
+// one forward step from buf[cur] into buf[cur^1] (or between given
+// snapshots), with the objective accumulated when `accumulate`
+int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumulate) {
+    Engine& e = h->e;
+    lbe::StepObjective so;
+    const bool in_window = accumulate && e.obj_kind != LBM_OBJ_NONE &&
+                           e.t >= e.obj_t0 && e.t < e.obj_t1;
+    if (in_window && e.obj_kind == LBM_OBJ_MEAN_UX) {
+        so.acc_ux = e.d_obj_acc;
+        so.w_ux = 1.0 / ((double)(e.obj_t1 - e.obj_t0) * (double)e.n_fluid);
+    }
+    HIPCHK(h, lbe::launch_step(e, in, out, so));
+    if (in_window && e.obj_kind == LBM_OBJ_FORCE_X)
+        HIPCHK(h, lbe::launch_force_objective(e, out, e.d_obj_acc, e.obj_tag,
+                                              1.0 / (double)(e.obj_t1 - e.obj_t0)));
+    return LBM_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
+               int64_t nz, const double* s, double rho0, const double* g) {
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return LBM_EINVAL;
+    if (precision != LBM_FP64 && precision != LBM_FP32) return LBM_EINVAL;
+    if (nx < 1 || ny < 1 || nz < 1) return LBM_EINVAL;
+    if (lattice == LBM_D2Q9 && nz != 1) return LBM_EINVAL;
+    if (nx > 65535 * 256LL || ny > (1LL << 31) || nz > (1LL << 31)) return LBM_EINVAL;
+    const int64_t N = nx * ny * nz;
+    if (N >= (1LL << 31)) return LBM_EINVAL;
+    if (!s || !(rho0 > 0.0) || !std::isfinite(rho0)) return LBM_EINVAL;
+    const int Q = lat_Q(lattice), D = lat_D(lattice);
+    for (int k = 0; k < Q; ++k) {
+        if (!std::isfinite(s[k])) return LBM_EINVAL;
+        if (!lat_conserved(lattice, k) && !(s[k] >= 0.0 && s[k] < 2.0)) return LBM_EINVAL;
+    }
+    if (g)
+        for (int a = 0; a < D; ++a)
+            if (!std::isfinite(g[a])) return LBM_EINVAL;
+
+    lbm_t* h = new (std::nothrow) lbm_t;
+    if (!h) return LBM_ENOMEM;
+    Engine& e = h->e;
+    e.lattice = lattice;
+    e.precision = precision;
+    e.Q = Q;
+    e.D = D;
+    e.nx = nx;
+    e.ny = ny;
+    e.nz = nz;
+    e.N = N;
+    e.elem = precision == LBM_FP64 ? 8 : 4;
+    for (int k = 0; k < Q; ++k) e.s[k] = s[k];
+    e.rho0 = rho0;
+    for (int a = 0; a < 3; ++a) e.g[a] = (g && a < D) ? g[a] : 0.0;
+    if (hipStreamCreate(&e.own_stream) != hipSuccess) {
+        delete h;
+        return LBM_EDEVICE;
+    }
+    e.stream = e.own_stream;
+    for (auto& b : e.buf) {
+        if (hipMalloc(&b.f, f_bytes(e)) != hipSuccess) {
+            b.f = nullptr;
+            lbm_destroy(h);
+            return LBM_ENOMEM;
+        }
+        if (hipMemsetAsync(b.f, 0, f_bytes(e), e.stream) != hipSuccess) {
+            lbm_destroy(h);
+            return LBM_EDEVICE;
+        }
+    }
+    if (hipEventCreate(&e.ev0) != hipSuccess || hipEventCreate(&e.ev1) != hipSuccess) {
+        lbm_destroy(h);
+        return LBM_EDEVICE;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_set_scheme(lbm_t* h, int l_rule, double b) {
+    if (!h) return LBM_EINVAL;
+    if (l_rule < LBM_L_GAMMA || l_rule > LBM_L_MIN)
+        return fail(h, LBM_EINVAL, "unknown l rule");
+    if (!(b > 0.0 && b <= 1.0)) return fail(h, LBM_EINVAL, "b must lie in (0, 1]");
+    if (h->e.has_geometry) return fail(h, LBM_ESTATE, "set the scheme before the geometry");
+    h->e.l_rule = l_rule;
+    h->e.b = b;
+    return LBM_OK;
+}
+
+int lbm_set_x_boundary(lbm_t* h, int kind, double drho) {
+    if (!h) return LBM_EINVAL;
+    if (kind < LBM_X_PERIODIC || kind > LBM_X_OUTFLOW)
+        return fail(h, LBM_EINVAL, "unknown x boundary kind");
+    if (!std::isfinite(drho)) return fail(h, LBM_EINVAL, "drho must be finite");
+    if (h->e.has_geometry)
+        return fail(h, LBM_ESTATE, "set the x boundary before the geometry");
+    h->e.xbc = kind;
+    h->e.drho = drho;
+    return LBM_OK;
+}
+
+int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
+                     const int64_t* node, const int8_t* dir, const double* q,
+                     const double* wall_u, const int32_t* tag) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!solid) return fail(h, LBM_EINVAL, "solid mask is NULL");
+    if (n_links < 0 || n_links >= (1LL << 26))
+        return fail(h, LBM_EINVAL, "number of links out of range [0, 2^26)");
+    if (n_links > 0 && (!node || !dir || !q))
+        return fail(h, LBM_EINVAL, "link arrays are NULL");
+    const int64_t N = e.N;
+    const int Q = e.Q, D = e.D;
+    for (int64_t n = 0; n < N; ++n)
+        if (solid[n] > 1) return fail(h, LBM_EINVAL, "solid mask values must be 0 or 1");
+    for (int64_t k = 0; k < n_links; ++k) {
+        if (node[k] < 0 || node[k] >= N) return fail(h, LBM_EINVAL, "link node out of range");
+        if (dir[k] < 1 || dir[k] >= Q) return fail(h, LBM_EINVAL, "link direction out of range");
+        if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(h, LBM_EINVAL, "q must lie in (0, 1]");
+        if (solid[node[k]]) return fail(h, LBM_EGEOM, "link at a solid node");
+        if (tag && tag[k] < 0) return fail(h, LBM_EINVAL, "negative tag");
+        if (wall_u)
+            for (int a = 0; a < D; ++a)
+                if (!std::isfinite(wall_u[k * D + a]))
+                    return fail(h, LBM_EINVAL, "wall velocity not finite");
+    }
+    // sort by (node, dir)
+    std::vector<int64_t> perm(n_links);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
+        return node[a] != node[b] ? node[a] < node[b] : dir[a] < dir[b];
+    });
+    // per-node link mask, duplicates, consistency with the mask
+    std::vector<uint32_t> mask(N, 0u);
+    for (int64_t k = 0; k < n_links; ++k) {
+        const uint32_t bit = 1u << dir[k];
+        if (mask[node[k]] & bit) return fail(h, LBM_EGEOM, "duplicate cut link");
+        mask[node[k]] |= bit;
+    }
+    int64_t n_fluid = 0;
+    for (int64_t z = 0; z < e.nz; ++z)
+        for (int64_t y = 0; y < e.ny; ++y)
+            for (int64_t x = 0; x < e.nx; ++x) {
+                const int64_t n = x + e.nx * (y + e.ny * z);
+                if (solid[n]) continue;
+                ++n_fluid;
+                if (e.xbc == LBM_X_OUTFLOW && x == 0)
+                    return fail(h, LBM_EGEOM, "outflow x boundary needs a solid column x = 0");
+                for (int i = 1; i < Q; ++i) {
+                    const bool need = solid[pull_source(e, x, y, z, i)] != 0;
+                    const bool have = (mask[n] >> i) & 1u;
+                    if (need != have)
+                        return fail(h, LBM_EGEOM,
+                                    need ? "fluid node pulls from a solid node without a cut link"
+                                         : "cut link whose pull source is fluid");
+                }
+            }
+    // host copies in sorted order
+    e.perm = perm;
+    e.n_links = n_links;
+    e.n_fluid = n_fluid;
+    e.lk_node_h.resize(n_links);
+    e.lk_dir_h.resize(n_links);
+    e.q_h.resize(n_links);
+    e.wall_u_h.assign((size_t)n_links * D, 0.0);
+    e.tag_h.resize(n_links);
+    int max_tag = -1;
+    for (int64_t k = 0; k < n_links; ++k) {
+        const int64_t p = perm[k];
+        e.lk_node_h[k] = node[p];
+        e.lk_dir_h[k] = dir[p];
+        e.q_h[k] = q[p];
+        if (wall_u)
+            for (int a = 0; a < D; ++a) e.wall_u_h[k * D + a] = wall_u[p * D + a];
+        e.tag_h[k] = tag ? tag[p] : 0;
+        max_tag = std::max(max_tag, e.tag_h[k]);
+    }
+    e.n_tags = max_tag + 1;
+    // node words: -1 solid, else (link count << 26) | first link
+    std::vector<int32_t> nw(N);
+    {
+        int64_t k = 0;
+        for (int64_t n = 0; n < N; ++n) {
+            if (solid[n]) {
+                nw[n] = -1;
+                continue;
+            }
+            const int cnt = __builtin_popcount(mask[n]);
+            nw[n] = cnt ? (int32_t)(((uint32_t)cnt << 26) | (uint32_t)k) : 0;
+            k += cnt;
+        }
+    }
+    std::vector<uint8_t> d8(n_links);
+    std::vector<int32_t> n32(n_links);
+    for (int64_t k = 0; k < n_links; ++k) {
+        d8[k] = (uint8_t)e.lk_dir_h[k];
+        n32[k] = (int32_t)e.lk_node_h[k];
+    }
+    e.has_geometry = false;
+    free_run(e);
+    int rc;
+    if ((rc = upload(h, e.d_nodeword, nw.data(), nw.size()))) return rc;
+    if ((rc = upload(h, e.d_lkdir, d8.data(), d8.size()))) return rc;
+    if ((rc = upload(h, e.d_lknode, n32.data(), n32.size()))) return rc;
+    if ((rc = upload(h, e.d_lktag, e.tag_h.data(), e.tag_h.size()))) return rc;
+    if ((rc = upload_coefficients(h))) return rc;
+    for (auto& b : e.buf) {
+        if (b.wa) (void)hipFree(b.wa);
+        if (hipMalloc(&b.wa, wa_bytes(e)) != hipSuccess) {
+            b.wa = nullptr;
+            return fail(h, LBM_ENOMEM, "device allocation of link slots failed");
+        }
+        if ((rc = zero(h, b.wa, wa_bytes(e)))) return rc;
+    }
+    e.has_geometry = true;
+    e.initialized = false;
+    e.have_grad = false;
+    return sync(h);
+}
+
+int lbm_update_links(lbm_t* h, const double* q, const double* wall_u) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.has_geometry) return fail(h, LBM_ESTATE, "no geometry");
+    std::vector<double> q_old = e.q_h, u_old = e.wall_u_h;
+    for (int64_t k = 0; k < e.n_links; ++k) {
+        const int64_t p = e.perm[k];
+        if (q) {
+            if (!(q[p] > 0.0 && q[p] <= 1.0)) {
+                e.q_h = q_old;
+                return fail(h, LBM_EINVAL, "q must lie in (0, 1]");
+            }
+            e.q_h[k] = q[p];
+        }
+        if (wall_u)
+            for (int a = 0; a < e.D; ++a) e.wall_u_h[k * e.D + a] = wall_u[p * e.D + a];
+    }
+    const int rc = upload_coefficients(h);
+    if (rc) {
+        e.q_h = q_old;
+        e.wall_u_h = u_old;
+    }
+    return rc;
+}
+
+static int init_common(lbm_t* h, const double* df, const double* rho, const double* u) {
+    Engine& e = h->e;
+    if (!e.has_geometry) return fail(h, LBM_ESTATE, "set the geometry before init");
+    int64_t need = 0;
+    if (df) need = (int64_t)e.Q * e.N;
+    else need = (rho ? e.N : 0) + (u ? e.N * e.D : 0);
+    int rc = ensure_scratch(h, std::max<int64_t>(need, 1));
+    if (rc) return rc;
+    double* d_df = nullptr;
+    double* d_rho = nullptr;
+    double* d_u = nullptr;
+    if (df) {
+        d_df = e.d_scratch;
+        HIPCHK(h, hipMemcpyAsync(d_df, df, (size_t)need * 8, hipMemcpyHostToDevice, e.stream));
+    } else {
+        double* p = e.d_scratch;
+        if (rho) {
+            d_rho = p;
+            HIPCHK(h, hipMemcpyAsync(d_rho, rho, (size_t)e.N * 8, hipMemcpyHostToDevice, e.stream));
+            p += e.N;
+        }
+        if (u) {
+            d_u = p;
+            HIPCHK(h, hipMemcpyAsync(d_u, u, (size_t)e.N * e.D * 8, hipMemcpyHostToDevice, e.stream));
+        }
+    }
+    Snapshot& s = e.buf[e.cur];
+    if ((rc = zero(h, s.f, f_bytes(e)))) return rc;
+    if ((rc = zero(h, s.wa, wa_bytes(e)))) return rc;
+    HIPCHK(h, lbe::launch_init(e, d_df, d_rho, d_u, s));
+    e.t = 0;
+    e.initialized = true;
+    e.stepped = false;
+    return sync(h);
+}
+
+int lbm_init(lbm_t* h, const double* rho, const double* u) {
+    if (!h) return LBM_EINVAL;
+    return init_common(h, nullptr, rho, u);
+}
+
+int lbm_init_deviation(lbm_t* h, const double* df) {
+    if (!h || !df) return LBM_EINVAL;
+    return init_common(h, df, nullptr, nullptr);
+}
+
+int lbm_step(lbm_t* h, int64_t n) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (n < 0) return fail(h, LBM_EINVAL, "negative step count");
+    if (!e.initialized) return fail(h, LBM_ESTATE, "initialise before stepping");
+    if (e.timing && n > 0) HIPCHK(h, hipEventRecord(e.ev0, e.stream));
+    for (int64_t s = 0; s < n; ++s) {
+        const int rc = forward_step(h, e.buf[e.cur], e.buf[e.cur ^ 1], true);
+        if (rc) return rc;
+        e.cur ^= 1;
+        ++e.t;
+        e.stepped = true;
+    }
+    if (e.timing && n > 0) {
+        HIPCHK(h, hipEventRecord(e.ev1, e.stream));
+        e.timed_steps = n;        // resolved in lbm_last_step_ms
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_t* h) { return h ? h->e.t : -1; }
+
+int lbm_moments(lbm_t* h, double* rho, double* u) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.initialized) return fail(h, LBM_ESTATE, "not initialised");
+    const int64_t need = e.N * (1 + e.D);
+    int rc = ensure_scratch(h, need);
+    if (rc) return rc;
+    double* d_rho = e.d_scratch;
+    double* d_u = e.d_scratch + e.N;
+    HIPCHK(h, lbe::launch_observe(e, e.buf[e.cur], d_rho, d_u, nullptr));
+    if (rho) HIPCHK(h, hipMemcpyAsync(rho, d_rho, (size_t)e.N * 8, hipMemcpyDeviceToHost, e.stream));
+    if (u) HIPCHK(h, hipMemcpyAsync(u, d_u, (size_t)e.N * e.D * 8, hipMemcpyDeviceToHost, e.stream));
+    return sync(h);
+}
+
+int lbm_get_distribution(lbm_t* h, double* df) {
+    if (!h || !df) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.initialized) return fail(h, LBM_ESTATE, "not initialised");
+    const int64_t need = (int64_t)e.Q * e.N;
+    int rc = ensure_scratch(h, need);
+    if (rc) return rc;
+    HIPCHK(h, lbe::launch_observe(e, e.buf[e.cur], nullptr, nullptr, e.d_scratch));
+    HIPCHK(h, hipMemcpyAsync(df, e.d_scratch, (size_t)need * 8, hipMemcpyDeviceToHost, e.stream));
+    return sync(h);
+}
+
+int lbm_reduce(lbm_t* h, double* mass, double* mom) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.initialized) return fail(h, LBM_ESTATE, "not initialised");
+    const int64_t nb = lbe::step_blocks(e);
+    const int cols = 1 + e.D;
+    int rc = ensure_scratch(h, nb * cols + cols);
+    if (rc) return rc;
+    int64_t rows = 0;
+    HIPCHK(h, lbe::launch_mass(e, e.buf[e.cur], e.d_scratch, &rows));
+    double* d_out = e.d_scratch + nb * cols;
+    HIPCHK(h, lbe::launch_sum_blocks(e, e.d_scratch, rows, cols, d_out));
+    double out[4] = {0, 0, 0, 0};
+    HIPCHK(h, hipMemcpyAsync(out, d_out, cols * 8, hipMemcpyDeviceToHost, e.stream));
+    if ((rc = sync(h))) return rc;
+    const double m = (double)e.n_fluid * e.rho0 + out[0];
+    if (mass) *mass = m;
+    if (mom)
+        for (int a = 0; a < e.D; ++a) mom[a] = out[1 + a];
+    bool finite = std::isfinite(m);
+    for (int a = 0; a < e.D; ++a) finite = finite && std::isfinite(out[1 + a]);
+    if (!finite) return fail(h, LBM_ENONFINITE, "mass or momentum is not finite");
+    return LBM_OK;
+}
+
+int lbm_force(lbm_t* h, int32_t n_tags, double* force) {
+    if (!h || !force || n_tags < 0) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.stepped) return fail(h, LBM_ESTATE, "no step taken yet");
+    const int D = e.D;
+    for (int64_t c = 0; c < (int64_t)n_tags * D; ++c) force[c] = 0.0;
+    if (e.n_links == 0 || e.n_tags == 0) return LBM_OK;
+    const int64_t nb = lbe::link_blocks(e);
+    const int64_t cols = (int64_t)e.n_tags * D;
+    int rc = ensure_scratch(h, nb * cols + cols);
+    if (rc) return rc;
+    int64_t rows = 0;
+    HIPCHK(h, lbe::launch_force(e, e.buf[e.cur], e.d_scratch, &rows));
+    double* d_out = e.d_scratch + nb * cols;
+    HIPCHK(h, lbe::launch_sum_blocks(e, e.d_scratch, rows, cols, d_out));
+    std::vector<double> out(cols);
+    HIPCHK(h, hipMemcpyAsync(out.data(), d_out, cols * 8, hipMemcpyDeviceToHost, e.stream));
+    if ((rc = sync(h))) return rc;
+    for (int t = 0; t < std::min<int>(n_tags, e.n_tags); ++t)
+        for (int a = 0; a < D; ++a) force[t * D + a] = out[t * D + a];
+    return LBM_OK;
+}
+
+int64_t lbm_state_bytes(const lbm_t* h) {
+    if (!h || !h->e.has_geometry) return -1;
+    return (int64_t)(f_bytes(h->e) + wa_bytes(h->e));
+}
+
+int lbm_get_state(lbm_t* h, void* dst) {
+    if (!h || !dst) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.initialized) return fail(h, LBM_ESTATE, "not initialised");
+    Snapshot d{dst, (char*)dst + f_bytes(e)};
+    int rc = copy_snap(h, d, e.buf[e.cur]);
+    if (rc) return rc;
+    return sync(h);
+}
+
+int lbm_set_state(lbm_t* h, const void* src, int64_t time) {
+    if (!h || !src || time < 0) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.has_geometry) return fail(h, LBM_ESTATE, "set the geometry first");
+    Snapshot s{(void*)src, (char*)src + f_bytes(e)};
+    int rc = copy_snap(h, e.buf[e.cur], s);
+    if (rc) return rc;
+    e.t = time;
+    e.initialized = true;
+    e.stepped = time > 0;
+    return sync(h);
+}
+
+int lbm_set_objective(lbm_t* h, int kind, int32_t tag, int64_t t_begin, int64_t t_end) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (kind < LBM_OBJ_NONE || kind > LBM_OBJ_MEAN_UX)
+        return fail(h, LBM_EINVAL, "unknown objective");
+    if (kind != LBM_OBJ_NONE && !(t_end > t_begin && t_begin >= 0))
+        return fail(h, LBM_EINVAL, "objective window must satisfy 0 <= t_begin < t_end");
+    if (!e.has_geometry) return fail(h, LBM_ESTATE, "set the geometry first");
+    if (kind == LBM_OBJ_FORCE_X && (tag < 0 || tag >= e.n_tags))
+        return fail(h, LBM_EINVAL, "objective tag has no links");
+    e.obj_kind = kind;
+    e.obj_tag = tag;
+    e.obj_t0 = t_begin;
+    e.obj_t1 = t_end;
+    const int64_t len = kind == LBM_OBJ_FORCE_X ? lbe::link_blocks(e) : lbe::step_blocks(e);
+    free_dev(e.d_obj_acc);
+    e.obj_acc_len = 0;
+    if (kind != LBM_OBJ_NONE) {
+        if (hipMalloc((void**)&e.d_obj_acc, (size_t)std::max<int64_t>(len, 1) * 8) != hipSuccess) {
+            e.d_obj_acc = nullptr;
+            return fail(h, LBM_ENOMEM, "objective accumulator allocation failed");
+        }
+        e.obj_acc_len = len;
+        int rc = zero(h, e.d_obj_acc, (size_t)std::max<int64_t>(len, 1) * 8);
+        if (rc) return rc;
+    }
+    return sync(h);
+}
+
+int lbm_objective(lbm_t* h, double* J) {
+    if (!h || !J) return LBM_EINVAL;
+    Engine& e = h->e;
+    *J = 0.0;
+    if (e.obj_kind == LBM_OBJ_NONE || e.obj_acc_len == 0) return LBM_OK;
+    int rc = ensure_scratch(h, 1);
+    if (rc) return rc;
+    HIPCHK(h, lbe::launch_sum_blocks(e, e.d_obj_acc, e.obj_acc_len, 1, e.d_scratch));
+    HIPCHK(h, hipMemcpyAsync(J, e.d_scratch, 8, hipMemcpyDeviceToHost, e.stream));
+    if ((rc = sync(h))) return rc;
+    if (!std::isfinite(*J)) return fail(h, LBM_ENONFINITE, "objective is not finite");
+    return LBM_OK;
+}
+
+int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.initialized) return fail(h, LBM_ESTATE, "initialise before running");
+    if (n < 1 || every < 1) return fail(h, LBM_EINVAL, "n and every must be >= 1");
+    free_run(e);
+    const int64_t nck = (n + every - 1) / every;
+    e.ckpt.resize(nck);
+    for (auto& s : e.ckpt) {
+        int rc = alloc_snap(h, s);
+        if (rc) {
+            free_run(e);
+            return rc;
+        }
+    }
+    e.run_t0 = e.t;
+    e.run_n = n;
+    e.run_every = every;
+    for (int64_t s = 0; s < n; ++s) {
+        int rc;
+        if (s % every == 0 && (rc = copy_snap(h, e.ckpt[s / every], e.buf[e.cur]))) return rc;
+        if ((rc = forward_step(h, e.buf[e.cur], e.buf[e.cur ^ 1], true))) return rc;
+        e.cur ^= 1;
+        ++e.t;
+        e.stepped = true;
+    }
+    e.have_grad = false;
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_t* h) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (e.run_t0 < 0 || e.ckpt.empty())
+        return fail(h, LBM_ESTATE, "no checkpointed run to reverse");
+    int rc;
+    const size_t lam_bytes = f_bytes(e);
+    for (auto& l : e.lam) {
+        if (!l && hipMalloc(&l, lam_bytes) != hipSuccess) {
+            l = nullptr;
+            return fail(h, LBM_ENOMEM, "adjoint array allocation failed");
+        }
+    }
+    if ((int64_t)e.pool.size() != e.run_every + 1) {
+        for (auto& s : e.pool) free_snap(s);
+        e.pool.assign(e.run_every + 1, Snapshot{});
+        for (auto& s : e.pool)
+            if ((rc = alloc_snap(h, s))) return rc;
+    }
+    const int NC = e.D + e.Q;
+    const int64_t nb = lbe::step_blocks(e);
+    free_dev(e.d_gq);
+    free_dev(e.d_gphi);
+    free_dev(e.d_gglob);
+    const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
+    if (hipMalloc((void**)&e.d_gq, L1 * 8) != hipSuccess ||
+        hipMalloc((void**)&e.d_gphi, L1 * e.D * 8) != hipSuccess ||
+        hipMalloc((void**)&e.d_gglob, (size_t)nb * NC * 8) != hipSuccess)
+        return fail(h, LBM_ENOMEM, "gradient accumulator allocation failed");
+    e.gglob_len = nb;
+    if ((rc = zero(h, e.d_gq, L1 * 8))) return rc;
+    if ((rc = zero(h, e.d_gphi, L1 * e.D * 8))) return rc;
+    if ((rc = zero(h, e.d_gglob, (size_t)nb * NC * 8))) return rc;
+    if ((rc = zero(h, e.lam[0], lam_bytes))) return rc;
+    if ((rc = zero(h, e.lam[1], lam_bytes))) return rc;
+
+    int lc = 0;   // lam[lc] holds lambda(t+1)
+    const int64_t nseg = (int64_t)e.ckpt.size();
+    const int64_t t_saved = e.t;
+    for (int64_t j = nseg - 1; j >= 0; --j) {
+        const int64_t t_seg = e.run_t0 + j * e.run_every;
+        const int64_t len = std::min(e.run_every, e.run_n - j * e.run_every);
+        if ((rc = copy_snap(h, e.pool[0], e.ckpt[j]))) return rc;
+        for (int64_t r = 0; r < len; ++r) {
+            e.t = t_seg + r;   // forward_step reads e.t only for the objective window
+            if ((rc = forward_step(h, e.pool[r], e.pool[r + 1], false))) {
+                e.t = t_saved;
+                return rc;
+            }
+        }
+        for (int64_t r = len - 1; r >= 0; --r) {
+            const int64_t t = t_seg + r;
+            lbe::AdjointObjective ao;
+            ao.kind = e.obj_kind;
+            ao.tag = e.obj_tag;
+            const bool in_w = e.obj_kind != LBM_OBJ_NONE && t >= e.obj_t0 && t < e.obj_t1;
+            ao.weight = in_w ? 1.0 / (double)(e.obj_t1 - e.obj_t0) : 0.0;
+            ao.inv_nfluid = e.n_fluid ? 1.0 / (double)e.n_fluid : 0.0;
+            if (!in_w) ao.kind = LBM_OBJ_NONE;
+            hipError_t st = lbe::launch_adjoint_step(e, e.pool[r], e.lam[lc], e.lam[lc ^ 1], ao);
+            if (st != hipSuccess) {
+                e.t = t_saved;
+                return fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));
+            }
+            lc ^= 1;
+        }
+    }
+    e.t = t_saved;
+    // lambda(run_t0) now in lam[lc]; keep it in lam[0]
+    if (lc != 0) std::swap(e.lam[0], e.lam[1]);
+    e.have_grad = true;
+    return LBM_OK;
+}
+
+int lbm_grad(lbm_t* h, double* dq, double* dwall_u, double* dg, double* ds) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.have_grad) return fail(h, LBM_ESTATE, "run lbm_adjoint first");
+    const int D = e.D, Q = e.Q, NC = D + Q;
+    int rc;
+    std::vector<double> gq(e.n_links), gphi((size_t)e.n_links * D);
+    if (e.n_links) {
+        HIPCHK(h, hipMemcpyAsync(gq.data(), e.d_gq, e.n_links * 8, hipMemcpyDeviceToHost, e.stream));
+        HIPCHK(h, hipMemcpyAsync(gphi.data(), e.d_gphi, e.n_links * D * 8,
+                                 hipMemcpyDeviceToHost, e.stream));
+    }
+    if ((rc = ensure_scratch(h, NC))) return rc;
+    HIPCHK(h, lbe::launch_sum_blocks(e, e.d_gglob, e.gglob_len, NC, e.d_scratch));
+    std::vector<double> glob(NC);
+    HIPCHK(h, hipMemcpyAsync(glob.data(), e.d_scratch, NC * 8, hipMemcpyDeviceToHost, e.stream));
+    if ((rc = sync(h))) return rc;
+    for (int64_t k = 0; k < e.n_links; ++k) {
+        const int64_t p = e.perm[k];
+        if (dq) dq[p] = gq[k];
+        if (dwall_u)
+            for (int a = 0; a < D; ++a) dwall_u[p * D + a] = gphi[k * D + a];
+    }
+    if (dg)
+        for (int a = 0; a < D; ++a) dg[a] = glob[a];
+    if (ds)
+        for (int k = 0; k < Q; ++k) ds[k] = glob[D + k];
+    return LBM_OK;
+}
+
+int lbm_get_adjoint(lbm_t* h, double* lam) {
+    if (!h || !lam) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.have_grad) return fail(h, LBM_ESTATE, "run lbm_adjoint first");
+    const int64_t need = (int64_t)e.Q * e.N;
+    int rc = ensure_scratch(h, need);
+    if (rc) return rc;
+    HIPCHK(h, lbe::launch_adjoint_out(e, e.lam[0], e.d_scratch));
+    HIPCHK(h, hipMemcpyAsync(lam, e.d_scratch, (size_t)need * 8, hipMemcpyDeviceToHost, e.stream));
+    return sync(h);
+}
+
+int lbm_set_stream(lbm_t* h, void* stream) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    HIPCHK(h, hipStreamSynchronize(e.stream));
+    e.stream = stream ? (hipStream_t)stream : e.own_stream;
+    return LBM_OK;
+}
+
+int lbm_lattice_info(int lattice, int32_t* Q, int32_t* D, int8_t* e, double* w,
+                     double* M) {
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return LBM_EINVAL;
+    const int q = lat_Q(lattice), d = lat_D(lattice);
+    if (Q) *Q = q;
+    if (D) *D = d;
+    for (int i = 0; i < q; ++i) {
+        if (e)
+            for (int a = 0; a < d; ++a) e[i * d + a] = (int8_t)lat_e(lattice, i, a);
+        if (w) w[i] = lat_w(lattice, i);
+    }
+    if (M)
+        for (int k = 0; k < q; ++k)
+            for (int i = 0; i < q; ++i) M[k * q + i] = lat_M(lattice, k, i);
+    return LBM_OK;
+}
+
+int lbm_counts(const lbm_t* h, int64_t* n_fluid, int64_t* n_links) {
+    if (!h) return LBM_EINVAL;
+    if (n_fluid) *n_fluid = h->e.n_fluid;
+    if (n_links) *n_links = h->e.n_links;
+    return LBM_OK;
+}
+
+int lbm_set_timing(lbm_t* h, int on) {
+    if (!h) return LBM_EINVAL;
+    h->e.timing = on != 0;
+    return LBM_OK;
+}
+
+int lbm_last_step_ms(lbm_t* h, double* ms) {
+    if (!h || !ms) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (e.timed_steps > 0) {
+        HIPCHK(h, hipEventSynchronize(e.ev1));
+        float el = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&el, e.ev0, e.ev1));
+        e.last_ms = (double)el / (double)e.timed_steps;
+        e.timed_steps = 0;
+    }
+    if (e.last_ms < 0) return fail(h, LBM_ESTATE, "no timed lbm_step call");
+    *ms = e.last_ms;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_t* h) { return h ? h->e.err.c_str() : "null handle"; }
+
+int lbm_destroy(lbm_t* h) {
+    if (!h) return LBM_OK;
+    Engine& e = h->e;
+    if (e.stream) (void)hipStreamSynchronize(e.stream);
+    free_run(e);
+    for (auto& b : e.buf) free_snap(b);
+    free_dev(e.d_nodeword);
+    free_dev(e.d_lkdir);
+    free_dev(e.d_lknode);
+    free_dev(e.d_lktag);
+    free_dev(e.d_lkcoef);
+    free_dev(e.d_lkderiv);
+    free_dev(e.d_lkc4);
+    free_dev(e.d_obj_acc);
+    free_dev(e.d_gq);
+    free_dev(e.d_gphi);
+    free_dev(e.d_gglob);
+    free_dev(e.d_scratch);
+    if (e.ev0) (void)hipEventDestroy(e.ev0);
+    if (e.ev1) (void)hipEventDestroy(e.ev1);
+    if (e.own_stream) (void)hipStreamDestroy(e.own_stream);
+    delete h;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Host-side state of one solver handle and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace lbe {
+
+struct LinkCoef {        // per cut link, double: Eq. (213) coefficients
+    double c1, c2, c3;   // on f_ibar(x_f,t), f'_i(x_f,t), f'_ibar(x_f,t)
+    double wall;         // c4 * 3 w_i rho0 e_i.phi
+};
+
+struct LinkDeriv {       // d/dgamma of c1, c2, c3 and of the wall term
+    double d1, d2, d3, dwall;
+};
+
+struct Snapshot {
+    void* f = nullptr;
+    void* wa = nullptr;
+};
+
+struct Engine {
+    // configuration
+    int lattice = 0, precision = 0, Q = 0, D = 0;
+    int64_t nx = 0, ny = 0, nz = 0, N = 0;
+    double s[19] = {0};
+    double rho0 = 1.0;
+    double g[3] = {0, 0, 0};
+    int l_rule = 6;
+    double b = 1.0;
+    int xbc = 0;
+    double drho = 0.0;
+    size_t elem = 8;         // bytes per stored value
+
+    // geometry
+    bool has_geometry = false;
+    int64_t n_links = 0, n_fluid = 0;
+    int n_tags = 0;
+    std::vector<int64_t> perm;          // sorted link k -> caller index
+    std::vector<int64_t> lk_node_h;     // sorted
+    std::vector<int8_t> lk_dir_h;
+    std::vector<double> q_h, wall_u_h;  // sorted, wall_u (L, D)
+    std::vector<int32_t> tag_h;
+
+    int32_t* d_nodeword = nullptr;
+    uint8_t* d_lkdir = nullptr;
+    int32_t* d_lknode = nullptr;
+    int32_t* d_lktag = nullptr;
+    LinkCoef* d_lkcoef = nullptr;
+    LinkDeriv* d_lkderiv = nullptr;
+    double* d_lkc4 = nullptr;           // c4 per link (for dJ/dphi)
+
+    // state: post-collision array A and link slots of the current time
+    Snapshot buf[2];
+    int cur = 0;
+    bool initialized = false;
+    int64_t t = 0;
+    bool stepped = false;               // at least one step since init
+
+    // objective
+    int obj_kind = 0;
+    int obj_tag = 0;
+    int64_t obj_t0 = 0, obj_t1 = 0;
+    double* d_obj_acc = nullptr;        // per-block partial sums
+    int64_t obj_acc_len = 0;
+
+    // checkpointed run and adjoint
+    std::vector<Snapshot> ckpt;         // snapshot j holds the state at t_run0 + j*every
+    std::vector<Snapshot> pool;         // replay pool, every + 1 states
+    int64_t run_t0 = -1, run_n = 0, run_every = 0;
+    void* lam[2] = {nullptr, nullptr};  // adjoint arrays (Q*N values of T)
+    double* d_gq = nullptr;             // dJ/dgamma per link
+    double* d_gphi = nullptr;           // dJ/dphi per link (L*D)
+    double* d_gglob = nullptr;          // per-block partials of dJ/dg (D) and dJ/ds (Q)
+    int64_t gglob_len = 0;
+    bool have_grad = false;
+
+    // scratch for reductions and host transfers
+    double* d_scratch = nullptr;
+    int64_t scratch_len = 0;
+
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = -1.0;
+    int64_t timed_steps = 0;
+
+    std::string err;
+};
+
+// ---- launchers (forward.hip) -------------------------------------------------
+struct StepObjective {
+    double* acc_ux = nullptr;    // per-block accumulator for MEAN_UX, or null
+    double w_ux = 0.0;           // weight (1/(window * n_fluid))
+};
+
+hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
+                       const StepObjective& obj);
+// initial state: df (Q*N, deviation) or fields rho (N), u (N*D); device pointers
+hipError_t launch_init(Engine& e, const double* df, const double* rho,
+                       const double* u, const Snapshot& out);
+// outputs from the pulled state: rho (N) and u (N*D), or df (Q*N); device
+hipError_t launch_observe(Engine& e, const Snapshot& in, double* rho, double* u,
+                          double* df);
+// per-block partial sums of (drho, rho0 u) over fluid nodes: (nblocks, 1 + D)
+hipError_t launch_mass(Engine& e, const Snapshot& in, double* partials,
+                       int64_t* nblocks);
+// per-block partial momentum-exchange force: (nblocks, n_tags, D)
+hipError_t launch_force(Engine& e, const Snapshot& post, double* partials,
+                        int64_t* nblocks);
+// accumulate the x force on one tag into per-block accumulators
+hipError_t launch_force_objective(Engine& e, const Snapshot& post, double* acc,
+                                  int tag, double weight);
+// out[c] = sum_b partials[b*cols + c], deterministic
+hipError_t launch_sum_blocks(Engine& e, const double* partials, int64_t rows,
+                             int64_t cols, double* out);
+int64_t step_blocks(const Engine& e);       // logical blocks of a node launch
+int64_t link_blocks(const Engine& e);       // blocks of a link launch
+
+// ---- launchers (adjoint.hip) -------------------------------------------------
+// One reverse step: lam_in = lambda(t+1) -> lam_out = lambda(t), with the
+// forward state at t in `fwd`.  Accumulates per-link and global gradients.
+struct AdjointObjective {
+    int kind = 0;
+    int tag = 0;
+    double weight = 0.0;         // 0 when step t is outside the window
+    double inv_nfluid = 0.0;
+};
+hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd,
+                               const void* lam_in, void* lam_out,
+                               const AdjointObjective& obj);
+hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
+
+}  // namespace lbe

@@ -1,0 +1,439 @@
+// Forward kernels: the fused pull collide-stream step with the single-node
+// boundary scheme, initialisation, observation and reductions.
+//
+// Storage (per precision T = float or double, deviation form f - w rho0):
+//   A[i*N + n]   post-collision value f'_i(n, t-1) at every node n;
+//   wa[k]        for cut link k = (x_f, i): the value f_i(x_f, t) produced by
+//                Eq. (213) during the previous step (the "write-ahead" slot).
+// Pulling f_i(x, t) = A_i(x - e_i) (+ seam term), or wa[k] on a cut link,
+// gives the pre-collision state of Eq. (21) at time t.
+#include "engine.hpp"
+#include "kernels.hpp"
+
+namespace lbe {
+
+// ----------------------------------------------------------------------------
+// the step: pull, collide, store, and evaluate Eq. (213) for the node's links
+template <class L, class T, int XB>
+__global__ void __launch_bounds__(BX)
+k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
+       T* __restrict__ waB, const int32_t* __restrict__ nodeword,
+       const uint8_t* __restrict__ lkdir, const LinkCoef* __restrict__ lkcoef,
+       Grid g, Params<L, T> p, double* __restrict__ acc_ux, double w_ux) {
+    const NodePos pos = node_of_thread(g);
+    const int32_t nw = pos.in ? nodeword[pos.n] : -1;
+    double ux_local = 0.0;
+    if (nw >= 0) {
+        const NodeLinks nl = node_links(nw, lkdir);
+        T f[L::Q];
+        pull<L, T, XB>(A, waA, g, pos, p, nl, f);
+        T fpre_link[L::Q];
+        if (nl.mask) {
+            unroll<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                fpre_link[i] = f[i];
+            });
+        }
+        Macro<L, T> mac;
+        collide<L, T>(f, p, mac);
+        ux_local = (double)mac.u[0];
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            __builtin_nontemporal_store(f[i], &B[(size_t)i * g.N + pos.n]);
+        });
+        if (nl.mask) {
+            unroll<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int ib = TAB<L>.opp[i];
+                if constexpr (i > 0) {
+                    if ((nl.mask >> i) & 1u) {
+                        const uint32_t k = link_index(nl, i);
+                        const LinkCoef c = lkcoef[k];
+                        const double v = p.c0 * (double)fpre_link[i] +
+                                         c.c1 * (double)fpre_link[ib] +
+                                         c.c2 * (double)f[i] + c.c3 * (double)f[ib] +
+                                         c.wall;
+                        waB[k] = (T)v;
+                    }
+                }
+            });
+        }
+    }
+    if (acc_ux) {   // uniform over the launch
+        const double s = block_sum(ux_local);
+        if (threadIdx.x == 0) {
+            uint32_t b = blockIdx.x;
+            if (g.chunk) b = (b % NXCD) * g.chunk + b / NXCD;
+            if (b < g.nblocks) acc_ux[b] += w_ux * s;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// initial state: scatter f(x, 0) into the slots the first pull reads
+template <class L, class T, int XB>
+__global__ void __launch_bounds__(BX)
+k_init(const double* __restrict__ df, const double* __restrict__ rho,
+       const double* __restrict__ u, T* __restrict__ A, T* __restrict__ wa,
+       const int32_t* __restrict__ nodeword, const uint8_t* __restrict__ lkdir,
+       Grid g, Params<L, T> p) {
+    const NodePos pos = node_of_thread(g);
+    if (!pos.in) return;
+    const int32_t nw = nodeword[pos.n];
+    if (nw < 0) return;
+    const NodeLinks nl = node_links(nw, lkdir);
+    double f[L::Q];
+    if (df) {
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            f[i] = df[(size_t)i * g.N + pos.n];
+        });
+    } else {
+        Macro<L, double> m;
+        m.rho = (rho ? rho[pos.n] : p.rho0_d) - p.rho0_d;
+        m.u[0] = m.u[1] = m.u[2] = 0.0;
+        if (u)
+            for (int a = 0; a < L::D; ++a) m.u[a] = u[(size_t)pos.n * L::D + a];
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            f[i] = feq<L, double, i>(m, p.rho0_d);
+        });
+    }
+    const Pull<XB> pl(g, pos);
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if (i > 0 && ((nl.mask >> i) & 1u)) {
+            wa[link_index(nl, i)] = (T)f[i];
+            return;
+        }
+        // the outlet column's -x populations share their slot with the
+        // neighbouring column's; that column's value is kept
+        if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1)
+            if (pos.ix + 1 == g.nx) return;
+        T v = (T)f[i];
+        if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
+            const int sg = seam_sign<L, i>(pos.ix, g.nx);
+            if (sg > 0) v -= p.seam[i];
+            else if (sg < 0) v += p.seam[i];
+        }
+        A[(size_t)i * g.N + pl.template src<L, i>()] = v;
+    });
+}
+
+// ----------------------------------------------------------------------------
+// observation: moments or the full distribution of f(x, t), NaN at solids
+template <class L, class T, int XB>
+__global__ void __launch_bounds__(BX)
+k_observe(const T* __restrict__ A, const T* __restrict__ wa,
+          const int32_t* __restrict__ nodeword, const uint8_t* __restrict__ lkdir,
+          Grid g, Params<L, T> p, double* __restrict__ rho, double* __restrict__ u,
+          double* __restrict__ df) {
+    const NodePos pos = node_of_thread(g);
+    if (!pos.in) return;
+    const int32_t nw = nodeword[pos.n];
+    const double nan = __builtin_nan("");
+    if (nw < 0) {
+        if (rho) rho[pos.n] = nan;
+        if (u)
+            for (int a = 0; a < L::D; ++a) u[(size_t)pos.n * L::D + a] = nan;
+        if (df)
+            for (int i = 0; i < L::Q; ++i) df[(size_t)i * g.N + pos.n] = nan;
+        return;
+    }
+    const NodeLinks nl = node_links(nw, lkdir);
+    T f[L::Q];
+    pull<L, T, XB>(A, wa, g, pos, p, nl, f);
+    if (df) {
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            df[(size_t)i * g.N + pos.n] = (double)f[i];
+        });
+    }
+    if (rho || u) {
+        double r = 0, j[3] = {0, 0, 0};
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double v = (double)f[i];
+            r += v;
+            macc<L::E[i][0]>(j[0], v);
+            macc<L::E[i][1]>(j[1], v);
+            macc<L::E[i][2]>(j[2], v);
+        });
+        if (rho) rho[pos.n] = p.rho0_d + r;
+        if (u)
+            for (int a = 0; a < L::D; ++a) u[(size_t)pos.n * L::D + a] = j[a] / p.rho0_d;
+    }
+}
+
+// per-block sums of drho and sum e f (= rho0 u) over fluid nodes
+template <class L, class T, int XB>
+__global__ void __launch_bounds__(BX)
+k_mass(const T* __restrict__ A, const T* __restrict__ wa,
+       const int32_t* __restrict__ nodeword, const uint8_t* __restrict__ lkdir,
+       Grid g, Params<L, T> p, double* __restrict__ partials) {
+    const NodePos pos = node_of_thread(g);
+    const int32_t nw = pos.in ? nodeword[pos.n] : -1;
+    double r = 0, j[3] = {0, 0, 0};
+    if (nw >= 0) {
+        const NodeLinks nl = node_links(nw, lkdir);
+        T f[L::Q];
+        pull<L, T, XB>(A, wa, g, pos, p, nl, f);
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double v = (double)f[i];
+            r += v;
+            macc<L::E[i][0]>(j[0], v);
+            macc<L::E[i][1]>(j[1], v);
+            macc<L::E[i][2]>(j[2], v);
+        });
+    }
+    uint32_t b = blockIdx.x;
+    if (g.chunk) b = (b % NXCD) * g.chunk + b / NXCD;
+    double vals[4] = {r, j[0], j[1], j[2]};
+    for (int c = 0; c < 1 + L::D; ++c) {
+        const double s = block_sum(vals[c]);
+        if (threadIdx.x == 0 && b < g.nblocks) partials[(size_t)b * (1 + L::D) + c] = s;
+    }
+}
+
+// momentum exchange of the last step on each link; `post` holds f'(t-1) at
+// every node and the link slots f_i(x_f, t)
+template <class L, class T>
+__global__ void __launch_bounds__(BX)
+k_force(const T* __restrict__ B, const T* __restrict__ wa,
+        const int32_t* __restrict__ lknode, const uint8_t* __restrict__ lkdir,
+        const int32_t* __restrict__ lktag, uint32_t n_links, uint32_t N,
+        int n_tags, double rho0, double* __restrict__ partials) {
+    const uint32_t k = blockIdx.x * BX + threadIdx.x;
+    double fx = 0, fy = 0, fz = 0;
+    int tag = -1;
+    if (k < n_links) {
+        const int i = lkdir[k];
+        const uint32_t n = (uint32_t)lknode[k];
+        tag = lktag[k];
+        double fp_ib = 0, wi = 0;
+        int ex = 0, ey = 0, ez = 0;
+        unroll<L::Q>([&](auto I) {
+            constexpr int ii = decltype(I)::value;
+            if (ii == i) {
+                constexpr int ib = TAB<L>.opp[ii];
+                fp_ib = (double)B[(size_t)ib * N + n];
+                wi = L::W[ii];
+                ex = L::E[ii][0];
+                ey = L::E[ii][1];
+                ez = L::E[ii][2];
+            }
+        });
+        // absolute values: f = delta f + w rho0 (w_i = w_ibar)
+        const double v = fp_ib + (double)wa[k] + 2.0 * wi * rho0;
+        fx = -ex * v;
+        fy = -ey * v;
+        fz = -ez * v;
+    }
+    for (int t = 0; t < n_tags; ++t) {
+        const bool mine = (tag == t);
+        const double comp[3] = {mine ? fx : 0.0, mine ? fy : 0.0, mine ? fz : 0.0};
+        for (int a = 0; a < L::D; ++a) {
+            const double s = block_sum(comp[a]);
+            if (threadIdx.x == 0)
+                partials[((size_t)blockIdx.x * n_tags + t) * L::D + a] = s;
+        }
+    }
+}
+
+template <class L, class T>
+__global__ void __launch_bounds__(BX)
+k_force_obj(const T* __restrict__ B, const T* __restrict__ wa,
+            const int32_t* __restrict__ lknode, const uint8_t* __restrict__ lkdir,
+            const int32_t* __restrict__ lktag, uint32_t n_links, uint32_t N,
+            int tag, double rho0, double weight, double* __restrict__ acc) {
+    const uint32_t k = blockIdx.x * BX + threadIdx.x;
+    double fx = 0;
+    if (k < n_links && lktag[k] == tag) {
+        const int i = lkdir[k];
+        const uint32_t n = (uint32_t)lknode[k];
+        unroll<L::Q>([&](auto I) {
+            constexpr int ii = decltype(I)::value;
+            if constexpr (L::E[ii][0] != 0) {
+                if (ii == i) {
+                    constexpr int ib = TAB<L>.opp[ii];
+                    const double v = (double)B[(size_t)ib * N + n] + (double)wa[k] +
+                                     2.0 * L::W[ii] * rho0;
+                    fx = -L::E[ii][0] * v;
+                }
+            }
+        });
+    }
+    const double s = block_sum(fx);
+    if (threadIdx.x == 0) acc[blockIdx.x] += weight * s;
+}
+
+// out[c] = sum over rows of partials[row*cols + c]; one block per column,
+// fixed summation order
+__global__ void __launch_bounds__(BX)
+k_sum_blocks(const double* __restrict__ partials, uint32_t rows, uint32_t cols,
+             double* __restrict__ out) {
+    const uint32_t c = blockIdx.x;
+    double s = 0;
+    for (uint32_t r = threadIdx.x; r < rows; r += BX) s += partials[(size_t)r * cols + c];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[c] = s;
+}
+
+// ----------------------------------------------------------------------------
+// host side
+
+static Grid make_grid(const Engine& e) {
+    Grid g;
+    g.nx = (uint32_t)e.nx;
+    g.ny = (uint32_t)e.ny;
+    g.nz = (uint32_t)e.nz;
+    g.N = (uint32_t)e.N;
+    g.bpr = (uint32_t)((e.nx + BX - 1) / BX);
+    g.nblocks = g.bpr * g.ny * g.nz;
+    g.chunk = (g.nblocks + NXCD - 1) / NXCD;
+    return g;
+}
+
+static unsigned launch_blocks(const Grid& g) {
+    return g.chunk ? g.chunk * NXCD : g.nblocks;
+}
+
+int64_t step_blocks(const Engine& e) { return make_grid(e).nblocks; }
+int64_t link_blocks(const Engine& e) { return (e.n_links + BX - 1) / BX; }
+
+template <class L, class T>
+static Params<L, T> make_params(const Engine& e) {
+    Params<L, T> p;
+    for (int k = 0; k < L::Q; ++k) {
+        const double r = L::conserved(k) ? 0.0 : e.s[k] / (double)TAB<L>.norm[k];
+        p.rate[k] = (T)r;
+    }
+    for (int i = 0; i < L::Q; ++i) {
+        double eg = 0;
+        for (int a = 0; a < L::D; ++a) eg += L::E[i][a] * e.g[a];
+        p.force[i] = (T)(3.0 * L::W[i] * e.rho0 * eg);
+        p.seam[i] = (T)(L::W[i] * (e.xbc == XBC_PRESSURE ? e.drho : 0.0));
+    }
+    p.rho0 = (T)e.rho0;
+    p.inv_rho0 = (T)(1.0 / e.rho0);
+    p.c0 = 1.0 - e.b;
+    p.rho0_d = e.rho0;
+    return p;
+}
+
+// runtime -> compile-time dispatch over lattice, precision and x boundary
+template <class F>
+static hipError_t dispatch(const Engine& e, F&& f) {
+    auto by_xbc = [&](auto lat, auto prec) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        switch (e.xbc) {
+            case XBC_PRESSURE: return f(L{}, T{}, std::integral_constant<int, XBC_PRESSURE>{});
+            case XBC_OUTFLOW: return f(L{}, T{}, std::integral_constant<int, XBC_OUTFLOW>{});
+            default: return f(L{}, T{}, std::integral_constant<int, XBC_PERIODIC>{});
+        }
+    };
+    if (e.lattice == 0)
+        return e.precision == 0 ? by_xbc(D2Q9{}, double{}) : by_xbc(D2Q9{}, float{});
+    return e.precision == 0 ? by_xbc(D3Q19{}, double{}) : by_xbc(D3Q19{}, float{});
+}
+
+hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
+                       const StepObjective& obj) {
+    const Grid g = make_grid(e);
+    return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_step<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
+                           e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
+                           (T*)out.wa, e.d_nodeword, e.d_lkdir, e.d_lkcoef, g,
+                           make_params<L, T>(e), obj.acc_ux, obj.w_ux);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_init(Engine& e, const double* df, const double* rho,
+                       const double* u, const Snapshot& out) {
+    const Grid g = make_grid(e);
+    return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_init<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
+                           e.stream, df, rho, u, (T*)out.f, (T*)out.wa, e.d_nodeword,
+                           e.d_lkdir, g, make_params<L, T>(e));
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_observe(Engine& e, const Snapshot& in, double* rho, double* u,
+                          double* df) {
+    const Grid g = make_grid(e);
+    return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_observe<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
+                           e.stream, (const T*)in.f, (const T*)in.wa, e.d_nodeword,
+                           e.d_lkdir, g, make_params<L, T>(e), rho, u, df);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_mass(Engine& e, const Snapshot& in, double* partials,
+                       int64_t* nblocks) {
+    const Grid g = make_grid(e);
+    *nblocks = g.nblocks;
+    return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_mass<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
+                           e.stream, (const T*)in.f, (const T*)in.wa, e.d_nodeword,
+                           e.d_lkdir, g, make_params<L, T>(e), partials);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_force(Engine& e, const Snapshot& post, double* partials,
+                        int64_t* nblocks) {
+    const int64_t nb = link_blocks(e);
+    *nblocks = nb;
+    if (nb == 0) return hipSuccess;
+    return dispatch(e, [&](auto lat, auto prec, auto) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        hipLaunchKernelGGL((k_force<L, T>), dim3((unsigned)nb), dim3(BX), 0, e.stream,
+                           (const T*)post.f, (const T*)post.wa, e.d_lknode, e.d_lkdir,
+                           e.d_lktag, (uint32_t)e.n_links, (uint32_t)e.N, e.n_tags,
+                           e.rho0, partials);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_force_objective(Engine& e, const Snapshot& post, double* acc,
+                                  int tag, double weight) {
+    const int64_t nb = link_blocks(e);
+    if (nb == 0) return hipSuccess;
+    return dispatch(e, [&](auto lat, auto prec, auto) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        hipLaunchKernelGGL((k_force_obj<L, T>), dim3((unsigned)nb), dim3(BX), 0,
+                           e.stream, (const T*)post.f, (const T*)post.wa, e.d_lknode,
+                           e.d_lkdir, e.d_lktag, (uint32_t)e.n_links, (uint32_t)e.N,
+                           tag, e.rho0, weight, acc);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_sum_blocks(Engine& e, const double* partials, int64_t rows,
+                             int64_t cols, double* out) {
+    if (cols == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_blocks, dim3((unsigned)cols), dim3(BX), 0, e.stream,
+                       partials, (uint32_t)rows, (uint32_t)cols, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbe

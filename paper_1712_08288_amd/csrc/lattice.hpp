@@ -1,0 +1,123 @@
+// Lattice tables for the HIP engine, built at compile time.
+//
+// D2Q9: velocity order and weights of the paper's Appendix (D2Q9 model);
+// moment rows are the Lallemand-Luo polynomials 1, 3e^2-4,
+// (9e^4-21e^2+8)/2, e_x, (3e^2-5)e_x, e_y, (3e^2-5)e_y, e_x^2-e_y^2, e_x e_y,
+// which reproduce the matrix printed in the Appendix.
+// D3Q19: rest, axis and edge vectors, weights 1/3, 1/18, 1/36; rows are the
+// d'Humieres et al. (2002) moment polynomials (the reference the paper
+// cites for its 3D MRT models).
+// Everything here is constexpr so that, after unrolling, every multiply by
+// a matrix entry is folded into an add, a subtract, a scaled FMA or nothing.
+#pragma once
+
+#include <cstdint>
+#include <utility>
+
+namespace lbe {
+
+struct D2Q9 {
+    static constexpr int Q = 9;
+    static constexpr int D = 2;
+    static constexpr int E[9][3] = {{0, 0, 0},  {1, 0, 0},  {0, 1, 0},
+                                    {-1, 0, 0}, {0, -1, 0}, {1, 1, 0},
+                                    {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+    static constexpr double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static constexpr int moment(int k, int i) {
+        const int ex = E[i][0], ey = E[i][1];
+        const int e2 = ex * ex + ey * ey;
+        switch (k) {
+            case 0: return 1;
+            case 1: return 3 * e2 - 4;
+            case 2: return (9 * e2 * e2 - 21 * e2 + 8) / 2;
+            case 3: return ex;
+            case 4: return (3 * e2 - 5) * ex;
+            case 5: return ey;
+            case 6: return (3 * e2 - 5) * ey;
+            case 7: return ex * ex - ey * ey;
+            default: return ex * ey;
+        }
+    }
+    // rows whose non-equilibrium part is identically zero (density, momentum)
+    static constexpr bool conserved(int k) { return k == 0 || k == 3 || k == 5; }
+};
+
+struct D3Q19 {
+    static constexpr int Q = 19;
+    static constexpr int D = 3;
+    static constexpr int E[19][3] = {
+        {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+        {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, 1, 0},  {1, -1, 0},
+        {-1, -1, 0}, {1, 0, 1}, {-1, 0, 1}, {1, 0, -1},  {-1, 0, -1},
+        {0, 1, 1},  {0, -1, 1}, {0, 1, -1}, {0, -1, -1}};
+    static constexpr double W[19] = {
+        1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static constexpr int moment(int k, int i) {
+        const int ex = E[i][0], ey = E[i][1], ez = E[i][2];
+        const int e2 = ex * ex + ey * ey + ez * ez;
+        switch (k) {
+            case 0: return 1;
+            case 1: return 19 * e2 - 30;
+            case 2: return (21 * e2 * e2 - 53 * e2 + 24) / 2;
+            case 3: return ex;
+            case 4: return (5 * e2 - 9) * ex;
+            case 5: return ey;
+            case 6: return (5 * e2 - 9) * ey;
+            case 7: return ez;
+            case 8: return (5 * e2 - 9) * ez;
+            case 9: return 3 * ex * ex - e2;
+            case 10: return (3 * e2 - 5) * (3 * ex * ex - e2);
+            case 11: return ey * ey - ez * ez;
+            case 12: return (3 * e2 - 5) * (ey * ey - ez * ez);
+            case 13: return ex * ey;
+            case 14: return ey * ez;
+            case 15: return ex * ez;
+            case 16: return (ey * ey - ez * ez) * ex;
+            case 17: return (ez * ez - ex * ex) * ey;
+            default: return (ex * ex - ey * ey) * ez;
+        }
+    }
+    static constexpr bool conserved(int k) {
+        return k == 0 || k == 3 || k == 5 || k == 7;
+    }
+};
+
+template <class L>
+struct Tables {
+    int M[L::Q][L::Q];
+    int norm[L::Q];
+    int opp[L::Q];
+    constexpr Tables() : M(), norm(), opp() {
+        for (int k = 0; k < L::Q; ++k) {
+            int s = 0;
+            for (int i = 0; i < L::Q; ++i) {
+                M[k][i] = L::moment(k, i);
+                s += M[k][i] * M[k][i];
+            }
+            norm[k] = s;
+        }
+        for (int i = 0; i < L::Q; ++i)
+            for (int j = 0; j < L::Q; ++j)
+                if (L::E[j][0] == -L::E[i][0] && L::E[j][1] == -L::E[i][1] &&
+                    L::E[j][2] == -L::E[i][2])
+                    opp[i] = j;
+    }
+};
+
+template <class L>
+inline constexpr Tables<L> TAB{};
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1.
+template <class F, int... I>
+__host__ __device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__host__ __device__ __forceinline__ void unroll(F&& f) {
+    unroll_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+}  // namespace lbe

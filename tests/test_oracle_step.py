@@ -234,3 +234,32 @@ def test_uncovered_solid_pull_is_rejected():
                      geom.dir[1:], geom.q[1:], geom.wall_u[1:], geom.tag[1:])
     with pytest.raises(ValueError):
         Oracle(bad, configs.d2q9_rates(0.7))
+
+
+@pytest.mark.parametrize("xbc", ["periodic", "pressure", "outflow"])
+def test_window_mode_matches_full_domain(xbc):
+    """The sampled-window evaluation used for full-size parity equals the
+    full-domain run at the window centres."""
+    from oracle.lbm import sampled_step_outputs
+    if xbc == "outflow":
+        geom = G.channel_cylinder(40, 21, 4.3, (15.2, 10.4), 0.03)
+    else:
+        geom = G.build("D3Q19", (17, 14, 12),
+                       balls=[G.Balls([[5.2, 6.1, 4.3], [12.6, 3.3, 8.8]], [3.1, 2.6])],
+                       x_bc=xbc)
+    lat = L.get(geom.lattice)
+    s = configs.d3q19_rates(0.7) if lat.Q == 19 else configs.d2q9_rates(0.7)
+    df0 = states.random_deviation(lat.Q, geom.n_nodes, seed=12)
+    kw = dict(g=(1e-5, 2e-6, 0), dp=1e-3, l_rule="gamma2")
+    o = Oracle(geom, s, **kw)
+    full = o.as_deviation(o.run(o.init_deviation(df0), 3))
+    fluid = np.nonzero(geom.solid == 0)[0]
+    rng = np.random.default_rng(0)
+    samples = np.sort(rng.choice(fluid, 12, replace=False))
+    # include nodes on the x seam / outlet column
+    nx = geom.shape[0]
+    edge = fluid[(fluid % nx == nx - 1) | (fluid % nx == 1)][:4]
+    samples = np.unique(np.concatenate([samples, edge]))
+    got = sampled_step_outputs(geom, s, df0, 3, samples, **kw)
+    assert np.all(np.isfinite(got))
+    assert np.allclose(got, full[:, samples], atol=1e-18, rtol=1e-12)

@@ -254,9 +254,11 @@ def build(lattice, shape, balls=(), hollows=(), planes=(), x_bc="periodic",
             labs = lab[sel]
             c = cs[labs][:, :D]
             r = rs[labs]
-            d = xf_pos[sel] - c
+            # offset from the centre of the image that contains x_r = x_f - e
+            d = xf_pos[sel] - ef - c
             for a in range(D):
                 d[:, a] = _min_image(d[:, a], L[a])
+            d = d + ef
             bh = d @ ef
             cc = (d * d).sum(1) - r * r
             disc = bh * bh - ee * cc
