@@ -125,6 +125,11 @@ int lbm_set_geometry(lbm_t *h, const uint8_t *solid, int64_t n_links,
  * Either pointer may be NULL to keep the current values. */
 int lbm_update_links(lbm_t *h, const double *q, const double *wall_u);
 
+/* Replace the relaxation rates (Q values, same rules as lbm_create) or the
+ * body force (D values); either pointer may be NULL.  Takes effect at the
+ * next step; the state is kept.  Errors: EINVAL. */
+int lbm_set_parameters(lbm_t *h, const double *s, const double *g);
+
 /* Initial state f(x,0) = f^eq(rho(x), u(x)) of Eq. (42) at fluid nodes.
  * rho: N values or NULL (rho0); u: N*D values, u[n*D + a], or NULL (0).
  * Resets the time counter to 0.  With LBM_X_OUTFLOW, the outlet column's

@@ -41,6 +41,7 @@ _set_scheme = _sig("lbm_set_scheme", _i, [_p, _i, _d])
 _set_xbc = _sig("lbm_set_x_boundary", _i, [_p, _i, _d])
 _set_geometry = _sig("lbm_set_geometry", _i, [_p, _p, _i64, _p, _p, _p, _p, _p])
 _update_links = _sig("lbm_update_links", _i, [_p, _p, _p])
+_set_params = _sig("lbm_set_parameters", _i, [_p, _p, _p])
 _init = _sig("lbm_init", _i, [_p, _p, _p])
 _init_dev = _sig("lbm_init_deviation", _i, [_p, _p])
 _step = _sig("lbm_step", _i, [_p, _i64])
@@ -67,7 +68,7 @@ _last_err = _sig("lbm_last_error", C.c_char_p, [_p])
 _destroy = _sig("lbm_destroy", _i, [_p])
 
 EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_x_boundary",
-            "lbm_set_geometry", "lbm_update_links", "lbm_init",
+            "lbm_set_geometry", "lbm_update_links", "lbm_set_parameters", "lbm_init",
             "lbm_init_deviation", "lbm_step", "lbm_time", "lbm_moments",
             "lbm_get_distribution", "lbm_reduce", "lbm_force",
             "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
@@ -187,6 +188,11 @@ class Solver:
         q = _f64(q)
         wall_u = _f64(wall_u)
         self._chk(_update_links(self._h, _ptr(q), _ptr(wall_u)), "update_links")
+
+    def set_parameters(self, s=None, g=None):
+        s = _f64(s, self.Q) if s is not None else None
+        g = _f64(np.asarray(g, float)[: self.D], self.D) if g is not None else None
+        self._chk(_set_params(self._h, _ptr(s), _ptr(g)), "set_parameters")
 
     def counts(self):
         nf, nl = _i64(), _i64()

@@ -483,6 +483,26 @@ int lbm_update_links(lbm_t* h, const double* q, const double* wall_u) {
     return rc;
 }
 
+int lbm_set_parameters(lbm_t* h, const double* s, const double* g) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (s)
+        for (int k = 0; k < e.Q; ++k) {
+            if (!std::isfinite(s[k])) return fail(h, LBM_EINVAL, "rate not finite");
+            if (!lat_conserved(e.lattice, k) && !(s[k] >= 0.0 && s[k] < 2.0))
+                return fail(h, LBM_EINVAL, "relaxation rates must lie in [0, 2)");
+        }
+    if (g)
+        for (int a = 0; a < e.D; ++a)
+            if (!std::isfinite(g[a])) return fail(h, LBM_EINVAL, "force not finite");
+    HIPCHK(h, hipStreamSynchronize(e.stream));
+    if (s)
+        for (int k = 0; k < e.Q; ++k) e.s[k] = s[k];
+    if (g)
+        for (int a = 0; a < e.D; ++a) e.g[a] = g[a];
+    return LBM_OK;
+}
+
 static int init_common(lbm_t* h, const double* df, const double* rho, const double* u) {
     Engine& e = h->e;
     if (!e.has_geometry) return fail(h, LBM_ESTATE, "set the geometry before init");

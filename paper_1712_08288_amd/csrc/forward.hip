@@ -106,10 +106,10 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
             wa[link_index(nl, i)] = (T)f[i];
             return;
         }
-        // the outlet column's -x populations share their slot with the
-        // neighbouring column's; that column's value is kept
+        // the outlet column's -x populations share their slot with the pull
+        // of node (nx-2, y, z); that node's value is kept unless it is solid
         if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1)
-            if (pos.ix + 1 == g.nx) return;
+            if (pos.ix + 1 == g.nx && nodeword[pos.n - 1] >= 0) return;
         T v = (T)f[i];
         if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
             const int sg = seam_sign<L, i>(pos.ix, g.nx);

@@ -1,0 +1,180 @@
+"""HIP adjoint against the oracle's reverse sweep and against central finite
+differences of the HIP forward run (GPU).
+
+Tolerances.  FP64 adjoint vs the oracle reverse sweep: both in double with
+different summation orders; 1e-10 relative (spec figure).  Central
+differences with step 1e-6 in FP64: truncation O(h^2 J''') ~ 1e-12 and
+cancellation eps |J| / h ~ 1e-10 |J|, compared on links whose |dJ/dq| is
+not tiny against |J|; bound 1e-6 relative (spec figure).
+FP32: the forward is FP32, so its gradient differs from the FP64 one by the
+FP32 forward error; reported against a 1e-3 relative bound (parity unpinned).
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import require_gpu
+from oracle.adjoint import Objective, forward, reverse
+from oracle.lbm import Oracle
+from workloads import configs, states
+from workloads import geometry as G
+from workloads.velocities import VELOCITIES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _gpu_grad(geom, s, kw, obj, steps, every, df0, precision="fp64"):
+    from paper_1712_08288_amd import binding
+    sv = binding.solver_for(geom, s, precision=precision, g=kw.get("g"),
+                            dp=kw.get("dp", 0.0), l_rule=kw.get("l_rule", "min"),
+                            b=kw.get("b", 1.0))
+    sv.init_deviation(df0)
+    sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1)
+    sv.run_checkpointed(steps, every)
+    J = sv.objective()
+    sv.adjoint()
+    gr = sv.grad()
+    gr["lam0"] = sv.get_adjoint()
+    return sv, J, gr
+
+
+CASES = [
+    ("d2q9_drag_periodic", lambda: G.random_cylinders(40, 29, 2, 3.1, 5.2, seed=6),
+     lambda: configs.d2q9_rates(0.7), dict(g=(1e-4, 2e-5, 0), l_rule="gamma2", b=0.9),
+     Objective("force_x", tag=1, t0=3, t1=12), 12),
+    ("d2q9_drag_outflow", lambda: G.channel_cylinder(48, 25, 4.2, (16.3, 12.4), 0.04),
+     lambda: configs.d2q9_rates(0.6), dict(l_rule="gamma2+gamma"),
+     Objective("force_x", tag=1, t0=0, t1=10), 10),
+    ("d3q19_meanux_seam", lambda: G.random_spheres(20, 14, 12, 2, 2.2, 3.4, seed=4, x_bc="pressure"),
+     lambda: configs.d3q19_rates(0.65), dict(g=(2e-5, 0, 1e-5), dp=1e-3, l_rule="gamma"),
+     Objective("mean_ux", t0=2, t1=8), 8),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_matches_oracle_reverse(case):
+    name, mk_geom, mk_s, kw, obj, steps = case
+    geom, s = mk_geom(), mk_s()
+    print("case", name, flush=True)
+    Q = 9 if geom.lattice == "D2Q9" else 19
+    df0 = states.random_deviation(Q, geom.n_nodes, seed=3, amp=2e-3)
+    if geom.x_bc == "outflow":
+        df0 = states.outlet_consistent(df0, geom.shape, VELOCITIES[geom.lattice])
+    base = dict(kw)
+    g0 = base.pop("g", None)
+    o = Oracle(geom, s, g=g0, **base)
+    J_o, st = forward(o, o.init_deviation(df0), steps, obj)
+    r = reverse(o, st, obj)
+    sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, 4, df0)
+    assert abs(J - J_o) <= 1e-12 * abs(J_o) + 1e-18
+    fl = geom.solid == 0
+    for key in ("q", "wall_u", "g"):
+        a, b = gr[key], r[key]
+        scale = max(np.abs(b).max(), 1e-300)
+        assert np.abs(a - b).max() <= 1e-10 * scale, (key, np.abs(a - b).max(), scale)
+    ds_scale = np.abs(r["s"]).max()
+    assert np.abs(gr["s"] - r["s"]).max() <= 1e-10 * ds_scale
+    lam_scale = np.abs(r["lam0"][:, fl]).max()
+    assert np.abs(gr["lam0"][:, fl] - r["lam0"][:, fl]).max() <= 1e-10 * lam_scale
+    sv.close()
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    name, mk_geom, mk_s, kw, obj, steps = CASES[0]
+    geom, s = mk_geom(), mk_s()
+    df0 = states.random_deviation(9, geom.n_nodes, seed=5, amp=2e-3)
+    out = []
+    for every in (1, 3, 5, steps):
+        sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, every, df0)
+        out.append((J, gr))
+        sv.close()
+    for J, gr in out[1:]:
+        assert J == out[0][0]
+        for key in ("q", "wall_u", "g", "s", "lam0"):
+            assert np.array_equal(gr[key], out[0][1][key]), key
+
+
+def test_adjoint_against_central_differences():
+    from paper_1712_08288_amd import binding
+    name, mk_geom, mk_s, kw, obj, steps = CASES[1]
+    geom, s = mk_geom(), mk_s()
+    df0 = np.zeros((9, geom.n_nodes))
+    sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, 5, df0)
+    h = 1e-6
+
+    def J_at(q=None, wall_u=None, g=None, ss=None):
+        sv.update_links(q if q is not None else geom.q,
+                        wall_u if wall_u is not None else geom.wall_u)
+        sv.set_parameters(ss if ss is not None else s, g if g is not None else (0, 0))
+        sv.init_deviation(df0)
+        sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1)
+        sv.step(steps)
+        return sv.objective()
+
+    order = np.argsort(-np.abs(gr["q"]))[:6]
+    for k in order:
+        qp, qm = geom.q.copy(), geom.q.copy()
+        qp[k] += h if geom.q[k] + h <= 1 else 0
+        qm[k] -= h
+        fd = (J_at(q=qp) - J_at(q=qm)) / (qp[k] - qm[k])
+        assert abs(fd - gr["q"][k]) <= 1e-6 * abs(gr["q"][k]), (k, fd, gr["q"][k])
+    # inflow velocity: sum over the inlet links (tag 2) of dJ/dphi_x
+    inlet = geom.tag == 2
+    up, um = geom.wall_u.copy(), geom.wall_u.copy()
+    up[inlet, 0] += h
+    um[inlet, 0] -= h
+    fd = (J_at(wall_u=up) - J_at(wall_u=um)) / (2 * h)
+    dui = gr["wall_u"][inlet, 0].sum()
+    assert abs(fd - dui) <= 1e-6 * abs(dui), (fd, dui)
+    # viscous rate s_nu (rows 7, 8 together), i.e. tau
+    sp, sm = s.copy(), s.copy()
+    sp[7:9] += h
+    sm[7:9] -= h
+    fd = (J_at(ss=sp) - J_at(ss=sm)) / (2 * h)
+    dsn = gr["s"][7] + gr["s"][8]
+    assert abs(fd - dsn) <= 1e-6 * abs(dsn), (fd, dsn)
+    sv.close()
+
+
+def test_fp32_adjoint_is_close_to_fp64():
+    name, mk_geom, mk_s, kw, obj, steps = CASES[2]
+    geom, s = mk_geom(), mk_s()
+    df0 = states.random_deviation(19, geom.n_nodes, seed=3, amp=2e-3)
+    sv64, J64, g64 = _gpu_grad(geom, s, kw, obj, steps, 4, df0, "fp64")
+    sv32, J32, g32 = _gpu_grad(geom, s, kw, obj, steps, 4, df0, "fp32")
+    assert abs(J32 - J64) <= 1e-4 * abs(J64)
+    for key in ("q", "g"):
+        scale = np.abs(g64[key]).max()
+        assert np.abs(g32[key] - g64[key]).max() <= 1e-3 * scale, key
+    sv64.close()
+    sv32.close()
+
+
+def test_autograd_function_matches_adjoint():
+    import torch
+    from paper_1712_08288_amd import binding
+    from paper_1712_08288_amd.autograd import Problem, objective
+    name, mk_geom, mk_s, kw, obj, steps = CASES[1]
+    geom, s = mk_geom(), mk_s()
+    sv = binding.solver_for(geom, s, l_rule=kw["l_rule"])
+    prob = Problem(sv, steps=steps, every=4, objective="force_x", tag=1,
+                   window=(obj.t0, obj.t1))
+    q = torch.tensor(geom.q, requires_grad=True)
+    wu = torch.tensor(geom.wall_u, requires_grad=True)
+    g = torch.zeros(2, dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(1.0 / s[7], dtype=torch.float64, requires_grad=True)
+    ss = torch.cat([torch.tensor(s[:7]), (1.0 / tau).reshape(1), (1.0 / tau).reshape(1)])
+    J = objective(q, wu, g, ss, prob)
+    J.backward()
+    sv2, J2, gr = _gpu_grad(geom, s, kw, obj, steps, 4, np.zeros((9, geom.n_nodes)))
+    assert float(J) == J2
+    assert np.array_equal(q.grad.numpy(), gr["q"])
+    dtau = -(gr["s"][7] + gr["s"][8]) / float(tau) ** 2
+    assert np.isclose(float(tau.grad), dtau, rtol=1e-12)
+    sv.close()
+    sv2.close()

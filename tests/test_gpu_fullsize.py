@@ -1,0 +1,88 @@
+"""Parity at the benchmark sizes (GPU): the full domain runs on the GPU in
+the launch configuration bench.py times; the oracle recomputes sampled
+nodes one by one on windows around them (window mode: exact after k steps
+when the window half-width exceeds k), from the same seeded non-equilibrium
+initial state.  Samples include nodes with cut links and nodes on the x
+seam.  Tolerances as in test_gpu_forward.py.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import require_gpu
+from oracle.lbm import sampled_step_outputs
+from workloads import configs, states
+from workloads.velocities import VELOCITIES
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 3
+TOL = {"fp64": 1e-12, "fp32": 3e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _samples(geom, n_random=24, n_link=16, seed=0):
+    rng = np.random.default_rng(seed)
+    fluid = np.nonzero(geom.solid == 0)[0]
+    pick = [rng.choice(fluid, n_random, replace=False)]
+    if geom.n_links:
+        pick.append(rng.choice(np.unique(geom.node), n_link, replace=False))
+    nx = geom.shape[0]
+    x = fluid % nx
+    for col in (0, nx - 1):
+        c = fluid[x == col]
+        if len(c):
+            pick.append(rng.choice(c, min(4, len(c)), replace=False))
+    return np.unique(np.concatenate(pick))
+
+
+def _run(w, precision, seed=17):
+    from paper_1712_08288_amd import binding
+    geom = w.geometry()
+    Q = 9 if geom.lattice == "D2Q9" else 19
+    print("workload", w.name, precision, geom.shape, "links", geom.n_links, flush=True)
+    df0 = states.random_deviation(Q, geom.n_nodes, seed=seed, amp=1e-3)
+    if geom.x_bc == "outflow":
+        df0 = states.outlet_consistent(df0, geom.shape, VELOCITIES[geom.lattice])
+    sv = binding.solver_for(geom, w.s, g=w.g, precision=precision, dp=w.dp,
+                            l_rule=w.l_rule, b=w.b)
+    sv.init_deviation(df0)
+    sv.step(STEPS)
+    got = sv.distribution()
+    sv.close()
+    samples = _samples(geom)
+    want = sampled_step_outputs(geom, w.s, df0, STEPS, samples, g=w.g, dp=w.dp,
+                                l_rule=w.l_rule, b=w.b)
+    g = got[:, samples]
+    err = np.sqrt(((g - want) ** 2).sum() / (want ** 2).sum())
+    return err, np.isfinite(g).all()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_c3_spheres_256(precision):
+    err, finite = _run(configs.c3_spheres(), precision)
+    assert finite
+    assert err < TOL[precision], err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c2_cylinders_2048(precision):
+    err, finite = _run(configs.c2_cylinders(), precision)
+    assert finite
+    assert err < TOL[precision], err
+
+
+def test_c4_channel_1024x512():
+    err, finite = _run(configs.c4_cylinder(), "fp64")
+    assert finite
+    assert err < TOL["fp64"], err
+
+
+def test_c5_porous_384x256x256_fp32():
+    err, finite = _run(configs.c5_porous(), "fp32")
+    assert finite
+    assert err < TOL["fp32"], err

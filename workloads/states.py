@@ -22,3 +22,17 @@ def random_deviation(Q, n_nodes, seed, amp=1e-3):
     the state has a non-equilibrium part for the collision to relax."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-amp, amp, size=(Q, n_nodes))
+
+
+def outlet_consistent(df, shape, velocities):
+    """Copy, for every population moving in -x, the initial value of column
+    nx-2 into column nx-1.  A zero-gradient outlet reads those populations
+    from the neighbouring column, so an initial state given with the outflow
+    x boundary must already satisfy this to be representable exactly."""
+    nx, ny, nz = shape
+    out = np.array(df, copy=True)
+    cols = out.reshape(out.shape[0], nz, ny, nx)
+    for i, e in enumerate(velocities):
+        if e[0] == -1:
+            cols[i, :, :, nx - 1] = cols[i, :, :, nx - 2]
+    return out
