@@ -53,7 +53,32 @@ def time_forward(binding, geom, w, precision, steps, warmup):
     return sv, (t1 - t0) * 1e3 / steps, kernel_ms
 
 
-def cpu_baseline(geom, w, slab=48, steps=4):
+def copy_ceiling(binding, torch, nbytes=1 << 31, reps=20, all_modes=False):
+    """Best streaming-copy rate (read + write of nbytes) of the library's
+    probe kernels, and of the HIP runtime copy used by torch."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    out = {"bytes": nbytes}
+    best = 0.0
+    for mode in (0, 1, 2):
+        ms = binding.stream_copy(b, a, nbytes, mode=mode, reps=reps)
+        gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+        out["mode%d_GBps" % mode] = round(gbs, 1)
+        best = max(best, gbs)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    out["hip_memcpy_GBps"] = round(2 * nbytes / ((time.perf_counter() - t0) / reps) / 1e9, 1)
+    out["best_GBps"] = round(best, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(geom, w, slab=48, steps=20):
     """Oracle on the z-slab 0 <= z < slab of the same workload (window mode:
     reads across the slab faces see NaN and are not used)."""
     from oracle.lbm import Oracle
@@ -85,6 +110,8 @@ def main():
     ap.add_argument("--every", type=int, default=8)
     ap.add_argument("--n", type=int, default=256, help="lattice edge (256 = the benchmark)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["fwd32", "fwd64", "adjoint32", "copy"],
+                    help="profiling runs: time only this part and print its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is a single-GPU kernel "
@@ -98,9 +125,36 @@ def main():
     from paper_1712_08288_amd import binding
     from workloads import configs
 
+    if args.only == "copy":
+        # reference copies of known size: HBM ceiling and counter scaling
+        print(json.dumps(copy_ceiling(binding, torch, reps=args.steps, all_modes=True)))
+        return
+
     w = configs.c3_spheres(args.n)
     geom = w.geometry()
     N, NF, NL = geom.n_nodes, geom.n_fluid, geom.n_links
+    if args.only in ("fwd32", "fwd64"):
+        prec = args.only.replace("fwd", "fp")
+        sv, ms, kms = time_forward(binding, geom, w, prec, args.steps, args.warmup)
+        s = 4 if prec == "fp32" else 8
+        by = algorithmic_bytes(19, s, N, NF, NL)
+        print(json.dumps({"only": args.only, "ms_per_step": ms, "kernel_ms": kms,
+                          "algorithmic_bytes": by, "GBps": by / (kms * 1e-3) / 1e9}))
+        sv.close()
+        return
+    if args.only == "adjoint32":
+        sv = binding.solver_for(geom, w.s, precision="fp32", dp=w.dp, l_rule=w.l_rule)
+        sv.init()
+        sv.step(args.warmup)
+        sv.set_rate_gradient(False)
+        sv.set_objective("mean_ux", 0, sv.time, sv.time + args.adjoint_steps)
+        sv.run_checkpointed(args.adjoint_steps, args.every)
+        sv.adjoint()
+        g = sv.grad()
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "adjoint32", "dJ_dg": [float(v) for v in g["g"]]}))
+        sv.close()
+        return
 
     # FP32 forward (headline)
     sv32, ms32, kms32 = time_forward(binding, geom, w, "fp32", args.steps, args.warmup)
@@ -115,6 +169,7 @@ def main():
 
     # FP32 forward + adjoint (checkpointed run, then the reverse sweep)
     A = args.adjoint_steps
+    sv32.set_rate_gradient(False)      # the benchmark objective needs dJ/dg and dJ/dq
     sv32.set_objective("mean_ux", 0, sv32.time, sv32.time + A)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -130,6 +185,7 @@ def main():
     ms_adj = (t2 - t1) * 1e3 / A
     sv32.close()
 
+    ceiling = copy_ceiling(binding, torch)
     bytes32 = algorithmic_bytes(19, 4, N, NF, NL)
     bytes64 = algorithmic_bytes(19, 8, N, NF, NL)
     achieved = bytes32 / (kms32 * 1e-3) / 1e9
@@ -163,6 +219,8 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
             "kernel": "k_step<D3Q19,float,pressure>",
+            "copy_ceiling_GBps": ceiling["best_GBps"],
+            "frac_of_copy_ceiling": round(achieved / ceiling["best_GBps"], 4),
             "kernel_ms": round(kms32, 4),
             "algorithmic_bytes": int(bytes32),
         },

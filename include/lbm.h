@@ -101,6 +101,14 @@ int lbm_create(lbm_t **out, int lattice, int precision, int64_t nx,
  * lbm_set_geometry.  Errors: EINVAL, ESTATE (geometry already set). */
 int lbm_set_scheme(lbm_t *h, int l_rule, double b);
 
+/* Use the two-node scheme Eq. (211) of Remark (2) instead of Eq. (210)
+ * (on != 0): the time-lagged f_ibar(x_f, t) is replaced by its advected
+ * value f'_ibar(x_f + e_i, t), which the next step's pull brings to x_f; a
+ * link whose neighbour x_f + e_i is solid keeps Eq. (210).  With b < 1 the
+ * bracket of Eq. (213) is modified the same way.  Must precede
+ * lbm_set_geometry.  Errors: ESTATE. */
+int lbm_set_two_node(lbm_t *h, int on);
+
 /* Choose the x boundary (see above); drho is used by LBM_X_PRESSURE only.
  * Must precede lbm_set_geometry.  Errors: EINVAL, ESTATE. */
 int lbm_set_x_boundary(lbm_t *h, int kind, double drho);
@@ -196,6 +204,11 @@ int lbm_run_checkpointed(lbm_t *h, int64_t n, int64_t every);
  * the objective.  Leaves the forward state at the end of the run. */
 int lbm_adjoint(lbm_t *h);
 
+/* Choose whether lbm_adjoint() accumulates dJ/ds for the relaxation rates
+ * (a block reduction of Q extra sums per step; default on).  When off,
+ * lbm_grad() reports zeros for ds. */
+int lbm_set_rate_gradient(lbm_t *h, int on);
+
 /* Gradients of J from the last lbm_adjoint(), in double: dq[k] = dJ/dgamma_k
  * (l follows gamma through the rule), dwall_u[k*D + a] = dJ/dphi_k,a,
  * dg[a] = dJ/dg_a, ds[k] = dJ/ds_k for the relaxation rates.  Any pointer
@@ -223,6 +236,18 @@ int lbm_counts(const lbm_t *h, int64_t *n_fluid, int64_t *n_links);
  * (timing enabled by lbm_set_timing(h, 1)). */
 int lbm_set_timing(lbm_t *h, int on);
 int lbm_last_step_ms(lbm_t *h, double *ms_per_step);
+
+/* Measurement helper, not part of the method: copy `bytes` (a multiple of
+ * 16) from src_dev to dst_dev `reps` times after one warm-up copy, on a
+ * private stream, and report the mean time per copy from HIP events.  Used
+ * as the practical HBM ceiling (read + write of `bytes`) that the step
+ * kernels are compared against.  mode 0: grid-stride loop with four
+ * independent 16-byte loads per thread and non-temporal stores; 1: one
+ * 16-byte element per thread, non-temporal stores; 2: as 1 with ordinary
+ * stores.  Both buffers are device memory owned by the caller and must not
+ * overlap.  Errors: EINVAL, EDEVICE. */
+int lbm_stream_copy(void *dst_dev, const void *src_dev, int64_t bytes,
+                    int32_t mode, int32_t reps, double *ms_per_copy);
 
 const char *lbm_last_error(const lbm_t *h);
 int lbm_destroy(lbm_t *h);

@@ -114,6 +114,11 @@ def reverse(o, states, obj, rule=None):
         a_link = a[i, xf].copy()
         a_stream = a.copy()
         a_stream[i, xf] = 0.0
+        # Eq. (211): the c1 term reads the advected f_ibar(x_f, t+1)
+        defer = o.two_node & ~o.lk_ibar_is_link if o.two_node else np.zeros(len(xf), bool)
+        np.add.at(a_stream, (ib[defer], xf[defer]), (c1 * a_link)[defer]
+                  if np.ndim(c1) else c1 * a_link[defer])
+        f_ib = np.where(defer, fn[ib, xf], f[ib, xf])
         mu = np.zeros((Q, N))
         for d in range(Q):
             np.add.at(mu[d], o.src[d, fluid], a_stream[d, fluid])
@@ -123,9 +128,9 @@ def reverse(o, states, obj, rule=None):
         np.add.at(mu, (i, xf), c2 * a_link)
         np.add.at(mu, (ib, xf), c3 * a_link)
         np.add.at(direct, (i, xf), c0 * a_link)
-        np.add.at(direct, (ib, xf), c1 * a_link)
+        np.add.at(direct, (ib, xf), np.where(defer, 0.0, c1 * a_link))
         # per-link gradients
-        gq += a_link * (d0 * f[i, xf] + d1 * f[ib, xf] + d2 * fp[i, xf]
+        gq += a_link * (d0 * f[i, xf] + d1 * f_ib + d2 * fp[i, xf]
                         + d3 * fp[ib, xf] + d4 * o.wall_term)
         gphi += (a_link * c4)[:, None] * unit_e
         # body force and rates

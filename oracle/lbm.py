@@ -38,8 +38,12 @@ from . import scheme as _scheme
 class Oracle:
     def __init__(self, geom, s, rho0=1.0, g=None, dp=0.0, l_rule="min",
                  b=1.0, deviation=True, q=None, wall_u=None,
-                 allow_nonconvex=False, nodes=None):
-        """nodes: optional sorted array of global node indices to simulate (a
+                 allow_nonconvex=False, nodes=None, two_node=False):
+        """two_node: use Eq. (211) (Remark (2)) instead of Eq. (210): the
+        time-lagged f_ibar(x_f, t) is replaced by its advected value
+        f'_ibar(x_f + e_i, t) whenever that neighbour is fluid; links whose
+        neighbour x_f + e_i is solid keep Eq. (210).
+        nodes: optional sorted array of global node indices to simulate (a
         window).  Pull sources outside the window read NaN, so after k steps
         exactly the nodes at least k pulls away from the window's edge are
         exact; the full domain is used when nodes is None."""
@@ -62,6 +66,7 @@ class Oracle:
         self.base = self.w * rho0 if deviation else np.zeros(self.Q)
         self.rho_base = rho0 if deviation else 0.0
         self.l_rule, self.b = l_rule, b
+        self.two_node = two_node
         n_all = nx * ny * nz
         self.window = nodes is not None
         self.nodes = (np.arange(n_all, dtype=np.int64) if nodes is None
@@ -114,6 +119,9 @@ class Oracle:
         self.F = 3.0 * self.w * rho0 * (self.e @ self.g)
         if not self.window:
             self._check_links()
+        is_link = np.zeros((self.Q, self.N), dtype=bool)
+        is_link[self.lk_dir, self.lk_node] = True
+        self.lk_ibar_is_link = is_link[self.lk_opp, self.lk_node]
 
     def _check_links(self):
         """A direction at a fluid node is a cut link exactly when the node it
@@ -165,10 +173,16 @@ class Oracle:
         return fn
 
     def boundary(self, f, fp, fn):
-        """Eq. (213) on every cut link, from values held at x_f only."""
+        """Eq. (213) on every cut link, from values held at x_f only
+        (Eq. (211) variant: the f_ibar term from the advected value)."""
         xf, i, ib = self.lk_node, self.lk_dir, self.lk_opp
         c0, c1, c2, c3, c4 = self.c
-        fn[i, xf] = (c0 * f[i, xf] + c1 * f[ib, xf] + c2 * fp[i, xf]
+        f_ib = f[ib, xf]
+        if self.two_node:
+            # f_ibar(x_f, t+1) after advection, unless (x_f, ibar) is itself
+            # a cut link (x_f + e_i solid): then the single-node form
+            f_ib = np.where(self.lk_ibar_is_link, f_ib, fn[ib, xf])
+        fn[i, xf] = (c0 * f[i, xf] + c1 * f_ib + c2 * fp[i, xf]
                      + c3 * fp[ib, xf] + c4 * self.wall_term)
         return fn
 

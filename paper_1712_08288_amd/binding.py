@@ -39,6 +39,7 @@ def _sig(name, res, args):
 _create = _sig("lbm_create", _i, [C.POINTER(_p), _i, _i, _i64, _i64, _i64, _dp, _d, _dp])
 _set_scheme = _sig("lbm_set_scheme", _i, [_p, _i, _d])
 _set_xbc = _sig("lbm_set_x_boundary", _i, [_p, _i, _d])
+_set_two_node = _sig("lbm_set_two_node", _i, [_p, _i])
 _set_geometry = _sig("lbm_set_geometry", _i, [_p, _p, _i64, _p, _p, _p, _p, _p])
 _update_links = _sig("lbm_update_links", _i, [_p, _p, _p])
 _set_params = _sig("lbm_set_parameters", _i, [_p, _p, _p])
@@ -58,24 +59,27 @@ _objective = _sig("lbm_objective", _i, [_p, _p])
 _run_ckpt = _sig("lbm_run_checkpointed", _i, [_p, _i64, _i64])
 _adjoint = _sig("lbm_adjoint", _i, [_p])
 _grad = _sig("lbm_grad", _i, [_p, _p, _p, _p, _p])
+_set_rate_grad = _sig("lbm_set_rate_gradient", _i, [_p, _i])
 _get_adj = _sig("lbm_get_adjoint", _i, [_p, _p])
 _set_stream = _sig("lbm_set_stream", _i, [_p, _p])
 _lat_info = _sig("lbm_lattice_info", _i, [_i, _p, _p, _p, _p, _p])
 _counts = _sig("lbm_counts", _i, [_p, _p, _p])
 _set_timing = _sig("lbm_set_timing", _i, [_p, _i])
 _last_ms = _sig("lbm_last_step_ms", _i, [_p, _p])
+_stream_copy = _sig("lbm_stream_copy", _i, [_p, _p, _i64, _i32, _i32, _p])
 _last_err = _sig("lbm_last_error", C.c_char_p, [_p])
 _destroy = _sig("lbm_destroy", _i, [_p])
 
-EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_x_boundary",
+EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_x_boundary",
             "lbm_set_geometry", "lbm_update_links", "lbm_set_parameters", "lbm_init",
             "lbm_init_deviation", "lbm_step", "lbm_time", "lbm_moments",
             "lbm_get_distribution", "lbm_reduce", "lbm_force",
             "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
             "lbm_set_objective", "lbm_objective", "lbm_run_checkpointed",
-            "lbm_adjoint", "lbm_grad", "lbm_get_adjoint", "lbm_set_stream",
+            "lbm_adjoint", "lbm_set_rate_gradient", "lbm_grad", "lbm_get_adjoint", "lbm_set_stream",
             "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
-            "lbm_last_step_ms", "lbm_last_error", "lbm_destroy"]
+            "lbm_last_step_ms", "lbm_stream_copy", "lbm_last_error",
+            "lbm_destroy"]
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
@@ -118,6 +122,18 @@ def lattice_info(lattice):
     if rc:
         raise LBMError(rc, "lattice_info")
     return e.astype(np.int64), w, M
+
+
+def stream_copy(dst, src, nbytes, mode=0, reps=10):
+    """Time a plain device copy of nbytes (the practical HBM ceiling);
+    dst/src: torch tensors or device pointers.  Returns ms per copy."""
+    d = dst.data_ptr() if hasattr(dst, "data_ptr") else int(dst)
+    s = src.data_ptr() if hasattr(src, "data_ptr") else int(src)
+    ms = np.zeros(1)
+    rc = _stream_copy(_p(d), _p(s), int(nbytes), int(mode), int(reps), _ptr(ms))
+    if rc:
+        raise LBMError(rc, "stream_copy")
+    return float(ms[0])
 
 
 class Solver:
@@ -167,6 +183,9 @@ class Solver:
     # -- set-up
     def set_scheme(self, l_rule="min", b=1.0):
         self._chk(_set_scheme(self._h, RULES[l_rule], float(b)), "set_scheme")
+
+    def set_two_node(self, on=True):
+        self._chk(_set_two_node(self._h, 1 if on else 0), "set_two_node")
 
     def set_x_boundary(self, kind="periodic", drho=0.0):
         self._chk(_set_xbc(self._h, X_BC[kind], float(drho)), "set_x_boundary")
@@ -270,6 +289,9 @@ class Solver:
     def adjoint(self):
         self._chk(_adjoint(self._h), "adjoint")
 
+    def set_rate_gradient(self, on=True):
+        self._chk(_set_rate_grad(self._h, 1 if on else 0), "set_rate_gradient")
+
     def grad(self):
         nf, nl = self.counts()
         dq = np.zeros(nl)
@@ -295,10 +317,12 @@ class Solver:
 
 
 def solver_for(geom, s, rho0=1.0, g=None, precision="fp64", l_rule="min",
-               b=1.0, dp=0.0):
+               b=1.0, dp=0.0, two_node=False):
     """Create a Solver and load a workloads.Geometry-like object into it."""
     sv = Solver(geom.lattice, geom.shape, s, rho0=rho0, g=g, precision=precision)
     sv.set_scheme(l_rule, b)
+    if two_node:
+        sv.set_two_node(True)
     sv.set_x_boundary(geom.x_bc, dp)
     sv.set_geometry(geom.solid, geom.node, geom.dir, geom.q, geom.wall_u, geom.tag)
     return sv

@@ -68,7 +68,7 @@ struct AdjArgs {
 };
 
 template <int NC>
-__device__ __forceinline__ void block_accumulate(double (&v)[NC], double* __restrict__ dst) {
+__device__ __forceinline__ void block_accumulate(const double (&v)[NC], double* __restrict__ dst) {
     __shared__ double part[BX / 64][NC];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -86,7 +86,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NC], double* __rest
     }
 }
 
-template <class L, class T, int XB>
+template <class L, class T, int XB, bool WANT_DS>
 __global__ void __launch_bounds__(BX)
 k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
@@ -95,84 +95,66 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
           const double* __restrict__ lkc4, const int32_t* __restrict__ lktag,
           double* __restrict__ gq, double* __restrict__ gphi,
           double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
-    constexpr int Q = L::Q, D = L::D;
-    constexpr int NC = D + Q;
+    constexpr int Q = L::Q, D = L::D, NP = NPAIR<L>;
+    constexpr int NC = D + Q;                 // layout of the per-block sums
+    constexpr int NR = WANT_DS ? NC : D;      // columns reduced here
     const NodePos pos = node_of_thread(g);
     const int32_t nw = pos.in ? nodeword[pos.n] : -1;
-    double acc[NC];
+    double acc[NR];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
 
     if (nw >= 0) {
         const NodeLinks nl = node_links(nw, lkdir);
-        // forward recomputation at this node
-        T f0[Q];
-        pull<L, T, XB>(A, wa, g, pos, p, nl, f0);
-        const Macro<L, T> mac = moments<L, T>(f0, p.inv_rho0);
-        T mneq[Q];
-        {
-            T d[Q];
-            unroll<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                d[i] = f0[i] - feq<L, T, i>(mac, p.rho0);
-            });
-            unroll<Q>([&](auto K) {
-                constexpr int k = decltype(K)::value;
-                T s = 0;
-                if constexpr (!L::conserved(k))
-                    unroll<Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        macc<TAB<L>.M[k][i]>(s, d[i]);
-                    });
-                mneq[k] = s;
-            });
-        }
-        T fp[Q];
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            T s = 0;
-            unroll<Q>([&](auto K) {
-                constexpr int k = decltype(K)::value;
-                if constexpr (!L::conserved(k)) macc<TAB<L>.M[k][i]>(s, mneq[k] * p.rate[k]);
-            });
-            fp[i] = f0[i] - s + p.force[i];
-        });
+        // forward state f(y, t) and its velocity
+        T f[Q];
+        pull<L, T, XB>(A, wa, g, pos, p, nl, f);
+        T sp[NP], dp[NP];
+        pair_split<L, T>(f, sp, dp);
+        T rho, j[3];
+        conserved_of<L, T>(f[0], sp, dp, rho, j);
+        const T u[3] = {j[0] * p.inv_rho0, j[1] * p.inv_rho0, j[2] * p.inv_rho0};
 
-        // mu: adjoint of the post-collision values at this node
-        T mu[Q];
-        T dir[Q];
+        // mu_i(y) = dJ/df'_i(y): lambda_i(y + e_i, t+1) where that node pulls
+        T mu[Q], dir[Q];
         const Push<XB> ps(g, pos);
         unroll<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int ib = TAB<L>.opp[i];
             dir[i] = 0;
-            mu[i] = 0;
             if constexpr (i == 0) {
-                mu[i] = lam_in[pos.n];
+                mu[i] = ld(lam_in, pos.n);
             } else {
-                const bool into_wall = (nl.mask >> ib) & 1u;
-                bool lost = into_wall;
+                bool lost = (nl.mask >> ib) & 1u;     // y + e_i is solid
                 if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == 1) lost = lost || ps.x_out;
-                if (!lost) mu[i] = lam_in[(size_t)i * g.N + ps.template dst<L, i>()];
+                mu[i] = lost ? T(0) : ld(lam_in + (size_t)i * g.S, ps.template dst<L, i>());
                 if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1) {
                     if (ps.x_out) {
                         const uint32_t n2 = ps.template dst_clamped<L, i>(pos.ix);
-                        if (nodeword[n2] >= 0) mu[i] += lam_in[(size_t)i * g.N + n2];
+                        if (nodeword[n2] >= 0) mu[i] += ld(lam_in + (size_t)i * g.S, n2);
                     }
                 }
             }
         });
 
-        // own cut links: Eq. (213) reversed, objective terms, per-link gradients
+        // own cut links: Eq. (213) reversed, drag terms, per-link gradients
         if (nl.mask) {
+            T fp[Q];
+            unroll<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                fp[i] = f[i];
+            });
+            Macro<L, T> mac;
+            collide<L, T>(fp, p, mac);
+            uint32_t k = nl.base;
             unroll<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 constexpr int ib = TAB<L>.opp[i];
                 if constexpr (i > 0) {
-                    if ((nl.mask >> i) & 1u) {
-                        const uint32_t k = link_index(nl, i);
-                        double ak = (double)lam_in[(size_t)i * g.N + pos.n];
-                        if (a.obj_kind == 1 && lktag[k] == a.obj_tag && L::E[i][0] != 0) {
+                    const uint32_t bit = (nl.mask >> i) & 1u;
+                    if (bit) {
+                        double ak = (double)ld(lam_in + (size_t)i * g.S, pos.n);
+                        if (a.obj_kind == 1 && L::E[i][0] != 0 && lktag[k] == a.obj_tag) {
                             // drag: (e_ibar)_x (f'_ibar(y,t) + f_i(y,t+1))
                             const double dfx = -(double)L::E[i][0] * a.w_force;
                             ak += dfx;
@@ -184,101 +166,140 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
                         mu[ib] += (T)(c.c3 * ak);
                         dir[i] += (T)(p.c0 * ak);
                         dir[ib] += (T)(c.c1 * ak);
-                        gq[k] += ak * (dc.d1 * (double)f0[ib] + dc.d2 * (double)fp[i] +
+                        gq[k] += ak * (dc.d1 * (double)f[ib] + dc.d2 * (double)fp[i] +
                                        dc.d3 * (double)fp[ib] + dc.dwall);
                         const double c4w = lkc4[k] * 3.0 * L::W[i] * p.rho0_d * ak;
 #pragma unroll
                         for (int al = 0; al < D; ++al)
-                            gphi[(size_t)k * D + al] += c4w * L::E[i][al];
+                            if (L::E[i][al] != 0)
+                                gphi[(size_t)k * D + al] += c4w * L::E[i][al];
                     }
+                    k += bit;
                 }
             });
         }
 
-        // dJ/dg and dJ/ds partials
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const double m3 = 3.0 * L::W[i] * p.rho0_d * (double)mu[i];
-#pragma unroll
-            for (int al = 0; al < D; ++al)
-                if (L::E[i][al] != 0) acc[al] += L::E[i][al] * m3;
+        // collision adjoint: lambda = mu - v + J^T v, v = M^T R M mu
+        T smu[NP], dmu[NP];
+        pair_split<L, T>(mu, smu, dmu);
+        T qm[Q];
+        moments_of<L, T>(mu[0], smu, dmu, qm);
+        T r[Q];
+        unroll<Q>([&](auto K) {
+            constexpr int kk = decltype(K)::value;
+            r[kk] = qm[kk] * p.rate[kk];
+        });
+        T e0, ev[NP], od[NP];
+        back_transform<L, T>(r, e0, ev, od);
+        // J^T v = as + b.e_j with as = sum w_i v_i and
+        // b = sum_i w_i v_i (3 e_i + 9 (e_i.u) e_i) - 3 u as
+        T as = T(L::W[0]) * e0;
+        T b[3] = {0, 0, 0};
+        unroll<NP>([&](auto P) {
+            constexpr int pp = decltype(P)::value;
+            constexpr int i = DER<L>.pi[pp];
+            const T w2 = T(2.0 * L::W[i]);
+            as += w2 * ev[pp];
+            T eu = 0;
+            macc<L::E[i][0]>(eu, u[0]);
+            macc<L::E[i][1]>(eu, u[1]);
+            macc<L::E[i][2]>(eu, u[2]);
+            const T t = w2 * (T(3) * od[pp] + T(9) * eu * ev[pp]);
+            macc<L::E[i][0]>(b[0], t);
+            macc<L::E[i][1]>(b[1], t);
+            macc<L::E[i][2]>(b[2], t);
+        });
+        b[0] -= T(3) * u[0] * as;
+        b[1] -= T(3) * u[1] * as;
+        b[2] -= T(3) * u[2] * as;
+        const T wux = (T)a.w_ux;
+        auto finish = [&](auto J, T v) {
+            constexpr int jd = decltype(J)::value;
+            T out = mu[jd] - v + as + dir[jd];
+            macc<L::E[jd][0]>(out, b[0]);
+            macc<L::E[jd][1]>(out, b[1]);
+            macc<L::E[jd][2]>(out, b[2]);
+            if (a.obj_kind == 2) macc<L::E[jd][0]>(out, wux);
+            st_nt(lam_out + (size_t)jd * g.S, pos.n, out);
+        };
+        finish(std::integral_constant<int, 0>{}, e0);
+        unroll<NP>([&](auto P) {
+            constexpr int pp = decltype(P)::value;
+            constexpr int i = DER<L>.pi[pp];
+            constexpr int ib = TAB<L>.opp[i];
+            finish(std::integral_constant<int, i>{}, ev[pp] + od[pp]);
+            finish(std::integral_constant<int, ib>{}, ev[pp] - od[pp]);
         });
 
-        // collision adjoint
-        T qm[Q];
-        unroll<Q>([&](auto K) {
-            constexpr int k = decltype(K)::value;
-            T s = 0;
-            if constexpr (!L::conserved(k))
-                unroll<Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    macc<TAB<L>.M[k][i]>(s, mu[i]);
-                });
-            qm[k] = s;
+        // dJ/dg += 3 rho0 sum_i w_i e_i mu_i (pair form: w_i e_i (mu_i - mu_ibar))
+        unroll<NP>([&](auto P) {
+            constexpr int pp = decltype(P)::value;
+            constexpr int i = DER<L>.pi[pp];
+            const double t = 3.0 * L::W[i] * p.rho0_d * (double)dmu[pp];
+#pragma unroll
+            for (int al = 0; al < D; ++al)
+                if (L::E[i][al] != 0) acc[al] += L::E[i][al] * t;
         });
-        if (a.want_ds) {
+        if constexpr (WANT_DS) {
+            // dJ/ds_k -= (M mu)_k (M (f - f^eq))_k / |M_k|^2
+            T m[Q];
+            moments_of<L, T>(f[0], sp, dp, m);
+            subtract_equilibrium<L, T>(m, rho, j, p.inv_rho0);
             unroll<Q>([&](auto K) {
-                constexpr int k = decltype(K)::value;
-                if constexpr (!L::conserved(k))
-                    acc[D + k] -= (double)qm[k] * (double)mneq[k] / (double)TAB<L>.norm[k];
+                constexpr int kk = decltype(K)::value;
+                if constexpr (!L::conserved(kk))
+                    acc[D + kk] -= (double)qm[kk] * (double)m[kk] / (double)TAB<L>.norm[kk];
             });
         }
-        T v[Q];
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            T s = 0;
-            unroll<Q>([&](auto K) {
-                constexpr int k = decltype(K)::value;
-                if constexpr (!L::conserved(k)) macc<TAB<L>.M[k][i]>(s, qm[k] * p.rate[k]);
-            });
-            v[i] = s;
-        });
-        // J^T v = a_s + b.e_j
-        T as = 0, bx = 0, by = 0, bz = 0;
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const T wv = T(L::W[i]) * v[i];
-            as += wv;
-            T eu = 0;
-            macc<L::E[i][0]>(eu, mac.u[0]);
-            macc<L::E[i][1]>(eu, mac.u[1]);
-            macc<L::E[i][2]>(eu, mac.u[2]);
-            const T c = T(3) + T(9) * eu;
-            macc<L::E[i][0]>(bx, c * wv);
-            macc<L::E[i][1]>(by, c * wv);
-            macc<L::E[i][2]>(bz, c * wv);
-        });
-        bx -= T(3) * mac.u[0] * as;
-        by -= T(3) * mac.u[1] * as;
-        bz -= T(3) * mac.u[2] * as;
-        const T wux = (T)a.w_ux;
-        unroll<Q>([&](auto J) {
-            constexpr int j = decltype(J)::value;
-            T jt = as;
-            macc<L::E[j][0]>(jt, bx);
-            macc<L::E[j][1]>(jt, by);
-            macc<L::E[j][2]>(jt, bz);
-            T out = mu[j] - v[j] + jt + dir[j];
-            if (a.obj_kind == 2) macc<L::E[j][0]>(out, wux);
-            lam_out[(size_t)j * g.N + pos.n] = out;
-        });
     }
 
     // b is uniform over the block, so the barrier inside is block-uniform
-    uint32_t b = blockIdx.x;
-    if (g.chunk) b = (b % NXCD) * g.chunk + b / NXCD;
-    if (b < g.nblocks) block_accumulate<NC>(acc, gglob + (size_t)b * NC);
+    uint32_t blk = blockIdx.x;
+    if (g.chunk) blk = (blk % NXCD) * g.chunk + blk / NXCD;
+    if (blk < g.nblocks) block_accumulate<NR>(acc, gglob + (size_t)blk * NC);
+}
+
+// Eq. (211) links k = (x_f, i) with a deferred c1: the link value is
+// f_i(x_f, t+1) = (terms at t) + c1 f_ibar(x_f, t+1), so its adjoint a_k also
+// reaches f_ibar(x_f, t+1) (whose own adjoint the node x_f + e_i gathers in
+// the next kernel) and dJ/dgamma gets a_k dc1 f_ibar(x_f, t+1).
+template <class L, class T, int XB>
+__global__ void __launch_bounds__(BX)
+k_two_node_pre(const T* __restrict__ A_next, T* __restrict__ lam_in,
+               const int32_t* __restrict__ lknode, const uint8_t* __restrict__ lkdir,
+               const int32_t* __restrict__ lktag, const double* __restrict__ c1d,
+               const double* __restrict__ d1d, double* __restrict__ gq,
+               uint32_t n_links, Grid g, Params<L, T> p, AdjArgs a) {
+    const uint32_t k = blockIdx.x * BX + threadIdx.x;
+    if (k >= n_links) return;
+    const double c = c1d[k];
+    if (c == 0.0) return;
+    const int i = lkdir[k];
+    const uint32_t n = (uint32_t)lknode[k];
+    int ib = 0, ex = 0;
+    unroll<L::Q>([&](auto I) {
+        constexpr int ii = decltype(I)::value;
+        if (ii == i) {
+            ib = TAB<L>.opp[ii];
+            ex = L::E[ii][0];
+        }
+    });
+    double ak = (double)lam_in[(size_t)i * g.S + n];
+    if (a.obj_kind == 1 && ex != 0 && lktag[k] == a.obj_tag) ak += -(double)ex * a.w_force;
+    T* dst = lam_in + (size_t)ib * g.S + n;
+    *dst = (T)((double)*dst + c * ak);
+    gq[k] += ak * d1d[k] * (double)pull_one<L, T, XB>(A_next, g, p, n, ib);
 }
 
 template <class L, class T>
 __global__ void __launch_bounds__(BX)
 k_adjoint_out(const T* __restrict__ lam, const int32_t* __restrict__ nodeword,
-              uint32_t N, double* __restrict__ out) {
+              uint32_t N, uint32_t S, double* __restrict__ out) {
     const uint32_t n = blockIdx.x * BX + threadIdx.x;
     if (n >= N) return;
     const bool fluid = nodeword[n] >= 0;
     for (int i = 0; i < L::Q; ++i)
-        out[(size_t)i * N + n] = fluid ? (double)lam[(size_t)i * N + n] : 0.0;
+        out[(size_t)i * N + n] = fluid ? (double)lam[(size_t)i * S + n] : 0.0;
 }
 
 // ----------------------------------------------------------------------------
@@ -298,6 +319,7 @@ static Params<L, T> adj_params(const Engine& e) {
     p.inv_rho0 = (T)(1.0 / e.rho0);
     p.c0 = 1.0 - e.b;
     p.rho0_d = e.rho0;
+    p.c1d = e.two_node ? e.d_lkc1d : nullptr;
     return p;
 }
 
@@ -307,9 +329,10 @@ static Grid adj_grid(const Engine& e) {
     g.ny = (uint32_t)e.ny;
     g.nz = (uint32_t)e.nz;
     g.N = (uint32_t)e.N;
+    g.S = (uint32_t)e.S;
     g.bpr = (uint32_t)((e.nx + BX - 1) / BX);
     g.nblocks = g.bpr * g.ny * g.nz;
-    g.chunk = (g.nblocks + NXCD - 1) / NXCD;
+    g.chunk = e.xcd_remap ? (g.nblocks + NXCD - 1) / NXCD : 0;
     return g;
 }
 
@@ -337,16 +360,40 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const void* lam_i
     a.obj_tag = obj.tag;
     a.w_force = obj.kind == 1 ? obj.weight : 0.0;
     a.w_ux = obj.kind == 2 ? obj.weight * obj.inv_nfluid / e.rho0 : 0.0;
-    a.want_ds = 1;
+    a.want_ds = e.want_ds ? 1 : 0;
     return adj_dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        hipLaunchKernelGGL((k_adjoint<L, T, XB>), dim3(g.chunk * NXCD), dim3(BX), 0,
+        auto kern = a.want_ds ? k_adjoint<L, T, XB, true> : k_adjoint<L, T, XB, false>;
+        hipLaunchKernelGGL(kern, dim3(g.chunk ? g.chunk * NXCD : g.nblocks), dim3(BX), 0,
                            e.stream, (const T*)fwd.f, (const T*)fwd.wa,
                            (const T*)lam_in, (T*)lam_out, e.d_nodeword, e.d_lkdir,
                            e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag, e.d_gq,
                            e.d_gphi, e.d_gglob, g, adj_params<L, T>(e), a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in,
+                                   const AdjointObjective& obj) {
+    if (e.n_links == 0) return hipSuccess;
+    const Grid g = adj_grid(e);
+    AdjArgs a;
+    a.obj_kind = obj.kind;
+    a.obj_tag = obj.tag;
+    a.w_force = obj.kind == 1 ? obj.weight : 0.0;
+    a.w_ux = 0.0;
+    a.want_ds = 0;
+    const unsigned nb = (unsigned)((e.n_links + BX - 1) / BX);
+    return adj_dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_two_node_pre<L, T, XB>), dim3(nb), dim3(BX), 0, e.stream,
+                           (const T*)next.f, (T*)lam_in, e.d_lknode, e.d_lkdir, e.d_lktag,
+                           e.d_lkc1d, e.d_lkd1d, e.d_gq, (uint32_t)e.n_links, g,
+                           adj_params<L, T>(e), a);
         return hipGetLastError();
     });
 }
@@ -357,7 +404,7 @@ hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out) {
         using L = decltype(lat);
         using T = decltype(prec);
         hipLaunchKernelGGL((k_adjoint_out<L, T>), dim3(nb), dim3(BX), 0, e.stream,
-                           (const T*)lam, e.d_nodeword, (uint32_t)e.N, out);
+                           (const T*)lam, e.d_nodeword, (uint32_t)e.N, (uint32_t)e.S, out);
         return hipGetLastError();
     });
 }

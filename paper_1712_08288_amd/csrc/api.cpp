@@ -24,6 +24,8 @@ struct lbm {
 
 namespace {
 
+constexpr int64_t kDefaultPadBytes = 0;
+
 int fail(lbm_t* h, int code, const std::string& msg) {
     if (h) h->e.err = msg;
     return code;
@@ -89,7 +91,19 @@ void free_snap(Snapshot& s) {
     s.f = s.wa = nullptr;
 }
 
-size_t f_bytes(const Engine& e) { return (size_t)e.Q * (size_t)e.N * e.elem; }
+size_t f_bytes(const Engine& e) { return (size_t)e.Q * (size_t)e.S * e.elem; }
+
+// Stride between direction planes.  Planes whose byte size is a multiple of
+// a large power of two would start the Q concurrent streams of a pull at the
+// same offset modulo the memory channel interleave; a pad of a few cache
+// lines staggers them.  LBM_PLANE_PAD (values) overrides the default.
+int64_t plane_stride(int64_t N, size_t elem) {
+    int64_t pad = -1;
+    if (const char* v = std::getenv("LBM_PLANE_PAD")) pad = std::atoll(v);
+    if (pad < 0) pad = (int64_t)(kDefaultPadBytes / elem);
+    int64_t S = ((N + 63) / 64) * 64 + pad;
+    return S;
+}
 size_t wa_bytes(const Engine& e) {
     return (size_t)std::max<int64_t>(e.n_links, 1) * e.elem;
 }
@@ -164,12 +178,15 @@ int64_t pull_source(const Engine& e, int64_t x, int64_t y, int64_t z, int i) {
 // Coefficients of Eq. (213) for every (sorted) link, and their gamma
 // derivatives along l = l(gamma).
 int compute_coefficients(lbm_t* h, std::vector<lbe::LinkCoef>& coef,
-                         std::vector<lbe::LinkDeriv>& der, std::vector<double>& c4v) {
+                         std::vector<lbe::LinkDeriv>& der, std::vector<double>& c4v,
+                         std::vector<double>& c1d, std::vector<double>& d1d) {
     Engine& e = h->e;
     const int64_t L = e.n_links;
     coef.resize(L);
     der.resize(L);
     c4v.resize(L);
+    c1d.resize(L);
+    d1d.resize(L);
     const double b = e.b;
     for (int64_t k = 0; k < L; ++k) {
         const double g = e.q_h[k];
@@ -189,13 +206,18 @@ int compute_coefficients(lbm_t* h, std::vector<lbe::LinkCoef>& coef,
         double ephi = 0.0;
         for (int a = 0; a < e.D; ++a) ephi += lat_e(e.lattice, i, a) * e.wall_u_h[k * e.D + a];
         const double unit = 3.0 * lat_w(e.lattice, i) * e.rho0 * ephi;
-        coef[k] = {c1, c2, c3, c4 * unit};
         const double den2 = den * den;
         const double d1 = b * ((lp - 2.0) * den - (1.0 + l - 2.0 * g) * lp) / den2;
         const double d2 = b * lp / den2;
         const double d3 = b * ((2.0 - lp) * den - (2.0 * g - l) * lp) / den2;
         const double d4 = -2.0 * b * lp / den2;
-        der[k] = {d1, d2, d3, d4 * unit};
+        // Eq. (211): the c1 term multiplies f_ibar(x_f, t+1) = f'_ibar(x_f + e_i, t)
+        // and is added at the next pull, unless x_f + e_i is solid
+        const bool defer = e.two_node && !e.ibar_is_link[k];
+        coef[k] = {defer ? 0.0 : c1, c2, c3, c4 * unit};
+        der[k] = {defer ? 0.0 : d1, d2, d3, d4 * unit};
+        c1d[k] = defer ? c1 : 0.0;
+        d1d[k] = defer ? d1 : 0.0;
         c4v[k] = c4;
     }
     return LBM_OK;
@@ -205,12 +227,14 @@ int upload_coefficients(lbm_t* h) {
     Engine& e = h->e;
     std::vector<lbe::LinkCoef> coef;
     std::vector<lbe::LinkDeriv> der;
-    std::vector<double> c4v;
-    int rc = compute_coefficients(h, coef, der, c4v);
+    std::vector<double> c4v, c1d, d1d;
+    int rc = compute_coefficients(h, coef, der, c4v, c1d, d1d);
     if (rc) return rc;
     if ((rc = upload(h, e.d_lkcoef, coef.data(), coef.size()))) return rc;
     if ((rc = upload(h, e.d_lkderiv, der.data(), der.size()))) return rc;
     if ((rc = upload(h, e.d_lkc4, c4v.data(), c4v.size()))) return rc;
+    if ((rc = upload(h, e.d_lkc1d, c1d.data(), c1d.size()))) return rc;
+    if ((rc = upload(h, e.d_lkd1d, d1d.data(), d1d.size()))) return rc;
     return sync(h);
 }
 
@@ -267,6 +291,8 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
     if (nx > 65535 * 256LL || ny > (1LL << 31) || nz > (1LL << 31)) return LBM_EINVAL;
     const int64_t N = nx * ny * nz;
     if (N >= (1LL << 31)) return LBM_EINVAL;
+    // one direction plane must stay below 4 GiB (32-bit byte offsets)
+    if (N * (precision == LBM_FP64 ? 8 : 4) >= (1LL << 32)) return LBM_EINVAL;
     if (!s || !(rho0 > 0.0) || !std::isfinite(rho0)) return LBM_EINVAL;
     const int Q = lat_Q(lattice), D = lat_D(lattice);
     for (int k = 0; k < Q; ++k) {
@@ -289,6 +315,12 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
     e.nz = nz;
     e.N = N;
     e.elem = precision == LBM_FP64 ? 8 : 4;
+    e.S = plane_stride(N, e.elem);
+    if (e.S * (int64_t)e.elem >= (1LL << 32)) {
+        delete h;
+        return LBM_EINVAL;
+    }
+    if (const char* v = std::getenv("LBM_XCD_REMAP")) e.xcd_remap = std::atoi(v) != 0;
     for (int k = 0; k < Q; ++k) e.s[k] = s[k];
     e.rho0 = rho0;
     for (int a = 0; a < 3; ++a) e.g[a] = (g && a < D) ? g[a] : 0.0;
@@ -324,6 +356,13 @@ int lbm_set_scheme(lbm_t* h, int l_rule, double b) {
     if (h->e.has_geometry) return fail(h, LBM_ESTATE, "set the scheme before the geometry");
     h->e.l_rule = l_rule;
     h->e.b = b;
+    return LBM_OK;
+}
+
+int lbm_set_two_node(lbm_t* h, int on) {
+    if (!h) return LBM_EINVAL;
+    if (h->e.has_geometry) return fail(h, LBM_ESTATE, "choose the variant before the geometry");
+    h->e.two_node = on != 0;
     return LBM_OK;
 }
 
@@ -416,6 +455,17 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         max_tag = std::max(max_tag, e.tag_h[k]);
     }
     e.n_tags = max_tag + 1;
+    e.ibar_is_link.assign(n_links, 0);
+    for (int64_t k = 0; k < n_links; ++k) {
+        const int i = e.lk_dir_h[k];
+        int ib = 0;
+        for (int j = 0; j < Q; ++j) {
+            bool opp = true;
+            for (int a = 0; a < D; ++a) opp = opp && lat_e(e.lattice, j, a) == -lat_e(e.lattice, i, a);
+            if (opp) ib = j;
+        }
+        e.ibar_is_link[k] = (mask[e.lk_node_h[k]] >> ib) & 1u;
+    }
     // node words: -1 solid, else (link count << 26) | first link
     std::vector<int32_t> nw(N);
     {
@@ -806,7 +856,10 @@ int lbm_adjoint(lbm_t* h) {
             ao.weight = in_w ? 1.0 / (double)(e.obj_t1 - e.obj_t0) : 0.0;
             ao.inv_nfluid = e.n_fluid ? 1.0 / (double)e.n_fluid : 0.0;
             if (!in_w) ao.kind = LBM_OBJ_NONE;
-            hipError_t st = lbe::launch_adjoint_step(e, e.pool[r], e.lam[lc], e.lam[lc ^ 1], ao);
+            hipError_t st = hipSuccess;
+            if (e.two_node) st = lbe::launch_two_node_adjoint(e, e.pool[r + 1], e.lam[lc], ao);
+            if (st == hipSuccess)
+                st = lbe::launch_adjoint_step(e, e.pool[r], e.lam[lc], e.lam[lc ^ 1], ao);
             if (st != hipSuccess) {
                 e.t = t_saved;
                 return fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));
@@ -818,6 +871,12 @@ int lbm_adjoint(lbm_t* h) {
     // lambda(run_t0) now in lam[lc]; keep it in lam[0]
     if (lc != 0) std::swap(e.lam[0], e.lam[1]);
     e.have_grad = true;
+    return LBM_OK;
+}
+
+int lbm_set_rate_gradient(lbm_t* h, int on) {
+    if (!h) return LBM_EINVAL;
+    h->e.want_ds = on != 0;
     return LBM_OK;
 }
 
@@ -931,6 +990,8 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_lkcoef);
     free_dev(e.d_lkderiv);
     free_dev(e.d_lkc4);
+    free_dev(e.d_lkc1d);
+    free_dev(e.d_lkd1d);
     free_dev(e.d_obj_acc);
     free_dev(e.d_gq);
     free_dev(e.d_gphi);

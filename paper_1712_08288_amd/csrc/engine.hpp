@@ -27,6 +27,8 @@ struct Engine {
     // configuration
     int lattice = 0, precision = 0, Q = 0, D = 0;
     int64_t nx = 0, ny = 0, nz = 0, N = 0;
+    int64_t S = 0;           // stride (values) between direction planes, >= N
+    bool xcd_remap = false;  // deal contiguous row slabs to each XCD (measured slower)
     double s[19] = {0};
     double rho0 = 1.0;
     double g[3] = {0, 0, 0};
@@ -53,6 +55,10 @@ struct Engine {
     LinkCoef* d_lkcoef = nullptr;
     LinkDeriv* d_lkderiv = nullptr;
     double* d_lkc4 = nullptr;           // c4 per link (for dJ/dphi)
+    bool two_node = false;              // Eq. (211) instead of Eq. (210)
+    std::vector<uint8_t> ibar_is_link;  // sorted link k: (x_f, ibar) is a link too
+    double* d_lkc1d = nullptr;          // c1 applied at the next pull (Eq. (211)), else 0
+    double* d_lkd1d = nullptr;          // its gamma derivative
 
     // state: post-collision array A and link slots of the current time
     Snapshot buf[2];
@@ -78,6 +84,7 @@ struct Engine {
     double* d_gglob = nullptr;          // per-block partials of dJ/dg (D) and dJ/ds (Q)
     int64_t gglob_len = 0;
     bool have_grad = false;
+    bool want_ds = true;                // accumulate dJ/ds in the adjoint
 
     // scratch for reductions and host transfers
     double* d_scratch = nullptr;
@@ -135,5 +142,10 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd,
                                const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
+// Eq. (211) links: move c1 * (adjoint of f_i(x_f, t+1)) onto the adjoint of
+// f_ibar(x_f, t+1) and add the gamma-derivative of that term, using the
+// forward state at t+1 in `next`.
+hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in,
+                                   const AdjointObjective& obj);
 
 }  // namespace lbe

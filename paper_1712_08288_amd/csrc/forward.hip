@@ -39,15 +39,16 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         ux_local = (double)mac.u[0];
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            __builtin_nontemporal_store(f[i], &B[(size_t)i * g.N + pos.n]);
+            st_nt(B + (size_t)i * g.S, pos.n, f[i]);
         });
         if (nl.mask) {
+            uint32_t k = nl.base;
             unroll<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 constexpr int ib = TAB<L>.opp[i];
                 if constexpr (i > 0) {
-                    if ((nl.mask >> i) & 1u) {
-                        const uint32_t k = link_index(nl, i);
+                    const uint32_t bit = (nl.mask >> i) & 1u;
+                    if (bit) {
                         const LinkCoef c = lkcoef[k];
                         const double v = p.c0 * (double)fpre_link[i] +
                                          c.c1 * (double)fpre_link[ib] +
@@ -55,6 +56,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
                                          c.wall;
                         waB[k] = (T)v;
                     }
+                    k += bit;
                 }
             });
         }
@@ -103,7 +105,10 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if (i > 0 && ((nl.mask >> i) & 1u)) {
-            wa[link_index(nl, i)] = (T)f[i];
+            const uint32_t k = link_index(nl, i);
+            // Eq. (211): the first pull adds c1 f_ibar(x_f, 0) to the slot
+            const double c = p.c1d ? p.c1d[k] : 0.0;
+            wa[k] = (T)(f[i] - c * f[TAB<L>.opp[i]]);
             return;
         }
         // the outlet column's -x populations share their slot with the pull
@@ -116,7 +121,7 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
             if (sg > 0) v -= p.seam[i];
             else if (sg < 0) v += p.seam[i];
         }
-        A[(size_t)i * g.N + pl.template src<L, i>()] = v;
+        A[(size_t)i * g.S + pl.template src<L, i>()] = v;
     });
 }
 
@@ -197,13 +202,32 @@ k_mass(const T* __restrict__ A, const T* __restrict__ wa,
 }
 
 // momentum exchange of the last step on each link; `post` holds f'(t-1) at
-// every node and the link slots f_i(x_f, t)
-template <class L, class T>
+// every node and the link slots of f_i(x_f, t)
+template <class L, class T, int XB>
+__device__ __forceinline__ double link_value(const T* __restrict__ B, const T* __restrict__ wa,
+                                             const Grid& g, const Params<L, T>& p,
+                                             uint32_t k, uint32_t n, int i) {
+    double v = (double)wa[k];
+    if (p.c1d) {
+        const double c = p.c1d[k];
+        if (c != 0.0) {
+            int ib = 0;
+            unroll<L::Q>([&](auto I) {
+                constexpr int ii = decltype(I)::value;
+                if (ii == i) ib = TAB<L>.opp[ii];
+            });
+            v = (double)(T)(v + c * (double)pull_one<L, T, XB>(B, g, p, n, ib));
+        }
+    }
+    return v;
+}
+
+template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
 k_force(const T* __restrict__ B, const T* __restrict__ wa,
         const int32_t* __restrict__ lknode, const uint8_t* __restrict__ lkdir,
-        const int32_t* __restrict__ lktag, uint32_t n_links, uint32_t N,
-        int n_tags, double rho0, double* __restrict__ partials) {
+        const int32_t* __restrict__ lktag, uint32_t n_links, Grid g, Params<L, T> p,
+        int n_tags, double* __restrict__ partials) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     double fx = 0, fy = 0, fz = 0;
     int tag = -1;
@@ -217,7 +241,7 @@ k_force(const T* __restrict__ B, const T* __restrict__ wa,
             constexpr int ii = decltype(I)::value;
             if (ii == i) {
                 constexpr int ib = TAB<L>.opp[ii];
-                fp_ib = (double)B[(size_t)ib * N + n];
+                fp_ib = (double)B[(size_t)ib * g.S + n];
                 wi = L::W[ii];
                 ex = L::E[ii][0];
                 ey = L::E[ii][1];
@@ -225,7 +249,7 @@ k_force(const T* __restrict__ B, const T* __restrict__ wa,
             }
         });
         // absolute values: f = delta f + w rho0 (w_i = w_ibar)
-        const double v = fp_ib + (double)wa[k] + 2.0 * wi * rho0;
+        const double v = fp_ib + link_value<L, T, XB>(B, wa, g, p, k, n, i) + 2.0 * wi * p.rho0_d;
         fx = -ex * v;
         fy = -ey * v;
         fz = -ez * v;
@@ -241,12 +265,12 @@ k_force(const T* __restrict__ B, const T* __restrict__ wa,
     }
 }
 
-template <class L, class T>
+template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
 k_force_obj(const T* __restrict__ B, const T* __restrict__ wa,
             const int32_t* __restrict__ lknode, const uint8_t* __restrict__ lkdir,
-            const int32_t* __restrict__ lktag, uint32_t n_links, uint32_t N,
-            int tag, double rho0, double weight, double* __restrict__ acc) {
+            const int32_t* __restrict__ lktag, uint32_t n_links, Grid g, Params<L, T> p,
+            int tag, double weight, double* __restrict__ acc) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     double fx = 0;
     if (k < n_links && lktag[k] == tag) {
@@ -257,8 +281,9 @@ k_force_obj(const T* __restrict__ B, const T* __restrict__ wa,
             if constexpr (L::E[ii][0] != 0) {
                 if (ii == i) {
                     constexpr int ib = TAB<L>.opp[ii];
-                    const double v = (double)B[(size_t)ib * N + n] + (double)wa[k] +
-                                     2.0 * L::W[ii] * rho0;
+                    const double v = (double)B[(size_t)ib * g.S + n] +
+                                     link_value<L, T, XB>(B, wa, g, p, k, n, ii) +
+                                     2.0 * L::W[ii] * p.rho0_d;
                     fx = -L::E[ii][0] * v;
                 }
             }
@@ -289,13 +314,14 @@ static Grid make_grid(const Engine& e) {
     g.ny = (uint32_t)e.ny;
     g.nz = (uint32_t)e.nz;
     g.N = (uint32_t)e.N;
+    g.S = (uint32_t)e.S;
     g.bpr = (uint32_t)((e.nx + BX - 1) / BX);
     g.nblocks = g.bpr * g.ny * g.nz;
-    g.chunk = (g.nblocks + NXCD - 1) / NXCD;
+    g.chunk = e.xcd_remap ? (g.nblocks + NXCD - 1) / NXCD : 0;
     return g;
 }
 
-static unsigned launch_blocks(const Grid& g) {
+unsigned launch_blocks(const Grid& g) {
     return g.chunk ? g.chunk * NXCD : g.nblocks;
 }
 
@@ -319,6 +345,7 @@ static Params<L, T> make_params(const Engine& e) {
     p.inv_rho0 = (T)(1.0 / e.rho0);
     p.c0 = 1.0 - e.b;
     p.rho0_d = e.rho0;
+    p.c1d = e.two_node ? e.d_lkc1d : nullptr;
     return p;
 }
 
@@ -402,13 +429,15 @@ hipError_t launch_force(Engine& e, const Snapshot& post, double* partials,
     const int64_t nb = link_blocks(e);
     *nblocks = nb;
     if (nb == 0) return hipSuccess;
-    return dispatch(e, [&](auto lat, auto prec, auto) -> hipError_t {
+    const Grid g = make_grid(e);
+    return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);
         using T = decltype(prec);
-        hipLaunchKernelGGL((k_force<L, T>), dim3((unsigned)nb), dim3(BX), 0, e.stream,
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_force<L, T, XB>), dim3((unsigned)nb), dim3(BX), 0, e.stream,
                            (const T*)post.f, (const T*)post.wa, e.d_lknode, e.d_lkdir,
-                           e.d_lktag, (uint32_t)e.n_links, (uint32_t)e.N, e.n_tags,
-                           e.rho0, partials);
+                           e.d_lktag, (uint32_t)e.n_links, g, make_params<L, T>(e),
+                           e.n_tags, partials);
         return hipGetLastError();
     });
 }
@@ -417,13 +446,15 @@ hipError_t launch_force_objective(Engine& e, const Snapshot& post, double* acc,
                                   int tag, double weight) {
     const int64_t nb = link_blocks(e);
     if (nb == 0) return hipSuccess;
-    return dispatch(e, [&](auto lat, auto prec, auto) -> hipError_t {
+    const Grid g = make_grid(e);
+    return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);
         using T = decltype(prec);
-        hipLaunchKernelGGL((k_force_obj<L, T>), dim3((unsigned)nb), dim3(BX), 0,
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_force_obj<L, T, XB>), dim3((unsigned)nb), dim3(BX), 0,
                            e.stream, (const T*)post.f, (const T*)post.wa, e.d_lknode,
-                           e.d_lkdir, e.d_lktag, (uint32_t)e.n_links, (uint32_t)e.N,
-                           tag, e.rho0, weight, acc);
+                           e.d_lkdir, e.d_lktag, (uint32_t)e.n_links, g,
+                           make_params<L, T>(e), tag, weight, acc);
         return hipGetLastError();
     });
 }

@@ -22,6 +22,7 @@ enum XBC : int { XBC_PERIODIC = 0, XBC_PRESSURE = 1, XBC_OUTFLOW = 2 };
 struct Grid {
     uint32_t nx, ny, nz;
     uint32_t N;          // nx*ny*nz
+    uint32_t S;          // stride between direction planes of device arrays (>= N)
     uint32_t bpr;        // blocks per row
     uint32_t nblocks;    // logical blocks = bpr*ny*nz
     uint32_t chunk;      // ceil(nblocks / NXCD) when remapping, else 0
@@ -94,6 +95,7 @@ struct Params {
     T rho0, inv_rho0;
     double c0;        // 1 - b of Eq. (213)
     double rho0_d;
+    const double* c1d;  // Eq. (211): per-link c1 added at the pull, or null
 };
 
 // Signed accumulate with a compile-time integer coefficient.
@@ -141,38 +143,160 @@ __device__ __forceinline__ T feq(const Macro<L, T>& m, T rho0) {
     return T(L::W[I]) * (m.rho + rho0 * poly);
 }
 
-// MRT collision of the Appendix plus forcing, in place:
-// f <- f - M^{-1} S M (f - f^eq) + F with M^{-1} = M^T diag(1/|M_k|^2).
+// ---- the MRT transform in even/odd pair form (see Derived<L>) -------------
+template <class L>
+constexpr int NPAIR = (L::Q - 1) / 2;
+
 template <class L, class T>
-__device__ __forceinline__ void collide(T (&f)[L::Q], const Params<L, T>& p,
-                                        Macro<L, T>& mac) {
-    mac = moments<L, T>(f, p.inv_rho0);
-    T d[L::Q];
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        d[i] = f[i] - feq<L, T, i>(mac, p.rho0);
+__device__ __forceinline__ void pair_split(const T (&x)[L::Q], T (&sp)[NPAIR<L>],
+                                           T (&dp)[NPAIR<L>]) {
+    unroll<NPAIR<L>>([&](auto P) {
+        constexpr int pp = decltype(P)::value;
+        constexpr int i = DER<L>.pi[pp];
+        constexpr int ib = TAB<L>.opp[i];
+        sp[pp] = x[i] + x[ib];
+        dp[pp] = x[i] - x[ib];
     });
-    T m[L::Q];
+}
+
+// (M x)_k for the non-conserved rows from the pair form of x
+template <class L, class T>
+__device__ __forceinline__ void moments_of(T x0, const T (&sp)[NPAIR<L>],
+                                           const T (&dp)[NPAIR<L>], T (&m)[L::Q]) {
+    unroll<L::Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        T acc = 0;
+        if constexpr (!L::conserved(k)) {
+            if constexpr (DER<L>.even[k]) {
+                macc<TAB<L>.M[k][0]>(acc, x0);
+                unroll<NPAIR<L>>([&](auto P) {
+                    constexpr int pp = decltype(P)::value;
+                    macc<TAB<L>.M[k][DER<L>.pi[pp]]>(acc, sp[pp]);
+                });
+            } else {
+                unroll<NPAIR<L>>([&](auto P) {
+                    constexpr int pp = decltype(P)::value;
+                    macc<TAB<L>.M[k][DER<L>.pi[pp]]>(acc, dp[pp]);
+                });
+            }
+        }
+        m[k] = acc;
+    });
+}
+
+// density deviation and momentum sum_i e_i x_i from the pair form
+template <class L, class T>
+__device__ __forceinline__ void conserved_of(T x0, const T (&sp)[NPAIR<L>],
+                                             const T (&dp)[NPAIR<L>], T& rho, T (&j)[3]) {
+    rho = x0;
+    j[0] = j[1] = j[2] = 0;
+    unroll<NPAIR<L>>([&](auto P) {
+        constexpr int pp = decltype(P)::value;
+        constexpr int i = DER<L>.pi[pp];
+        rho += sp[pp];
+        macc<L::E[i][0]>(j[0], dp[pp]);
+        macc<L::E[i][1]>(j[1], dp[pp]);
+        macc<L::E[i][2]>(j[2], dp[pp]);
+    });
+}
+
+// m_k -= m^eq_k(drho, j) for the non-conserved rows (projection of Eq. (42))
+template <class L, class T>
+__device__ __forceinline__ void subtract_equilibrium(T (&m)[L::Q], T rho, const T (&j)[3],
+                                                     T inv_rho0) {
+    const T u[3] = {j[0] * inv_rho0, j[1] * inv_rho0, j[2] * inv_rho0};
+    const T jj[6] = {j[0] * u[0], j[1] * u[1], j[2] * u[2],
+                     j[0] * u[1], j[1] * u[2], j[0] * u[2]};
     unroll<L::Q>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if constexpr (!L::conserved(k)) {
-            T acc = 0;
-            unroll<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                macc<TAB<L>.M[k][i]>(acc, d[i]);
+            if constexpr (DER<L>.A[k] != 0.0) m[k] -= T(DER<L>.A[k]) * rho;
+            unroll<3>([&](auto X) {
+                constexpr int x = decltype(X)::value;
+                if constexpr (DER<L>.B[k][x] != 0.0) m[k] -= T(DER<L>.B[k][x]) * j[x];
             });
-            m[k] = acc * p.rate[k];
+            unroll<6>([&](auto C) {
+                constexpr int c = decltype(C)::value;
+                if constexpr (DER<L>.C[k][c] != 0.0) m[k] -= T(DER<L>.C[k][c]) * jj[c];
+            });
         }
     });
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        T acc = 0;
+}
+
+// y = M^T r over the non-conserved rows, in pair form:
+// y_0 = e0, y_i = ev_p + od_p, y_ibar = ev_p - od_p
+template <class L, class T>
+__device__ __forceinline__ void back_transform(const T (&r)[L::Q], T& e0,
+                                               T (&ev)[NPAIR<L>], T (&od)[NPAIR<L>]) {
+    e0 = 0;
+    unroll<L::Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (!L::conserved(k) && DER<L>.even[k]) macc<TAB<L>.M[k][0]>(e0, r[k]);
+    });
+    unroll<NPAIR<L>>([&](auto P) {
+        constexpr int pp = decltype(P)::value;
+        constexpr int i = DER<L>.pi[pp];
+        T a = 0, b = 0;
         unroll<L::Q>([&](auto K) {
             constexpr int k = decltype(K)::value;
-            if constexpr (!L::conserved(k)) macc<TAB<L>.M[k][i]>(acc, m[k]);
+            if constexpr (!L::conserved(k)) {
+                if constexpr (DER<L>.even[k]) macc<TAB<L>.M[k][i]>(a, r[k]);
+                else macc<TAB<L>.M[k][i]>(b, r[k]);
+            }
         });
-        f[i] = f[i] - acc + p.force[i];
+        ev[pp] = a;
+        od[pp] = b;
     });
+}
+
+// MRT collision of the Appendix plus forcing, in place:
+// f <- f - M^{-1} S (M f - m^eq) + F with M^{-1} = M^T diag(1/|M_k|^2)
+// (the rates arrive already divided by |M_k|^2).  m^eq is the projection of
+// Eq. (42), so M f - m^eq = M (f - f^eq) exactly in real arithmetic.
+// Optionally returns the non-equilibrium moments (M (f - f^eq))_k.
+template <class L, class T, bool KEEP_NEQ = false>
+__device__ __forceinline__ void collide(T (&f)[L::Q], const Params<L, T>& p,
+                                        Macro<L, T>& mac, T* neq = nullptr) {
+    constexpr int NP = NPAIR<L>;
+    T sp[NP], dp[NP];
+    pair_split<L, T>(f, sp, dp);
+    T rho, j[3];
+    conserved_of<L, T>(f[0], sp, dp, rho, j);
+    mac.rho = rho;
+    mac.u[0] = j[0] * p.inv_rho0;
+    mac.u[1] = j[1] * p.inv_rho0;
+    mac.u[2] = j[2] * p.inv_rho0;
+    T r[L::Q];
+    moments_of<L, T>(f[0], sp, dp, r);
+    subtract_equilibrium<L, T>(r, rho, j, p.inv_rho0);
+    unroll<L::Q>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (KEEP_NEQ) neq[k] = r[k];
+        r[k] *= p.rate[k];
+    });
+    T e0, ev[NP], od[NP];
+    back_transform<L, T>(r, e0, ev, od);
+    f[0] -= e0;
+    unroll<NP>([&](auto P) {
+        constexpr int pp = decltype(P)::value;
+        constexpr int i = DER<L>.pi[pp];
+        constexpr int ib = TAB<L>.opp[i];
+        const T o = od[pp] - p.force[i];    // F_ibar = -F_i
+        f[i] = f[i] - ev[pp] - o;
+        f[ib] = f[ib] - ev[pp] + o;
+    });
+}
+
+// Loads and stores through a uniform plane pointer and a 32-bit byte
+// offset, so the address is a scalar base plus one VGPR (the caller keeps
+// every plane below 4 GiB).
+template <class T>
+__device__ __forceinline__ T ld(const T* __restrict__ plane, uint32_t idx) {
+    return *(const T*)((const char*)plane + idx * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st_nt(T* __restrict__ plane, uint32_t idx, T v) {
+    __builtin_nontemporal_store(v, (T*)((char*)plane + idx * (uint32_t)sizeof(T)));
 }
 
 // ----------------------------------------------------------------------------
@@ -205,7 +329,7 @@ __device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restric
     const Pull<XB> pl(g, pos);
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        f[i] = A[(size_t)i * g.N + pl.template src<L, i>()];
+        f[i] = ld(A + (size_t)i * g.S, pl.template src<L, i>());
         if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
             const int sg = seam_sign<L, i>(pos.ix, g.nx);
             if (sg > 0) f[i] += p.seam[i];
@@ -213,12 +337,68 @@ __device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restric
         }
     });
     if (nl.mask) {
+        // links are sorted by direction: a running index replaces a popcount
+        uint32_t k = nl.base;
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            if constexpr (i > 0)
-                if ((nl.mask >> i) & 1u) f[i] = wa[link_index(nl, i)];
+            if constexpr (i > 0) {
+                const uint32_t bit = (nl.mask >> i) & 1u;
+                if (bit) f[i] = wa[k];
+                k += bit;
+            }
         });
+        if (p.c1d) {
+            // Eq. (211): f_i(x_f, t) gets c1 f_ibar(x_f, t), the value just
+            // advected from x_f + e_i (c1d is zero when that is a link too)
+            uint32_t kk = nl.base;
+            unroll<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                constexpr int ib = TAB<L>.opp[i];
+                if constexpr (i > 0) {
+                    const uint32_t bit = (nl.mask >> i) & 1u;
+                    if (bit) {
+                        const double c = p.c1d[kk];
+                        if (c != 0.0) f[i] = (T)((double)f[i] + c * (double)f[ib]);
+                    }
+                    kk += bit;
+                }
+            });
+        }
     }
+}
+
+// The value f_i(n, t) that a pull of direction i at fluid node n would read
+// from A (no link override); used by link kernels.
+template <class L, class T, int XB>
+__device__ __forceinline__ T pull_one(const T* __restrict__ A, const Grid& g,
+                                      const Params<L, T>& p, uint32_t n, int i) {
+    const uint32_t ix = n % g.nx, r = n / g.nx;
+    const uint32_t iy = r % g.ny, iz = r / g.ny;
+    T out = 0;
+    unroll<L::Q>([&](auto I) {
+        constexpr int ii = decltype(I)::value;
+        if (ii == i) {
+            int sx = (int)ix - L::E[ii][0];
+            int sg = 0;
+            if (XB == XBC_OUTFLOW) {
+                sx = sx < 0 ? 0 : (sx >= (int)g.nx ? (int)g.nx - 1 : sx);
+            } else {
+                if (sx < 0) { sx += g.nx; sg = 1; }
+                else if (sx >= (int)g.nx) { sx -= g.nx; sg = -1; }
+            }
+            int sy = (int)iy - L::E[ii][1];
+            sy = sy < 0 ? sy + (int)g.ny : (sy >= (int)g.ny ? sy - (int)g.ny : sy);
+            int sz = (int)iz - L::E[ii][2];
+            sz = sz < 0 ? sz + (int)g.nz : (sz >= (int)g.nz ? sz - (int)g.nz : sz);
+            const uint32_t src = (uint32_t)sx + g.nx * ((uint32_t)sy + g.ny * (uint32_t)sz);
+            out = A[(size_t)ii * g.S + src];
+            if (XB == XBC_PRESSURE) {
+                if (sg > 0) out += p.seam[ii];
+                else if (sg < 0) out -= p.seam[ii];
+            }
+        }
+    });
+    return out;
 }
 
 // Block-wide sum of one double per thread (all threads must call).

@@ -110,6 +110,71 @@ struct Tables {
 template <class L>
 inline constexpr Tables<L> TAB{};
 
+// Quantities derived from the tables for the symmetric form of the MRT
+// transform.  Velocities come in opposite pairs (i, ibar); every moment row
+// is either even (M_k,ibar = M_k,i) or odd (M_k,ibar = -M_k,i), so with
+// s_p = f_i + f_ibar and d_p = f_i - f_ibar an even row needs only f_0 and
+// the s_p, an odd row only the d_p.  The equilibrium moments are written in
+// closed form, m^eq_k = A_k drho + B_k.j + sum_c C_kc (jj)_c / rho0, where
+// (jj) = (jx^2, jy^2, jz^2, jx jy, jy jz, jx jz), by projecting Eq. (42)
+// onto the rows: A_k = sum_i M_ki w_i, B_ka = 3 sum_i M_ki w_i e_ia and
+// C_kab = 4.5 sum_i M_ki w_i e_ia e_ib - 1.5 delta_ab A_k (doubled for a != b).
+template <class L>
+struct Derived {
+    int npair;
+    int pi[(L::Q - 1) / 2];     // the member i of each pair with i < ibar
+    bool even[L::Q];
+    double A[L::Q];
+    double B[L::Q][3];
+    double C[L::Q][6];
+    constexpr Derived() : npair(0), pi(), even(), A(), B(), C() {
+        const auto& t = TAB<L>;
+        for (int i = 1; i < L::Q; ++i)
+            if (t.opp[i] > i) pi[npair++] = i;
+        for (int k = 0; k < L::Q; ++k) {
+            even[k] = true;
+            for (int i = 0; i < L::Q; ++i)
+                if (t.M[k][t.opp[i]] != t.M[k][i]) even[k] = false;
+            double a = 0, b[3] = {0, 0, 0}, c[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int i = 0; i < L::Q; ++i) {
+                const double mw = t.M[k][i] * L::W[i];
+                a += mw;
+                for (int x = 0; x < 3; ++x) {
+                    b[x] += 3.0 * mw * L::E[i][x];
+                    for (int y = 0; y < 3; ++y) c[x][y] += 4.5 * mw * L::E[i][x] * L::E[i][y];
+                }
+            }
+            A[k] = a;
+            for (int x = 0; x < 3; ++x) B[k][x] = b[x];
+            C[k][0] = c[0][0] - 1.5 * a;
+            C[k][1] = c[1][1] - 1.5 * a;
+            C[k][2] = c[2][2] - 1.5 * a;
+            C[k][3] = 2.0 * c[0][1];
+            C[k][4] = 2.0 * c[1][2];
+            C[k][5] = 2.0 * c[0][2];
+        }
+    }
+};
+
+template <class L>
+inline constexpr Derived<L> DER{};
+
+// every row is even or odd, and the conserved rows are density and momentum
+template <class L>
+constexpr bool rows_have_parity() {
+    for (int k = 0; k < L::Q; ++k) {
+        bool ev = true, od = true;
+        for (int i = 0; i < L::Q; ++i) {
+            if (TAB<L>.M[k][TAB<L>.opp[i]] != TAB<L>.M[k][i]) ev = false;
+            if (TAB<L>.M[k][TAB<L>.opp[i]] != -TAB<L>.M[k][i]) od = false;
+        }
+        if (ev == od) return false;
+    }
+    return DER<L>.npair * 2 + 1 == L::Q;
+}
+static_assert(rows_have_parity<D2Q9>(), "D2Q9 rows must be even or odd");
+static_assert(rows_have_parity<D3Q19>(), "D3Q19 rows must be even or odd");
+
 // Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1.
 template <class F, int... I>
 __host__ __device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, I...>) {

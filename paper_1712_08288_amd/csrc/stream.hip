@@ -1,0 +1,83 @@
+// Streaming copy used as the practical HBM ceiling that the step kernels are
+// compared against (read `bytes`, write `bytes`).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/lbm.h"
+
+namespace lbe {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// mode 0: grid-stride loop, four independent 16-byte loads per thread per
+//         iteration, non-temporal stores
+// mode 1: one 16-byte element per thread, one-shot grid, non-temporal stores
+// mode 2: as mode 1 with ordinary stores
+__global__ void __launch_bounds__(256)
+k_copy_ilp4(const v4f* __restrict__ src, v4f* __restrict__ dst, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const v4f a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                     d = src[i + 3 * stride];
+        __builtin_nontemporal_store(a, &dst[i]);
+        __builtin_nontemporal_store(b, &dst[i + stride]);
+        __builtin_nontemporal_store(c, &dst[i + 2 * stride]);
+        __builtin_nontemporal_store(d, &dst[i + 3 * stride]);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(src[i], &dst[i]);
+}
+
+template <bool NT>
+__global__ void __launch_bounds__(256)
+k_copy_flat(const v4f* __restrict__ src, v4f* __restrict__ dst, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (NT) __builtin_nontemporal_store(src[i], &dst[i]);
+    else dst[i] = src[i];
+}
+
+}  // namespace lbe
+
+extern "C" int lbm_stream_copy(void* dst, const void* src, int64_t bytes, int32_t mode,
+                               int32_t reps, double* ms_per_copy) {
+    if (!dst || !src || bytes <= 0 || bytes % 16 != 0 || reps < 1 || mode < 0 || mode > 2)
+        return LBM_EINVAL;
+    const uint64_t n = (uint64_t)bytes / 16;
+    hipStream_t s;
+    hipEvent_t e0, e1;
+    if (hipStreamCreate(&s) != hipSuccess) return LBM_EDEVICE;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return LBM_EDEVICE;
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+    const unsigned flat_blocks = (unsigned)((n + 255) / 256);
+    const unsigned ilp_blocks = (unsigned)cus * 16u;
+    auto launch = [&]() {
+        if (mode == 0)
+            hipLaunchKernelGGL(lbe::k_copy_ilp4, dim3(ilp_blocks), dim3(256), 0, s,
+                               (const lbe::v4f*)src, (lbe::v4f*)dst, n);
+        else if (mode == 1)
+            hipLaunchKernelGGL(lbe::k_copy_flat<true>, dim3(flat_blocks), dim3(256), 0, s,
+                               (const lbe::v4f*)src, (lbe::v4f*)dst, n);
+        else
+            hipLaunchKernelGGL(lbe::k_copy_flat<false>, dim3(flat_blocks), dim3(256), 0, s,
+                               (const lbe::v4f*)src, (lbe::v4f*)dst, n);
+    };
+    launch();   // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) launch();
+    (void)hipEventRecord(e1, s);
+    int rc = LBM_OK;
+    if (hipEventSynchronize(e1) != hipSuccess) rc = LBM_EDEVICE;
+    float ms = 0.f;
+    if (rc == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LBM_EDEVICE;
+    if (ms_per_copy) *ms_per_copy = ms / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    return rc;
+}

@@ -20,15 +20,15 @@ def rel_l2(a, b, mask=None):
 
 
 def pair(geom, s, steps, precision="fp64", init="deviation", seed=1, amp=1e-3,
-         g=None, dp=0.0, l_rule="min", b=1.0, rho0=1.0, fields=None):
+         g=None, dp=0.0, l_rule="min", b=1.0, rho0=1.0, fields=None, two_node=False):
     """Run `steps` steps on the GPU and on the oracle from the same seeded
     initial state; return (gpu deviations, oracle deviations, fluid mask,
     solver, oracle, oracle state)."""
     from paper_1712_08288_amd import binding
     Q = 9 if geom.lattice == "D2Q9" else 19
     sv = binding.solver_for(geom, s, rho0=rho0, g=g, precision=precision,
-                            l_rule=l_rule, b=b, dp=dp)
-    o = Oracle(geom, s, rho0=rho0, g=g, dp=dp, l_rule=l_rule, b=b)
+                            l_rule=l_rule, b=b, dp=dp, two_node=two_node)
+    o = Oracle(geom, s, rho0=rho0, g=g, dp=dp, l_rule=l_rule, b=b, two_node=two_node)
     if init == "deviation":
         df0 = states.random_deviation(Q, geom.n_nodes, seed=seed, amp=amp)
         sv.init_deviation(df0)

@@ -32,7 +32,7 @@ def _gpu_grad(geom, s, kw, obj, steps, every, df0, precision="fp64"):
     from paper_1712_08288_amd import binding
     sv = binding.solver_for(geom, s, precision=precision, g=kw.get("g"),
                             dp=kw.get("dp", 0.0), l_rule=kw.get("l_rule", "min"),
-                            b=kw.get("b", 1.0))
+                            b=kw.get("b", 1.0), two_node=kw.get("two_node", False))
     sv.init_deviation(df0)
     sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1)
     sv.run_checkpointed(steps, every)
@@ -53,6 +53,12 @@ CASES = [
     ("d3q19_meanux_seam", lambda: G.random_spheres(20, 14, 12, 2, 2.2, 3.4, seed=4, x_bc="pressure"),
      lambda: configs.d3q19_rates(0.65), dict(g=(2e-5, 0, 1e-5), dp=1e-3, l_rule="gamma"),
      Objective("mean_ux", t0=2, t1=8), 8),
+    ("d2q9_drag_two_node", lambda: G.random_cylinders(40, 29, 2, 3.1, 5.2, seed=6),
+     lambda: configs.d2q9_rates(0.7), dict(g=(1e-4, 2e-5, 0), l_rule="gamma2", b=0.9, two_node=True),
+     Objective("force_x", tag=1, t0=3, t1=12), 12),
+    ("d3q19_meanux_two_node_seam", lambda: G.random_spheres(20, 14, 12, 2, 2.2, 3.4, seed=4, x_bc="pressure"),
+     lambda: configs.d3q19_rates(0.65), dict(dp=1e-3, l_rule="gamma", two_node=True),
+     Objective("mean_ux", t0=0, t1=8), 8),
 ]
 
 

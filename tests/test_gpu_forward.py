@@ -66,6 +66,23 @@ def test_distribution_matches_oracle(case, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[3]], ids=[CASES[0][0], CASES[1][0], CASES[3][0]])
+def test_two_node_scheme_matches_oracle(case, precision):
+    """Eq. (211): the c1 term applied at the next pull from x_f + e_i."""
+    name, geom, s, kw, steps = case
+    got, want, fl, sv, o, f = pair(geom, s, steps, precision=precision, two_node=True, **kw)
+    assert rel_l2(got, want, fl) < TOL[precision] * (1 if precision == "fp64" else 3)
+    # the momentum-exchange force uses the completed link values
+    if precision == "fp64" and geom.n_links:
+        f_prev = o.init_deviation(states.random_deviation(o.Q, geom.n_nodes, seed=1))
+        f_prev = o.run(f_prev, steps - 1)
+        fn, fp = o.step(f_prev)
+        nt = geom.n_tags
+        assert np.allclose(sv.force(nt), o.force(fp, fn, n_tags=nt), rtol=1e-10, atol=1e-13)
+    sv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_outflow_channel_matches_oracle(precision):
     """Zero-gradient outlet, moving inlet wall and resting walls (rest start)."""
     geom = G.channel_cylinder(60, 31, 5.2, (20.4, 15.3), 0.03)

@@ -97,3 +97,21 @@ def test_min_rule_gradient_away_from_the_kink():
     assert keep.all()
     obj = Objective("force_x", tag=1, t0=0, t1=4)
     _check(geom, configs.d2q9_rates(0.8), dict(l_rule="min"), obj, 4, n_q=8)
+
+
+def test_two_node_scheme_gradient():
+    """Eq. (211): the c1 term reads the advected f_ibar(x_f, t+1)."""
+    geom = G.random_cylinders(22, 17, 2, 2.4, 3.6, seed=6)
+    wu = np.zeros_like(geom.wall_u)
+    wu[:, 1] = 0.015
+    geom = geom.with_wall_u(wu)
+    obj = Objective("force_x", tag=1, t0=1, t1=6)
+    _check(geom, configs.d2q9_rates(0.7),
+           dict(g=(1e-4, 0, 0), l_rule="gamma2", b=0.85, two_node=True), obj, 6, n_q=12)
+
+
+def test_two_node_gradient_seam_d3q19():
+    geom = G.random_spheres(10, 8, 7, 1, 1.8, 2.4, seed=4, x_bc="pressure")
+    obj = Objective("mean_ux", t0=0, t1=5)
+    _check(geom, configs.d3q19_rates(0.65),
+           dict(dp=1e-3, l_rule="gamma", two_node=True), obj, 5, n_q=8)

@@ -26,7 +26,7 @@ def run_steady(o, f, chunk=200, tol=1e-9, max_steps=200_000):
     raise AssertionError("no steady state")
 
 
-def poiseuille_error(ny_mesh, gamma, s_nu, rule, nu=0.03, lattice="D2Q9"):
+def poiseuille_error(ny_mesh, gamma, s_nu, rule, nu=0.03, lattice="D2Q9", two_node=False):
     """Paper Section 3.1: h = H/(N_y - 2 + 2 gamma), dt = eta h^2 with
     eta = (1/s_nu - 1/2)/(3 nu); body force G = 0.8 nu, H = 1.  In lattice
     units the force is G dt^2 / h."""
@@ -37,7 +37,7 @@ def poiseuille_error(ny_mesh, gamma, s_nu, rule, nu=0.03, lattice="D2Q9"):
     geom = G.poiseuille_channel(ny_mesh, gamma, nx=2, lattice=lattice,
                                 nz=1 if lattice == "D2Q9" else 2)
     s = configs.d2q9_paper_rates(s_nu) if lattice == "D2Q9" else configs.d3q19_rates(1.0 / s_nu)
-    o = Oracle(geom, s, g=(G_lat, 0, 0), l_rule=rule)
+    o = Oracle(geom, s, g=(G_lat, 0, 0), l_rule=rule, two_node=two_node)
     x, y, z = geom.coords()
     H = geom.meta["H"]
     nu_lat = (1.0 / s_nu - 0.5) / 3.0
@@ -60,6 +60,17 @@ def test_poiseuille_second_order(rule, gamma):
     """Section 3.1 reports orders around 2 for every rule, gamma and s_nu."""
     sizes = [11, 21, 41]
     errs = [poiseuille_error(n, gamma, 1.0, rule) for n in sizes]
+    p = order([n - 2 + 2 * gamma for n in sizes], errs)
+    assert 1.85 < p < 2.15, (errs, p)
+
+
+@pytest.mark.parametrize("rule", ["gamma", "2gamma", "gamma2"])
+@pytest.mark.parametrize("gamma", [0.25, 1.0])
+def test_two_node_scheme_second_order(rule, gamma):
+    """Eq. (211) (Remark (2)) is second order too; with l = gamma it is the
+    scheme of Remark (4) attributed to Yu, Mei and Shyy."""
+    sizes = [11, 21, 41]
+    errs = [poiseuille_error(n, gamma, 1.0, rule, two_node=True) for n in sizes]
     p = order([n - 2 + 2 * gamma for n in sizes], errs)
     assert 1.85 < p < 2.15, (errs, p)
 

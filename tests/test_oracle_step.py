@@ -17,7 +17,7 @@ from workloads.velocities import opposite
 # brute force: plain nested loops over nodes and directions, absolute f
 
 
-def brute_step(geom, s, rho0, g, rule, b, dp, f):
+def brute_step(geom, s, rho0, g, rule, b, dp, f, two_node=False):
     """One step written node by node from Eq. (22a), the Appendix MRT
     collision with Eq. (42), Eq. (22b) and Eq. (213).  f: dict node -> list."""
     lat = L.get(geom.lattice)
@@ -52,9 +52,26 @@ def brute_step(geom, s, rho0, g, rule, b, dp, f):
     links = {}
     for k in range(geom.n_links):
         links[(int(geom.node[k]), int(geom.dir[k]))] = k
+
+    def streamed(n, i):
+        x, y, z = n % nx, (n // nx) % ny, n // (nx * ny)
+        ex = e[i][0]
+        ey = e[i][1]
+        ez = e[i][2] if D == 3 else 0
+        sx = x - ex
+        jump = 0.0
+        if geom.x_bc == "outflow":
+            sx = min(max(sx, 0), nx - 1)
+        else:
+            if geom.x_bc == "pressure":
+                jump = w[i] * dp if sx < 0 else (-w[i] * dp if sx >= nx else 0.0)
+            sx %= nx
+        src = sx + nx * (((y - ey) % ny) + ny * ((z - ez) % nz))
+        assert fluid[src], "pull from a solid node without a link"
+        return fp[src][i] + jump
+
     new = {}
     for n in f:
-        x, y, z = n % nx, (n // nx) % ny, n // (nx * ny)
         vals = []
         for i in range(Q):
             if (n, i) in links:
@@ -69,23 +86,13 @@ def brute_step(geom, s, rho0, g, rule, b, dp, f):
                 phi = [float(v) for v in geom.wall_u[k]]
                 wall = 3 * w[i] * rho0 * sum(e[i][a] * phi[a] for a in range(D))
                 ib = opp[i]
-                vals.append(c0 * f[n][i] + c1 * f[n][ib] + c2 * fp[n][i]
+                f_ib = f[n][ib]
+                if two_node and (n, ib) not in links:
+                    f_ib = streamed(n, ib)      # f'_ibar(x_f + e_i, t), Eq. (211)
+                vals.append(c0 * f[n][i] + c1 * f_ib + c2 * fp[n][i]
                             + c3 * fp[n][ib] + c4 * wall)
                 continue
-            ex = e[i][0]
-            ey = e[i][1]
-            ez = e[i][2] if D == 3 else 0
-            sx = x - ex
-            jump = 0.0
-            if geom.x_bc == "outflow":
-                sx = min(max(sx, 0), nx - 1)
-            else:
-                if geom.x_bc == "pressure":
-                    jump = w[i] * dp if sx < 0 else (-w[i] * dp if sx >= nx else 0.0)
-                sx %= nx
-            src = sx + nx * (((y - ey) % ny) + ny * ((z - ez) % nz))
-            assert fluid[src], "pull from a solid node without a link"
-            vals.append(fp[src][i] + jump)
+            vals.append(streamed(n, i))
         new[n] = vals
     return new
 
@@ -105,18 +112,19 @@ def _tiny_cases():
         configs.d3q19_rates(0.65), (1e-4, 0, 2e-5), 2e-3, "gamma"
 
 
+@pytest.mark.parametrize("two_node", [False, True], ids=["eq210", "eq211"])
 @pytest.mark.parametrize("case", list(_tiny_cases()), ids=lambda c: c[0])
-def test_oracle_matches_brute_force(case):
+def test_oracle_matches_brute_force(case, two_node):
     name, geom, s, g, dp, rule = case
     lat = L.get(geom.lattice)
-    rng = np.random.default_rng(11)
-    o = Oracle(geom, s, rho0=1.0, g=g, dp=dp, l_rule=rule, b=0.9, deviation=False)
+    o = Oracle(geom, s, rho0=1.0, g=g, dp=dp, l_rule=rule, b=0.9, deviation=False,
+               two_node=two_node)
     df = states.random_deviation(lat.Q, o.N, seed=3, amp=2e-3)
     f = o.init_deviation(df)
     fb = {n: list(f[:, n]) for n in range(o.N) if o.fluid[n]}
     for _ in range(3):
         f, _ = o.step(f)
-        fb = brute_step(geom, s, 1.0, g, rule, 0.9, dp, fb)
+        fb = brute_step(geom, s, 1.0, g, rule, 0.9, dp, fb, two_node=two_node)
     got = np.array([f[:, n] for n in sorted(fb)])
     want = np.array([fb[n] for n in sorted(fb)])
     assert np.all(np.isfinite(got))
