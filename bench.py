@@ -28,6 +28,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per k_step<D3Q19, float> launch on this workload from rocprofv3
+# FETCH_SIZE/WRITE_SIZE (scaled by a copy of known size), valid for the
+# kernel sources with this hash (profiles/k_step_d3q19_fp32_spheres256.md).
+MEASURED_TRAFFIC = {"sources_sha256_16": "f15b3f57086f4019", "bytes": 2609470182}
+KERNEL_SOURCES = ["paper_1712_08288_amd/csrc/forward.hip",
+                  "paper_1712_08288_amd/csrc/kernels.hpp",
+                  "paper_1712_08288_amd/csrc/lattice.hpp"]
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
 
 def algorithmic_bytes(Q, s, n_nodes, n_fluid, n_links):
     """Bytes one forward step must move: each fluid node reads and writes Q
@@ -217,7 +233,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": (MEASURED_TRAFFIC["bytes"]
+                        if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]
+                        else None),
             "kernel": "k_step<D3Q19,float,pressure>",
             "copy_ceiling_GBps": ceiling["best_GBps"],
             "frac_of_copy_ceiling": round(achieved / ceiling["best_GBps"], 4),

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
+# LBM_LIBRARY may point at another build of the same sources (A/B timing)
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(_HERE, "_lib", "liblbm.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

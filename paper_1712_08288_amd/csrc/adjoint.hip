@@ -90,8 +90,8 @@ template <class L, class T, int XB, bool WANT_DS>
 __global__ void __launch_bounds__(BX)
 k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
-          const int32_t* __restrict__ nodeword, const uint8_t* __restrict__ lkdir,
-          const LinkCoef* __restrict__ lkcoef, const LinkDeriv* __restrict__ lkderiv,
+          NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
+          const LinkDeriv* __restrict__ lkderiv,
           const double* __restrict__ lkc4, const int32_t* __restrict__ lktag,
           double* __restrict__ gq, double* __restrict__ gphi,
           double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
@@ -99,16 +99,34 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
     constexpr int NC = D + Q;                 // layout of the per-block sums
     constexpr int NR = WANT_DS ? NC : D;      // columns reduced here
     const NodePos pos = node_of_thread(g);
-    const int32_t nw = pos.in ? nodeword[pos.n] : -1;
+    uint32_t lb = blockIdx.x;
+    if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t kind = lb < g.nblocks ? nm.wkind[lb * (BX / 64) + wid] : WAVE_IDLE;
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
 
-    if (nw >= 0) {
-        const NodeLinks nl = node_links(nw, lkdir);
+    // loads that do not depend on the node's metadata are issued first:
+    // the planes of the forward pull and the adjoint gathers
+    // lambda_i(y + e_i, t+1) (entries of solid or absent neighbours are
+    // read and then discarded)
+    T f[Q], lg[Q];
+    const Push<XB> ps(g, pos);
+    if (kind != WAVE_IDLE && pos.in) {
+        pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
+        unroll<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            lg[i] = ld(lam_in + (size_t)i * g.S, i == 0 ? pos.n : ps.template dst<L, i>());
+        });
+    }
+
+    // one node; PLAIN: the whole wave is fluid without cut links
+    auto node = [&](auto plain_c, uint32_t info) {
+        constexpr bool PLAIN = decltype(plain_c)::value;
+        const NodeLinks nl = PLAIN ? NodeLinks{0u, 0u} : node_links(nm, info, pos.n);
         // forward state f(y, t) and its velocity
-        T f[Q];
-        pull<L, T, XB>(A, wa, g, pos, p, nl, f);
+        apply_links<L, T>(wa, p, nl, f);
         T sp[NP], dp[NP];
         pair_split<L, T>(f, sp, dp);
         T rho, j[3];
@@ -117,28 +135,27 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
 
         // mu_i(y) = dJ/df'_i(y): lambda_i(y + e_i, t+1) where that node pulls
         T mu[Q], dir[Q];
-        const Push<XB> ps(g, pos);
         unroll<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             constexpr int ib = TAB<L>.opp[i];
             dir[i] = 0;
             if constexpr (i == 0) {
-                mu[i] = ld(lam_in, pos.n);
+                mu[i] = lg[0];
             } else {
                 bool lost = (nl.mask >> ib) & 1u;     // y + e_i is solid
                 if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == 1) lost = lost || ps.x_out;
-                mu[i] = lost ? T(0) : ld(lam_in + (size_t)i * g.S, ps.template dst<L, i>());
+                mu[i] = lost ? T(0) : lg[i];
                 if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1) {
                     if (ps.x_out) {
                         const uint32_t n2 = ps.template dst_clamped<L, i>(pos.ix);
-                        if (nodeword[n2] >= 0) mu[i] += ld(lam_in + (size_t)i * g.S, n2);
+                        if (!is_solid(nm.info[n2])) mu[i] += ld(lam_in + (size_t)i * g.S, n2);
                     }
                 }
             }
         });
 
         // own cut links: Eq. (213) reversed, drag terms, per-link gradients
-        if (nl.mask) {
+        if (!PLAIN && nl.mask) {
             T fp[Q];
             unroll<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
@@ -251,12 +268,17 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
                     acc[D + kk] -= (double)qm[kk] * (double)m[kk] / (double)TAB<L>.norm[kk];
             });
         }
+    };
+
+    if (kind == WAVE_PLAIN) {
+        node(std::true_type{}, 0u);
+    } else if (kind == WAVE_MIXED) {
+        const uint32_t info = pos.in ? nm.info[pos.n] : 0x80000000u;
+        if (!is_solid(info)) node(std::false_type{}, info);
     }
 
-    // b is uniform over the block, so the barrier inside is block-uniform
-    uint32_t blk = blockIdx.x;
-    if (g.chunk) blk = (blk % NXCD) * g.chunk + blk / NXCD;
-    if (blk < g.nblocks) block_accumulate<NR>(acc, gglob + (size_t)blk * NC);
+    // lb is uniform over the block, so the barrier inside is block-uniform
+    if (lb < g.nblocks) block_accumulate<NR>(acc, gglob + (size_t)lb * NC);
 }
 
 // Eq. (211) links k = (x_f, i) with a deferred c1: the link value is
@@ -293,11 +315,11 @@ k_two_node_pre(const T* __restrict__ A_next, T* __restrict__ lam_in,
 
 template <class L, class T>
 __global__ void __launch_bounds__(BX)
-k_adjoint_out(const T* __restrict__ lam, const int32_t* __restrict__ nodeword,
+k_adjoint_out(const T* __restrict__ lam, const uint32_t* __restrict__ info,
               uint32_t N, uint32_t S, double* __restrict__ out) {
     const uint32_t n = blockIdx.x * BX + threadIdx.x;
     if (n >= N) return;
-    const bool fluid = nodeword[n] >= 0;
+    const bool fluid = !is_solid(info[n]);
     for (int i = 0; i < L::Q; ++i)
         out[(size_t)i * N + n] = fluid ? (double)lam[(size_t)i * S + n] : 0.0;
 }
@@ -368,8 +390,8 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const void* lam_i
         auto kern = a.want_ds ? k_adjoint<L, T, XB, true> : k_adjoint<L, T, XB, false>;
         hipLaunchKernelGGL(kern, dim3(g.chunk ? g.chunk * NXCD : g.nblocks), dim3(BX), 0,
                            e.stream, (const T*)fwd.f, (const T*)fwd.wa,
-                           (const T*)lam_in, (T*)lam_out, e.d_nodeword, e.d_lkdir,
-                           e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag, e.d_gq,
+                           (const T*)lam_in, (T*)lam_out,
+                           NodeMeta{e.d_info, e.d_base, e.d_wkind}, e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag, e.d_gq,
                            e.d_gphi, e.d_gglob, g, adj_params<L, T>(e), a);
         return hipGetLastError();
     });
@@ -404,7 +426,7 @@ hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out) {
         using L = decltype(lat);
         using T = decltype(prec);
         hipLaunchKernelGGL((k_adjoint_out<L, T>), dim3(nb), dim3(BX), 0, e.stream,
-                           (const T*)lam, e.d_nodeword, (uint32_t)e.N, (uint32_t)e.S, out);
+                           (const T*)lam, e.d_info, (uint32_t)e.N, (uint32_t)e.S, out);
         return hipGetLastError();
     });
 }

@@ -321,6 +321,10 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
         return LBM_EINVAL;
     }
     if (const char* v = std::getenv("LBM_XCD_REMAP")) e.xcd_remap = std::atoi(v) != 0;
+    if (const char* v = std::getenv("LBM_ROWS_PER_BLOCK")) {
+        const int r = std::atoi(v);
+        e.rows_per_block = (r == 2 || r == 4) ? r : 1;
+    }
     for (int k = 0; k < Q; ++k) e.s[k] = s[k];
     e.rho0 = rho0;
     for (int a = 0; a < 3; ++a) e.g[a] = (g && a < D) ? g[a] : 0.0;
@@ -466,18 +470,42 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         }
         e.ibar_is_link[k] = (mask[e.lk_node_h[k]] >> ib) & 1u;
     }
-    // node words: -1 solid, else (link count << 26) | first link
-    std::vector<int32_t> nw(N);
+    // per node: bit 31 solid, else the link-direction mask; first link index
+    std::vector<uint32_t> info(N), base(N, 0u);
     {
         int64_t k = 0;
         for (int64_t n = 0; n < N; ++n) {
             if (solid[n]) {
-                nw[n] = -1;
+                info[n] = 0x80000000u;
                 continue;
             }
-            const int cnt = __builtin_popcount(mask[n]);
-            nw[n] = cnt ? (int32_t)(((uint32_t)cnt << 26) | (uint32_t)k) : 0;
-            k += cnt;
+            info[n] = mask[n];
+            base[n] = (uint32_t)k;
+            k += __builtin_popcount(mask[n]);
+        }
+    }
+    // per 64-node wave of a node launch (rows in chunks of kBlock threads):
+    // idle (no fluid), plain (64 fluid nodes without links) or mixed
+    std::vector<uint32_t> wkind;
+    {
+        const int64_t bpr = (e.nx + lbe::kBlock - 1) / lbe::kBlock;
+        const int64_t nb = bpr * e.ny * e.nz;
+        const int wpb = lbe::kBlock / lbe::kWave;
+        wkind.assign(nb * wpb, 2u);
+        for (int64_t lb = 0; lb < nb; ++lb) {
+            const int64_t row = lb / bpr, xb = lb % bpr;
+            for (int w = 0; w < wpb; ++w) {
+                const int64_t x0 = xb * lbe::kBlock + w * lbe::kWave;
+                const int64_t nin = std::max<int64_t>(0, std::min<int64_t>(lbe::kWave, e.nx - x0));
+                bool any_fluid = false, all_plain = nin == lbe::kWave;
+                for (int64_t l = 0; l < nin; ++l) {
+                    const int64_t n = row * e.nx + x0 + l;
+                    const bool fl = !solid[n];
+                    any_fluid = any_fluid || fl;
+                    all_plain = all_plain && fl && mask[n] == 0u;
+                }
+                wkind[lb * wpb + w] = !any_fluid ? 2u : (all_plain ? 1u : 0u);
+            }
         }
     }
     std::vector<uint8_t> d8(n_links);
@@ -489,7 +517,9 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     e.has_geometry = false;
     free_run(e);
     int rc;
-    if ((rc = upload(h, e.d_nodeword, nw.data(), nw.size()))) return rc;
+    if ((rc = upload(h, e.d_info, info.data(), info.size()))) return rc;
+    if ((rc = upload(h, e.d_base, base.data(), base.size()))) return rc;
+    if ((rc = upload(h, e.d_wkind, wkind.data(), wkind.size()))) return rc;
     if ((rc = upload(h, e.d_lkdir, d8.data(), d8.size()))) return rc;
     if ((rc = upload(h, e.d_lknode, n32.data(), n32.size()))) return rc;
     if ((rc = upload(h, e.d_lktag, e.tag_h.data(), e.tag_h.size()))) return rc;
@@ -983,7 +1013,9 @@ int lbm_destroy(lbm_t* h) {
     if (e.stream) (void)hipStreamSynchronize(e.stream);
     free_run(e);
     for (auto& b : e.buf) free_snap(b);
-    free_dev(e.d_nodeword);
+    free_dev(e.d_info);
+    free_dev(e.d_base);
+    free_dev(e.d_wkind);
     free_dev(e.d_lkdir);
     free_dev(e.d_lknode);
     free_dev(e.d_lktag);

@@ -9,6 +9,9 @@
 
 namespace lbe {
 
+constexpr int kBlock = 256;             // threads per block of node launches
+constexpr int kWave = 64;
+
 struct LinkCoef {        // per cut link, double: Eq. (213) coefficients
     double c1, c2, c3;   // on f_ibar(x_f,t), f'_i(x_f,t), f'_ibar(x_f,t)
     double wall;         // c4 * 3 w_i rho0 e_i.phi
@@ -29,6 +32,7 @@ struct Engine {
     int64_t nx = 0, ny = 0, nz = 0, N = 0;
     int64_t S = 0;           // stride (values) between direction planes, >= N
     bool xcd_remap = false;  // deal contiguous row slabs to each XCD (measured slower)
+    int rows_per_block = 1;  // step kernel: rows swept per block (1, 2 or 4)
     double s[19] = {0};
     double rho0 = 1.0;
     double g[3] = {0, 0, 0};
@@ -48,7 +52,9 @@ struct Engine {
     std::vector<double> q_h, wall_u_h;  // sorted, wall_u (L, D)
     std::vector<int32_t> tag_h;
 
-    int32_t* d_nodeword = nullptr;
+    uint32_t* d_info = nullptr;         // per node: bit 31 solid, bits 0..Q-1 link directions
+    uint32_t* d_base = nullptr;         // per node: first link index
+    uint32_t* d_wkind = nullptr;        // per 64-node wave of a node launch
     uint8_t* d_lkdir = nullptr;
     int32_t* d_lknode = nullptr;
     int32_t* d_lktag = nullptr;

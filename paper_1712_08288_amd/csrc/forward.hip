@@ -12,28 +12,53 @@
 
 namespace lbe {
 
+static_assert(BX == kBlock && BX % 64 == 0, "node launches use kBlock-thread blocks");
+
 // ----------------------------------------------------------------------------
 // the step: pull, collide, store, and evaluate Eq. (213) for the node's links
+
+// Eq. (213) for every cut link of one node, from its pre-collision values
+// (fpre) and post-collision values (f), into the link slots of the next step
+template <class L, class T>
+__device__ __forceinline__ void link_tail(const NodeLinks& nl, const T (&fpre)[L::Q],
+                                          const T (&f)[L::Q],
+                                          const LinkCoef* __restrict__ lkcoef,
+                                          T* __restrict__ waB, double c0) {
+    uint32_t k = nl.base;
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ib = TAB<L>.opp[i];
+        if constexpr (i > 0) {
+            const uint32_t bit = (nl.mask >> i) & 1u;
+            if (bit) {
+                const LinkCoef c = lkcoef[k];
+                const double v = c0 * (double)fpre[i] + c.c1 * (double)fpre[ib] +
+                                 c.c2 * (double)f[i] + c.c3 * (double)f[ib] + c.wall;
+                waB[k] = (T)v;
+            }
+            k += bit;
+        }
+    });
+}
+
+// Waves are classified on the host (one scalar load per wave): a wave whose
+// 64 nodes are all fluid and free of cut links issues its 19 pulls at once;
+// a mixed wave first reads each node's link mask, skips solid nodes and the
+// planes of its link directions; a wave without fluid exits.
 template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
-       T* __restrict__ waB, const int32_t* __restrict__ nodeword,
-       const uint8_t* __restrict__ lkdir, const LinkCoef* __restrict__ lkcoef,
+       T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
        Grid g, Params<L, T> p, double* __restrict__ acc_ux, double w_ux) {
     const NodePos pos = node_of_thread(g);
-    const int32_t nw = pos.in ? nodeword[pos.n] : -1;
+    uint32_t lb = blockIdx.x;
+    if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t kind = lb < g.nblocks ? nm.wkind[lb * (BX / 64) + wid] : WAVE_IDLE;
     double ux_local = 0.0;
-    if (nw >= 0) {
-        const NodeLinks nl = node_links(nw, lkdir);
+    if (kind == WAVE_PLAIN) {
         T f[L::Q];
-        pull<L, T, XB>(A, waA, g, pos, p, nl, f);
-        T fpre_link[L::Q];
-        if (nl.mask) {
-            unroll<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                fpre_link[i] = f[i];
-            });
-        }
+        pull<L, T, XB>(A, waA, g, pos, p, NodeLinks{0u, 0u}, f);
         Macro<L, T> mac;
         collide<L, T>(f, p, mac);
         ux_local = (double)mac.u[0];
@@ -41,33 +66,108 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             constexpr int i = decltype(I)::value;
             st_nt(B + (size_t)i * g.S, pos.n, f[i]);
         });
-        if (nl.mask) {
-            uint32_t k = nl.base;
+    } else if (kind == WAVE_MIXED) {
+        // the plane reads are issued before the node's metadata arrives
+        // (measured faster than waiting for it, despite reading solid slots)
+        T f[L::Q];
+        if (pos.in) pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
+        const uint32_t info = pos.in ? nm.info[pos.n] : 0x80000000u;
+        if (!is_solid(info)) {
+            const NodeLinks nl = node_links(nm, info, pos.n);
+            apply_links<L, T>(waA, p, nl, f);
+            T fpre[L::Q];
             unroll<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                constexpr int ib = TAB<L>.opp[i];
-                if constexpr (i > 0) {
-                    const uint32_t bit = (nl.mask >> i) & 1u;
-                    if (bit) {
-                        const LinkCoef c = lkcoef[k];
-                        const double v = p.c0 * (double)fpre_link[i] +
-                                         c.c1 * (double)fpre_link[ib] +
-                                         c.c2 * (double)f[i] + c.c3 * (double)f[ib] +
-                                         c.wall;
-                        waB[k] = (T)v;
-                    }
-                    k += bit;
-                }
+                fpre[i] = f[i];
             });
+            Macro<L, T> mac;
+            collide<L, T>(f, p, mac);
+            ux_local = (double)mac.u[0];
+            unroll<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                st_nt(B + (size_t)i * g.S, pos.n, f[i]);
+            });
+            if (nl.mask) link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0);
         }
     }
     if (acc_ux) {   // uniform over the launch
         const double s = block_sum(ux_local);
-        if (threadIdx.x == 0) {
-            uint32_t b = blockIdx.x;
-            if (g.chunk) b = (b % NXCD) * g.chunk + b / NXCD;
-            if (b < g.nblocks) acc_ux[b] += w_ux * s;
+        if (threadIdx.x == 0 && lb < g.nblocks) acc_ux[lb] += w_ux * s;
+    }
+}
+
+// The same step with each block sweeping R consecutive rows of one x-chunk:
+// the plane reads (and link-mask word) of row r+1 are issued before row r is
+// collided, so a wave keeps loads in flight through its compute phase.
+template <class L, class T, int XB, int R>
+__global__ void __launch_bounds__(BX)
+k_step_rows(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
+            T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
+            Grid g, Params<L, T> p, double* __restrict__ acc_ux, double w_ux) {
+    const uint32_t nrows = g.ny * g.nz;
+    const uint32_t rg = blockIdx.x / g.bpr;              // group of R rows
+    const uint32_t xb = blockIdx.x - rg * g.bpr;
+    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t ix = xb * BX + threadIdx.x;
+    auto pos_of = [&](uint32_t row) {
+        NodePos q;
+        q.ix = ix;
+        q.iy = row % g.ny;
+        q.iz = row / g.ny;
+        q.in = row < nrows && ix < g.nx;
+        q.n = ix + g.nx * row;
+        return q;
+    };
+    double ux_local = 0.0;
+    T buf[2][L::Q];
+    uint32_t info[2];
+    {
+        const NodePos q = pos_of(rg * R);
+        if (q.in) pull_planes<L, T, XB>(A, g, q, p, NodeLinks{0u, 0u}, buf[0]);
+        info[0] = q.in ? nm.info[q.n] : 0x80000000u;
+    }
+    unroll<R>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        constexpr int cb = r & 1, nb = cb ^ 1;
+        const uint32_t row = rg * R + r;
+        if constexpr (r + 1 < R) {
+            const NodePos q = pos_of(row + 1);
+            if (q.in) pull_planes<L, T, XB>(A, g, q, p, NodeLinks{0u, 0u}, buf[nb]);
+            info[nb] = q.in ? nm.info[q.n] : 0x80000000u;
         }
+        const NodePos pos = pos_of(row);
+        const uint32_t kind = row < nrows ? nm.wkind[(row * g.bpr + xb) * (BX / 64) + wid]
+                                          : (uint32_t)WAVE_IDLE;
+        T (&f)[L::Q] = buf[cb];
+        if (kind == WAVE_PLAIN) {
+            Macro<L, T> mac;
+            collide<L, T>(f, p, mac);
+            ux_local += (double)mac.u[0];
+            unroll<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                st_nt(B + (size_t)i * g.S, pos.n, f[i]);
+            });
+        } else if (kind == WAVE_MIXED && !is_solid(info[cb])) {
+            const NodeLinks nl = node_links(nm, info[cb], pos.n);
+            apply_links<L, T>(waA, p, nl, f);
+            T fpre[L::Q];
+            unroll<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                fpre[i] = f[i];
+            });
+            Macro<L, T> mac;
+            collide<L, T>(f, p, mac);
+            ux_local += (double)mac.u[0];
+            unroll<L::Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                st_nt(B + (size_t)i * g.S, pos.n, f[i]);
+            });
+            if (nl.mask) link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0);
+        }
+    });
+    if (acc_ux) {   // uniform over the launch; one partial per (row group, x-chunk)
+        const double s = block_sum(ux_local);
+        if (threadIdx.x == 0) acc_ux[blockIdx.x] += w_ux * s;
     }
 }
 
@@ -77,13 +177,12 @@ template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
 k_init(const double* __restrict__ df, const double* __restrict__ rho,
        const double* __restrict__ u, T* __restrict__ A, T* __restrict__ wa,
-       const int32_t* __restrict__ nodeword, const uint8_t* __restrict__ lkdir,
-       Grid g, Params<L, T> p) {
+       NodeMeta nm, Grid g, Params<L, T> p) {
     const NodePos pos = node_of_thread(g);
     if (!pos.in) return;
-    const int32_t nw = nodeword[pos.n];
-    if (nw < 0) return;
-    const NodeLinks nl = node_links(nw, lkdir);
+    const uint32_t info = nm.info[pos.n];
+    if (is_solid(info)) return;
+    const NodeLinks nl = node_links(nm, info, pos.n);
     double f[L::Q];
     if (df) {
         unroll<L::Q>([&](auto I) {
@@ -114,7 +213,7 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
         // the outlet column's -x populations share their slot with the pull
         // of node (nx-2, y, z); that node's value is kept unless it is solid
         if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1)
-            if (pos.ix + 1 == g.nx && nodeword[pos.n - 1] >= 0) return;
+            if (pos.ix + 1 == g.nx && !is_solid(nm.info[pos.n - 1])) return;
         T v = (T)f[i];
         if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
             const int sg = seam_sign<L, i>(pos.ix, g.nx);
@@ -129,15 +228,14 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
 // observation: moments or the full distribution of f(x, t), NaN at solids
 template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
-k_observe(const T* __restrict__ A, const T* __restrict__ wa,
-          const int32_t* __restrict__ nodeword, const uint8_t* __restrict__ lkdir,
+k_observe(const T* __restrict__ A, const T* __restrict__ wa, NodeMeta nm,
           Grid g, Params<L, T> p, double* __restrict__ rho, double* __restrict__ u,
           double* __restrict__ df) {
     const NodePos pos = node_of_thread(g);
     if (!pos.in) return;
-    const int32_t nw = nodeword[pos.n];
+    const uint32_t info = nm.info[pos.n];
     const double nan = __builtin_nan("");
-    if (nw < 0) {
+    if (is_solid(info)) {
         if (rho) rho[pos.n] = nan;
         if (u)
             for (int a = 0; a < L::D; ++a) u[(size_t)pos.n * L::D + a] = nan;
@@ -145,9 +243,9 @@ k_observe(const T* __restrict__ A, const T* __restrict__ wa,
             for (int i = 0; i < L::Q; ++i) df[(size_t)i * g.N + pos.n] = nan;
         return;
     }
-    const NodeLinks nl = node_links(nw, lkdir);
+    const NodeLinks nl = node_links(nm, info, pos.n);
     T f[L::Q];
-    pull<L, T, XB>(A, wa, g, pos, p, nl, f);
+    pull<L, T, XB, true>(A, wa, g, pos, p, nl, f);
     if (df) {
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
@@ -173,16 +271,15 @@ k_observe(const T* __restrict__ A, const T* __restrict__ wa,
 // per-block sums of drho and sum e f (= rho0 u) over fluid nodes
 template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
-k_mass(const T* __restrict__ A, const T* __restrict__ wa,
-       const int32_t* __restrict__ nodeword, const uint8_t* __restrict__ lkdir,
+k_mass(const T* __restrict__ A, const T* __restrict__ wa, NodeMeta nm,
        Grid g, Params<L, T> p, double* __restrict__ partials) {
     const NodePos pos = node_of_thread(g);
-    const int32_t nw = pos.in ? nodeword[pos.n] : -1;
+    const uint32_t info = pos.in ? nm.info[pos.n] : 0x80000000u;
     double r = 0, j[3] = {0, 0, 0};
-    if (nw >= 0) {
-        const NodeLinks nl = node_links(nw, lkdir);
+    if (!is_solid(info)) {
+        const NodeLinks nl = node_links(nm, info, pos.n);
         T f[L::Q];
-        pull<L, T, XB>(A, wa, g, pos, p, nl, f);
+        pull<L, T, XB, true>(A, wa, g, pos, p, nl, f);
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const double v = (double)f[i];
@@ -325,7 +422,16 @@ unsigned launch_blocks(const Grid& g) {
     return g.chunk ? g.chunk * NXCD : g.nblocks;
 }
 
-int64_t step_blocks(const Engine& e) { return make_grid(e).nblocks; }
+int64_t step_blocks(const Engine& e) {
+    const Grid g = make_grid(e);
+    if (e.rows_per_block > 1) {
+        const int64_t nrows = (int64_t)g.ny * g.nz;
+        return (int64_t)g.bpr * ((nrows + e.rows_per_block - 1) / e.rows_per_block);
+    }
+    return g.nblocks;
+}
+
+NodeMeta meta(const Engine& e) { return NodeMeta{e.d_info, e.d_base, e.d_wkind}; }
 int64_t link_blocks(const Engine& e) { return (e.n_links + BX - 1) / BX; }
 
 template <class L, class T>
@@ -373,9 +479,24 @@ hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
+        if (e.rows_per_block > 1) {
+            const uint32_t nrows = g.ny * g.nz;
+            const int R = e.rows_per_block;
+            const unsigned nb = g.bpr * ((nrows + R - 1) / R);
+            auto launch = [&](auto rr) {
+                constexpr int RR = decltype(rr)::value;
+                hipLaunchKernelGGL((k_step_rows<L, T, XB, RR>), dim3(nb), dim3(BX), 0, e.stream,
+                                   (const T*)in.f, (T*)out.f, (const T*)in.wa, (T*)out.wa,
+                                   meta(e), e.d_lkcoef, g, make_params<L, T>(e), obj.acc_ux,
+                                   obj.w_ux);
+            };
+            if (R == 2) launch(std::integral_constant<int, 2>{});
+            else launch(std::integral_constant<int, 4>{});
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL((k_step<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
-                           (T*)out.wa, e.d_nodeword, e.d_lkdir, e.d_lkcoef, g,
+                           (T*)out.wa, meta(e), e.d_lkcoef, g,
                            make_params<L, T>(e), obj.acc_ux, obj.w_ux);
         return hipGetLastError();
     });
@@ -389,8 +510,8 @@ hipError_t launch_init(Engine& e, const double* df, const double* rho,
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
         hipLaunchKernelGGL((k_init<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
-                           e.stream, df, rho, u, (T*)out.f, (T*)out.wa, e.d_nodeword,
-                           e.d_lkdir, g, make_params<L, T>(e));
+                           e.stream, df, rho, u, (T*)out.f, (T*)out.wa, meta(e), g,
+                           make_params<L, T>(e));
         return hipGetLastError();
     });
 }
@@ -403,8 +524,8 @@ hipError_t launch_observe(Engine& e, const Snapshot& in, double* rho, double* u,
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
         hipLaunchKernelGGL((k_observe<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
-                           e.stream, (const T*)in.f, (const T*)in.wa, e.d_nodeword,
-                           e.d_lkdir, g, make_params<L, T>(e), rho, u, df);
+                           e.stream, (const T*)in.f, (const T*)in.wa, meta(e), g,
+                           make_params<L, T>(e), rho, u, df);
         return hipGetLastError();
     });
 }
@@ -418,8 +539,8 @@ hipError_t launch_mass(Engine& e, const Snapshot& in, double* partials,
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
         hipLaunchKernelGGL((k_mass<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
-                           e.stream, (const T*)in.f, (const T*)in.wa, e.d_nodeword,
-                           e.d_lkdir, g, make_params<L, T>(e), partials);
+                           e.stream, (const T*)in.f, (const T*)in.wa, meta(e), g,
+                           make_params<L, T>(e), partials);
         return hipGetLastError();
     });
 }

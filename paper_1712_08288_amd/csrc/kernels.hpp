@@ -306,13 +306,22 @@ struct NodeLinks {
     uint32_t base;   // index of the node's first link
 };
 
-__device__ __forceinline__ NodeLinks node_links(int32_t nw, const uint8_t* __restrict__ lkdir) {
-    NodeLinks r{0u, 0u};
-    if (nw > 0) {
-        const uint32_t cnt = (uint32_t)nw >> 26;
-        r.base = (uint32_t)nw & 0x3FFFFFFu;
-        for (uint32_t k = 0; k < cnt; ++k) r.mask |= 1u << lkdir[r.base + k];
-    }
+// Per-node and per-wave metadata of the geometry.
+struct NodeMeta {
+    const uint32_t* __restrict__ info;   // bit 31: solid; bits 0..Q-1: cut-link directions
+    const uint32_t* __restrict__ base;   // first link of the node (links sorted by direction)
+    const uint32_t* __restrict__ wkind;  // per 64-node wave of a node launch:
+                                         // 0 mixed, 1 all fluid without links, 2 no fluid
+};
+
+enum WaveKind : uint32_t { WAVE_MIXED = 0, WAVE_PLAIN = 1, WAVE_IDLE = 2 };
+
+__device__ __forceinline__ bool is_solid(uint32_t info) { return (info >> 31) != 0; }
+
+__device__ __forceinline__ NodeLinks node_links(const NodeMeta& nm, uint32_t info, uint32_t n) {
+    NodeLinks r;
+    r.mask = info & 0x7FFFFFFFu;
+    r.base = r.mask ? nm.base[n] : 0u;
     return r;
 }
 
@@ -320,15 +329,19 @@ __device__ __forceinline__ uint32_t link_index(const NodeLinks& nl, int i) {
     return nl.base + __popc(nl.mask & ((1u << i) - 1u));
 }
 
-// Pull the pre-collision state f(x, t) of one fluid node.
-template <class L, class T, int XB>
-__device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restrict__ wa,
-                                     const Grid& g, const NodePos& pos,
-                                     const Params<L, T>& p, const NodeLinks& nl,
-                                     T (&f)[L::Q]) {
+// Read the planes of a pull: f_i = A_i(x - e_i) (+ seam term).  With PRED
+// the planes of cut-link directions are not read.
+template <class L, class T, int XB, bool PRED = false>
+__device__ __forceinline__ void pull_planes(const T* __restrict__ A, const Grid& g,
+                                            const NodePos& pos, const Params<L, T>& p,
+                                            const NodeLinks& nl, T (&f)[L::Q]) {
     const Pull<XB> pl(g, pos);
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
+        if (PRED && i > 0 && ((nl.mask >> i) & 1u)) {
+            f[i] = 0;
+            return;
+        }
         f[i] = ld(A + (size_t)i * g.S, pl.template src<L, i>());
         if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
             const int sg = seam_sign<L, i>(pos.ix, g.nx);
@@ -336,35 +349,49 @@ __device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restric
             else if (sg < 0) f[i] -= p.seam[i];
         }
     });
-    if (nl.mask) {
-        // links are sorted by direction: a running index replaces a popcount
-        uint32_t k = nl.base;
+}
+
+// Cut-link directions take their link slot (links are sorted by direction,
+// so a running index replaces a popcount); with Eq. (211) the slot is
+// completed by c1 f_ibar(x, t), the value just advected from x + e_i.
+template <class L, class T>
+__device__ __forceinline__ void apply_links(const T* __restrict__ wa, const Params<L, T>& p,
+                                            const NodeLinks& nl, T (&f)[L::Q]) {
+    if (!nl.mask) return;
+    uint32_t k = nl.base;
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (i > 0) {
+            const uint32_t bit = (nl.mask >> i) & 1u;
+            if (bit) f[i] = wa[k];
+            k += bit;
+        }
+    });
+    if (p.c1d) {
+        uint32_t kk = nl.base;
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
+            constexpr int ib = TAB<L>.opp[i];
             if constexpr (i > 0) {
                 const uint32_t bit = (nl.mask >> i) & 1u;
-                if (bit) f[i] = wa[k];
-                k += bit;
+                if (bit) {
+                    const double c = p.c1d[kk];
+                    if (c != 0.0) f[i] = (T)((double)f[i] + c * (double)f[ib]);
+                }
+                kk += bit;
             }
         });
-        if (p.c1d) {
-            // Eq. (211): f_i(x_f, t) gets c1 f_ibar(x_f, t), the value just
-            // advected from x_f + e_i (c1d is zero when that is a link too)
-            uint32_t kk = nl.base;
-            unroll<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                constexpr int ib = TAB<L>.opp[i];
-                if constexpr (i > 0) {
-                    const uint32_t bit = (nl.mask >> i) & 1u;
-                    if (bit) {
-                        const double c = p.c1d[kk];
-                        if (c != 0.0) f[i] = (T)((double)f[i] + c * (double)f[ib]);
-                    }
-                    kk += bit;
-                }
-            });
-        }
     }
+}
+
+// Pull the pre-collision state f(x, t) of one fluid node.
+template <class L, class T, int XB, bool PRED = false>
+__device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restrict__ wa,
+                                     const Grid& g, const NodePos& pos,
+                                     const Params<L, T>& p, const NodeLinks& nl,
+                                     T (&f)[L::Q]) {
+    pull_planes<L, T, XB, PRED>(A, g, pos, p, nl, f);
+    apply_links<L, T>(wa, p, nl, f);
 }
 
 // The value f_i(n, t) that a pull of direction i at fluid node n would read
