@@ -117,6 +117,212 @@ def cpu_baseline(geom, w, slab=48, steps=20):
                       % (steps, nx, ny, min(slab, nz), len(nodes), threads, dt)}
 
 
+def _timed_steps(sv, n):
+    import torch
+    torch.cuda.synchronize()
+    sv.set_timing(True)
+    t0 = time.perf_counter()
+    sv.step(n)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / max(n, 1)
+    ms = sv.last_step_ms()
+    sv.set_timing(False)
+    return ms, wall
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _progress(what):
+    print("[bench --all] " + what, file=sys.stderr, flush=True)
+
+
+def all_configs(binding, torch):
+    """Every benchmark workload: MLUPS and HBM fraction per precision,
+    accuracy figures, and the checkpointed adjoints of C4 and C5."""
+    from workloads import analytic, configs
+    out = {}
+
+    def fwd(w, geom, prec, steps, warm=10, **kw):
+        sv = binding.solver_for(geom, w.s, g=w.g, precision=prec, dp=w.dp,
+                                l_rule=w.l_rule, **kw)
+        sv.init()
+        sv.step(warm)
+        ms, wall = _timed_steps(sv, steps)
+        Q = 9 if geom.lattice == "D2Q9" else 19
+        by = algorithmic_bytes(Q, 4 if prec == "fp32" else 8, geom.n_nodes,
+                               geom.n_fluid, geom.n_links)
+        return sv, {"ms_per_step": round(ms, 5), "wall_ms_per_step": round(wall, 5),
+                    "mlups": round(geom.n_nodes / (ms * 1e-3) / 1e6, 1),
+                    "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    _progress("C1")
+    # C1: circular Couette, FP64, refinement under diffusive scaling
+    errs, sizes = [], [32, 64, 128]
+    for n in sizes:
+        w = configs.c1_couette(n)
+        geom = w.geometry()
+        sv = binding.solver_for(geom, w.s, precision="fp64", l_rule=w.l_rule)
+        sv.init()
+        ms, wall = _timed_steps(sv, w.steps)
+        _, u = sv.moments()
+        sv.close()
+        e = analytic.relative_l2(u, analytic.couette_velocity(geom), geom.solid == 0)
+        errs.append(e)
+        if n == 64:
+            out["c1_couette_64"] = {"steps": w.steps, "ms_per_step": round(ms, 5),
+                                    "mlups": round(geom.n_nodes / (ms * 1e-3) / 1e6, 1),
+                                    "u_rel_l2_vs_analytic": e}
+    out["c1_refinement"] = {"sizes": sizes, "u_rel_l2": errs,
+                            "fitted_order": float(-np.polyfit(np.log(sizes), np.log(errs), 1)[0])}
+
+    _progress("C2")
+    # C2: 2048^2 cylinders, FP64 and FP32, 1000 steps
+    w = configs.c2_cylinders()
+    geom = w.geometry()
+    res = {"n_fluid": geom.n_fluid, "n_links": geom.n_links}
+    us = {}
+    for prec in ("fp64", "fp32"):
+        sv, r = fwd(w, geom, prec, w.steps - 10)
+        _, us[prec] = sv.moments()
+        sv.close()
+        res[prec] = r
+    fl = geom.solid == 0
+    res["u_rel_l2_fp32_vs_fp64"] = _rel(us["fp32"][fl], us["fp64"][fl])
+    out["c2_cylinders_2048"] = res
+
+    _progress("C3")
+    # C3: 256^3 spheres, 500 steps in both precisions
+    w = configs.c3_spheres()
+    geom = w.geometry()
+    res = {}
+    for prec in ("fp32", "fp64"):
+        sv, r = fwd(w, geom, prec, w.steps - 10)
+        _, us[prec] = sv.moments()
+        sv.close()
+        res[prec] = r
+    fl = geom.solid == 0
+    res["u_rel_l2_fp32_vs_fp64"] = _rel(us["fp32"][fl], us["fp64"][fl])
+    res["speedup_fp32_over_fp64"] = round(res["fp64"]["ms_per_step"] / res["fp32"]["ms_per_step"], 3)
+    out["c3_spheres_256"] = res
+    del geom
+
+    _progress("C4")
+    # C4: channel + cylinder, drag over the last 1000 of 3000 steps, sqrt(N)
+    # checkpointing, gradients in q, u_in and tau; FD checks in FP64
+    w = configs.c4_cylinder()
+    geom = w.geometry()
+    t0, t1 = w.extra["obj_window"]
+    every = int(round(np.sqrt(w.steps)))
+    res = {"n_links": geom.n_links, "checkpoint_every": every}
+    for prec in ("fp64", "fp32"):
+        sv = binding.solver_for(geom, w.s, precision=prec, l_rule=w.l_rule)
+        sv.init()
+        sv.set_objective("force_x", 1, t0, t1)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sv.run_checkpointed(w.steps, every)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        sv.adjoint()
+        gr = sv.grad()
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        J = sv.objective()
+        inlet = geom.tag == 2
+        tau = 1.0 / w.s[7]
+        r = {"J_drag": J, "dJ_du_in": float(gr["wall_u"][inlet, 0].sum()),
+             "dJ_dtau": float(-(gr["s"][7] + gr["s"][8]) * w.s[7] ** 2),
+             "forward_s": round(b - a, 4), "reverse_s": round(c - b, 4),
+             "reverse_over_forward": round((c - b) / (b - a), 3)}
+        if prec == "fp64":
+            h = 1e-6
+
+            def J_at(q=geom.q, wu=geom.wall_u, s=w.s):
+                sv.update_links(q, wu)
+                sv.set_parameters(s, (0.0, 0.0))
+                sv.init()
+                sv.set_objective("force_x", 1, t0, t1)
+                sv.step(w.steps)
+                return sv.objective()
+            up, um = geom.wall_u.copy(), geom.wall_u.copy()
+            up[inlet, 0] += h
+            um[inlet, 0] -= h
+            fd_u = (J_at(wu=up) - J_at(wu=um)) / (2 * h)
+            sp, sm = w.s.copy(), w.s.copy()
+            sp[7:9] = 1.0 / (tau + h)
+            sm[7:9] = 1.0 / (tau - h)
+            fd_tau = (J_at(s=sp) - J_at(s=sm)) / (2 * h)
+            # a single link moves J by ~1e-9: a larger step keeps the
+            # difference above round-off, away from the l-rule kink at 1/2
+            hq = 1e-4
+            cyl = np.nonzero((geom.tag == 1) & (np.abs(geom.q - 0.5) > 10 * hq))[0]
+            k = cyl[np.argsort(-np.abs(gr["q"][cyl]))[:3]]
+            fd_q = []
+            for kk in k:
+                qp, qm = geom.q.copy(), geom.q.copy()
+                qp[kk] += hq
+                qm[kk] -= hq
+                fd_q.append((J_at(q=qp) - J_at(q=qm)) / (2 * hq))
+            r["fd_rel_err"] = {"u_in": abs(fd_u - r["dJ_du_in"]) / abs(fd_u),
+                               "tau": abs(fd_tau - r["dJ_dtau"]) / abs(fd_tau),
+                               "q_top3": [abs(f - gr["q"][kk]) / abs(f) for f, kk in zip(fd_q, k)]}
+            g64 = gr
+        else:
+            ref = res["fp64"]["dJ_du_in"]
+            r["grad_rel_err_vs_fp64"] = {"q": _rel(gr["q"], g64["q"]),
+                                         "u_in": abs(r["dJ_du_in"] - ref) / abs(ref)}
+        sv.close()
+        res[prec] = r
+    out["c4_cylinder_1024x512"] = res
+
+    _progress("C5")
+    # C5: 384x256x256 porous medium, FP32, 2000 steps + adjoint, every 64
+    w = configs.c5_porous()
+    geom = w.geometry()
+    sv = binding.solver_for(geom, w.s, g=w.g, precision="fp32", l_rule=w.l_rule)
+    sv.set_rate_gradient(False)
+    sv.init()
+    sv.set_objective("mean_ux", 0, w.steps - 500, w.steps)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    sv.run_checkpointed(w.steps, 64)
+    torch.cuda.synchronize()
+    b = time.perf_counter()
+    sv.adjoint()
+    gr = sv.grad()
+    torch.cuda.synchronize()
+    c = time.perf_counter()
+    J = sv.objective()
+    sv.close()
+    out["c5_porous_384x256x256"] = {
+        "n_fluid": geom.n_fluid, "n_links": geom.n_links, "J_mean_ux": J,
+        "dJ_dgx": float(gr["g"][0]), "J_over_gx": J / w.g[0],
+        "forward_ms_per_step": round((b - a) * 1e3 / w.steps, 4),
+        "reverse_ms_per_step": round((c - b) * 1e3 / w.steps, 4)}
+    del geom
+    # crop-sized medium: FP32 gradient against the FP64 GPU gradient
+    w = configs.c5_crop(steps=400)
+    geom = w.geometry()
+    gsets = {}
+    for prec in ("fp64", "fp32"):
+        sv = binding.solver_for(geom, w.s, g=w.g, precision=prec, l_rule=w.l_rule)
+        sv.init()
+        sv.set_objective("mean_ux", 0, w.steps - 100, w.steps)
+        sv.run_checkpointed(w.steps, 20)
+        sv.adjoint()
+        gsets[prec] = (sv.objective(), sv.grad())
+        sv.close()
+    out["c5_crop_96x64x64"] = {
+        "steps": w.steps,
+        "J_rel_err_fp32": abs(gsets["fp32"][0] - gsets["fp64"][0]) / abs(gsets["fp64"][0]),
+        "dJ_dg_rel_err_fp32": _rel(gsets["fp32"][1]["g"], gsets["fp64"][1]["g"]),
+        "dJ_dq_rel_l2_fp32": _rel(gsets["fp32"][1]["q"], gsets["fp64"][1]["q"])}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +332,8 @@ def main():
     ap.add_argument("--every", type=int, default=8)
     ap.add_argument("--n", type=int, default=256, help="lattice edge (256 = the benchmark)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--all", action="store_true",
+                    help="also measure every workload (C1-C5) into 'per_config'")
     ap.add_argument("--only", choices=["fwd32", "fwd64", "adjoint32", "copy"],
                     help="profiling runs: time only this part and print its line")
     args = ap.parse_args()
@@ -261,6 +469,9 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(geom, w)
+    if args.all:
+        del geom
+        out["per_config"] = all_configs(binding, torch)
     print(json.dumps(out), flush=True)
 
 

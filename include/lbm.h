@@ -149,7 +149,11 @@ int lbm_init(lbm_t *h, const double *rho, const double *u);
  * (solid entries ignored).  Resets the time counter to 0. */
 int lbm_init_deviation(lbm_t *h, const double *df);
 
-/* Enqueue n >= 0 time steps. */
+/* Enqueue n >= 0 time steps.  On domains of at most 2^20 nodes, runs of 64
+ * steps outside an objective window are replayed from a captured HIP graph
+ * (launch-bound sizes); results are identical to single launches.  The
+ * graph is rebuilt after any change of parameters, links, geometry or
+ * stream. */
 int lbm_step(lbm_t *h, int64_t n);
 
 /* Current time (number of steps taken since init or set_state). */

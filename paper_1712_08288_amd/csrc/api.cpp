@@ -238,6 +238,41 @@ int upload_coefficients(lbm_t* h) {
     return sync(h);
 }
 
+// Captured step loops become invalid when kernel arguments change.
+void drop_graphs(Engine& e) {
+    for (auto& g : e.graph_exec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// Capture graph_steps consecutive steps starting from buffer `start` (an
+// even count, so the graph starts and ends on the same buffer).
+int build_graph(lbm_t* h, int start) {
+    Engine& e = h->e;
+    hipGraph_t graph = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(e.stream, hipStreamCaptureModeThreadLocal));
+    int cur = start;
+    hipError_t st = hipSuccess;
+    for (int s = 0; s < e.graph_steps && st == hipSuccess; ++s) {
+        st = lbe::launch_step(e, e.buf[cur], e.buf[cur ^ 1], lbe::StepObjective{});
+        cur ^= 1;
+    }
+    const hipError_t st2 = hipStreamEndCapture(e.stream, &graph);
+    if (st != hipSuccess || st2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(h, LBM_EDEVICE, std::string("graph capture: ") +
+                                        hipGetErrorString(st != hipSuccess ? st : st2));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t st3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (st3 != hipSuccess)
+        return fail(h, LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(st3));
+    e.graph_exec[start] = exec;
+    return LBM_OK;
+}
+
 void free_run(Engine& e) {
     for (auto& s : e.ckpt) free_snap(s);
     for (auto& s : e.pool) free_snap(s);
@@ -321,6 +356,13 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
         return LBM_EINVAL;
     }
     if (const char* v = std::getenv("LBM_XCD_REMAP")) e.xcd_remap = std::atoi(v) != 0;
+    // launch-bound sizes replay graphs of 64 steps (LBM_GRAPH_STEPS overrides;
+    // an even count, 0 disables)
+    e.graph_steps = N <= (1LL << 20) ? 64 : 0;
+    if (const char* v = std::getenv("LBM_GRAPH_STEPS")) {
+        const int gsteps = std::atoi(v);
+        e.graph_steps = gsteps > 0 ? (gsteps + 1) / 2 * 2 : 0;
+    }
     if (const char* v = std::getenv("LBM_ROWS_PER_BLOCK")) {
         const int r = std::atoi(v);
         e.rows_per_block = (r == 2 || r == 4) ? r : 1;
@@ -515,6 +557,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         n32[k] = (int32_t)e.lk_node_h[k];
     }
     e.has_geometry = false;
+    drop_graphs(e);
     free_run(e);
     int rc;
     if ((rc = upload(h, e.d_info, info.data(), info.size()))) return rc;
@@ -555,6 +598,8 @@ int lbm_update_links(lbm_t* h, const double* q, const double* wall_u) {
         if (wall_u)
             for (int a = 0; a < e.D; ++a) e.wall_u_h[k * e.D + a] = wall_u[p * e.D + a];
     }
+    HIPCHK(h, hipStreamSynchronize(e.stream));
+    drop_graphs(e);
     const int rc = upload_coefficients(h);
     if (rc) {
         e.q_h = q_old;
@@ -576,6 +621,7 @@ int lbm_set_parameters(lbm_t* h, const double* s, const double* g) {
         for (int a = 0; a < e.D; ++a)
             if (!std::isfinite(g[a])) return fail(h, LBM_EINVAL, "force not finite");
     HIPCHK(h, hipStreamSynchronize(e.stream));
+    drop_graphs(e);
     if (s)
         for (int k = 0; k < e.Q; ++k) e.s[k] = s[k];
     if (g)
@@ -635,7 +681,23 @@ int lbm_step(lbm_t* h, int64_t n) {
     if (n < 0) return fail(h, LBM_EINVAL, "negative step count");
     if (!e.initialized) return fail(h, LBM_ESTATE, "initialise before stepping");
     if (e.timing && n > 0) HIPCHK(h, hipEventRecord(e.ev0, e.stream));
-    for (int64_t s = 0; s < n; ++s) {
+    int64_t left = n;
+    // small domains are launch-bound: replay captured loops of graph_steps
+    // steps while no objective window is open
+    const bool obj_open = e.obj_kind != LBM_OBJ_NONE && e.t < e.obj_t1 && e.t + n > e.obj_t0;
+    if (e.graph_steps > 0 && !obj_open) {
+        while (left >= e.graph_steps) {
+            if (!e.graph_exec[e.cur]) {
+                const int rc = build_graph(h, e.cur);
+                if (rc) return rc;
+            }
+            HIPCHK(h, hipGraphLaunch(e.graph_exec[e.cur], e.stream));
+            e.t += e.graph_steps;
+            left -= e.graph_steps;
+            e.stepped = true;
+        }
+    }
+    for (; left > 0; --left) {
         const int rc = forward_step(h, e.buf[e.cur], e.buf[e.cur ^ 1], true);
         if (rc) return rc;
         e.cur ^= 1;
@@ -956,6 +1018,7 @@ int lbm_set_stream(lbm_t* h, void* stream) {
     if (!h) return LBM_EINVAL;
     Engine& e = h->e;
     HIPCHK(h, hipStreamSynchronize(e.stream));
+    drop_graphs(e);
     e.stream = stream ? (hipStream_t)stream : e.own_stream;
     return LBM_OK;
 }
@@ -1011,6 +1074,7 @@ int lbm_destroy(lbm_t* h) {
     if (!h) return LBM_OK;
     Engine& e = h->e;
     if (e.stream) (void)hipStreamSynchronize(e.stream);
+    drop_graphs(e);
     free_run(e);
     for (auto& b : e.buf) free_snap(b);
     free_dev(e.d_info);

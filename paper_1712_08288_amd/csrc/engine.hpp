@@ -33,6 +33,8 @@ struct Engine {
     int64_t S = 0;           // stride (values) between direction planes, >= N
     bool xcd_remap = false;  // deal contiguous row slabs to each XCD (measured slower)
     int rows_per_block = 1;  // step kernel: rows swept per block (1, 2 or 4)
+    int graph_steps = 0;     // >0: replay captured graphs of this many steps
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // by starting buffer
     double s[19] = {0};
     double rho0 = 1.0;
     double g[3] = {0, 0, 0};
