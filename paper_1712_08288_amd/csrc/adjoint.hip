@@ -102,7 +102,8 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
     uint32_t lb = blockIdx.x;
     if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t kind = lb < g.nblocks ? nm.wkind[lb * (BX / 64) + wid] : WAVE_IDLE;
+    const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
+    const uint32_t kind = wv.x;
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
@@ -121,10 +122,10 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
         });
     }
 
-    // one node; PLAIN: the whole wave is fluid without cut links
+    // one fluid node; PLAIN: the whole wave is fluid without cut links
     auto node = [&](auto plain_c, uint32_t info) {
         constexpr bool PLAIN = decltype(plain_c)::value;
-        const NodeLinks nl = PLAIN ? NodeLinks{0u, 0u} : node_links(nm, info, pos.n);
+        const NodeLinks nl = PLAIN ? NodeLinks{0u, 0u} : node_links(info, wv.y);
         // forward state f(y, t) and its velocity
         apply_links<L, T>(wa, p, nl, f);
         T sp[NP], dp[NP];
@@ -273,8 +274,17 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
     if (kind == WAVE_PLAIN) {
         node(std::true_type{}, 0u);
     } else if (kind == WAVE_MIXED) {
-        const uint32_t info = pos.in ? nm.info[pos.n] : 0x80000000u;
+        const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
         if (!is_solid(info)) node(std::false_type{}, info);
+    }
+    // the solid lanes of a mixed wave store NaN (nothing reads lambda at
+    // solid nodes) so that the wave writes whole lines of lam_out: partial
+    // lines cost HBM read-modify-write cycles
+    if (kind == WAVE_MIXED && pos.in && is_solid(nm.info[pos.n])) {
+        unroll<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));
+        });
     }
 
     // lb is uniform over the block, so the barrier inside is block-uniform
@@ -391,7 +401,7 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const void* lam_i
         hipLaunchKernelGGL(kern, dim3(g.chunk ? g.chunk * NXCD : g.nblocks), dim3(BX), 0,
                            e.stream, (const T*)fwd.f, (const T*)fwd.wa,
                            (const T*)lam_in, (T*)lam_out,
-                           NodeMeta{e.d_info, e.d_base, e.d_wkind}, e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag, e.d_gq,
+                           NodeMeta{e.d_info, e.d_wave}, e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag, e.d_gq,
                            e.d_gphi, e.d_gglob, g, adj_params<L, T>(e), a);
         return hipGetLastError();
     });

@@ -512,43 +512,42 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         }
         e.ibar_is_link[k] = (mask[e.lk_node_h[k]] >> ib) & 1u;
     }
-    // per node: bit 31 solid, else the link-direction mask; first link index
-    std::vector<uint32_t> info(N), base(N, 0u);
-    {
-        int64_t k = 0;
-        for (int64_t n = 0; n < N; ++n) {
-            if (solid[n]) {
-                info[n] = 0x80000000u;
-                continue;
-            }
-            info[n] = mask[n];
-            base[n] = (uint32_t)k;
-            k += __builtin_popcount(mask[n]);
-        }
-    }
-    // per 64-node wave of a node launch (rows in chunks of kBlock threads):
-    // idle (no fluid), plain (64 fluid nodes without links) or mixed
-    std::vector<uint32_t> wkind;
+    // per node: bit 31 solid, else the link-direction mask and, in bits
+    // 19..30, the number of links at earlier nodes of its wave; per 64-node
+    // wave of a node launch (rows in chunks of kBlock threads): its kind --
+    // idle (no fluid), plain (64 fluid nodes without links) or mixed -- and
+    // the index of its first link (links are sorted by node)
+    std::vector<uint32_t> info(N);
+    std::vector<uint2> wave;
     {
         const int64_t bpr = (e.nx + lbe::kBlock - 1) / lbe::kBlock;
         const int64_t nb = bpr * e.ny * e.nz;
         const int wpb = lbe::kBlock / lbe::kWave;
-        wkind.assign(nb * wpb, 2u);
+        wave.assign(nb * wpb, make_uint2(2u, 0u));
+        int64_t k = 0;
         for (int64_t lb = 0; lb < nb; ++lb) {
             const int64_t row = lb / bpr, xb = lb % bpr;
             for (int w = 0; w < wpb; ++w) {
                 const int64_t x0 = xb * lbe::kBlock + w * lbe::kWave;
                 const int64_t nin = std::max<int64_t>(0, std::min<int64_t>(lbe::kWave, e.nx - x0));
                 bool any_fluid = false, all_plain = nin == lbe::kWave;
+                const int64_t k0 = k;
                 for (int64_t l = 0; l < nin; ++l) {
                     const int64_t n = row * e.nx + x0 + l;
-                    const bool fl = !solid[n];
-                    any_fluid = any_fluid || fl;
-                    all_plain = all_plain && fl && mask[n] == 0u;
+                    if (solid[n]) {
+                        info[n] = 0x80000000u;
+                        all_plain = false;
+                        continue;
+                    }
+                    any_fluid = true;
+                    all_plain = all_plain && mask[n] == 0u;
+                    info[n] = mask[n] | ((uint32_t)(k - k0) << 19);
+                    k += __builtin_popcount(mask[n]);
                 }
-                wkind[lb * wpb + w] = !any_fluid ? 2u : (all_plain ? 1u : 0u);
+                wave[lb * wpb + w] = make_uint2(!any_fluid ? 2u : (all_plain ? 1u : 0u), (uint32_t)k0);
             }
         }
+        if (k != n_links) return fail(h, LBM_EGEOM, "link count mismatch");
     }
     std::vector<uint8_t> d8(n_links);
     std::vector<int32_t> n32(n_links);
@@ -561,8 +560,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     free_run(e);
     int rc;
     if ((rc = upload(h, e.d_info, info.data(), info.size()))) return rc;
-    if ((rc = upload(h, e.d_base, base.data(), base.size()))) return rc;
-    if ((rc = upload(h, e.d_wkind, wkind.data(), wkind.size()))) return rc;
+    if ((rc = upload(h, e.d_wave, wave.data(), wave.size()))) return rc;
     if ((rc = upload(h, e.d_lkdir, d8.data(), d8.size()))) return rc;
     if ((rc = upload(h, e.d_lknode, n32.data(), n32.size()))) return rc;
     if ((rc = upload(h, e.d_lktag, e.tag_h.data(), e.tag_h.size()))) return rc;
@@ -1078,8 +1076,7 @@ int lbm_destroy(lbm_t* h) {
     free_run(e);
     for (auto& b : e.buf) free_snap(b);
     free_dev(e.d_info);
-    free_dev(e.d_base);
-    free_dev(e.d_wkind);
+    free_dev(e.d_wave);
     free_dev(e.d_lkdir);
     free_dev(e.d_lknode);
     free_dev(e.d_lktag);

@@ -54,9 +54,9 @@ struct Engine {
     std::vector<double> q_h, wall_u_h;  // sorted, wall_u (L, D)
     std::vector<int32_t> tag_h;
 
-    uint32_t* d_info = nullptr;         // per node: bit 31 solid, bits 0..Q-1 link directions
-    uint32_t* d_base = nullptr;         // per node: first link index
-    uint32_t* d_wkind = nullptr;        // per 64-node wave of a node launch
+    uint32_t* d_info = nullptr;         // per node: bit 31 solid, bits 19..30 link offset
+                                        // within the wave, bits 0..Q-1 link directions
+    uint2* d_wave = nullptr;            // per 64-node wave of a node launch: kind, first link
     uint8_t* d_lkdir = nullptr;
     int32_t* d_lknode = nullptr;
     int32_t* d_lktag = nullptr;

@@ -42,9 +42,12 @@ __device__ __forceinline__ void link_tail(const NodeLinks& nl, const T (&fpre)[L
 }
 
 // Waves are classified on the host (one scalar load per wave): a wave whose
-// 64 nodes are all fluid and free of cut links issues its 19 pulls at once;
-// a mixed wave first reads each node's link mask, skips solid nodes and the
-// planes of its link directions; a wave without fluid exits.
+// 64 nodes are all fluid and free of cut links issues its pulls at once and
+// collides; a wave without fluid exits.  A mixed wave reads every plane as
+// if its nodes were plain (solid and cut-link slots included) and replaces
+// the cut-link directions from their slots.  Its solid lanes store NaN into
+// their own slots, which nothing reads: a full store keeps every written
+// cache line whole (partial lines cost HBM read-modify-write cycles).
 template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
@@ -54,7 +57,8 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
     uint32_t lb = blockIdx.x;
     if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t kind = lb < g.nblocks ? nm.wkind[lb * (BX / 64) + wid] : WAVE_IDLE;
+    const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
+    const uint32_t kind = wv.x;
     double ux_local = 0.0;
     if (kind == WAVE_PLAIN) {
         T f[L::Q];
@@ -67,13 +71,14 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             st_nt(B + (size_t)i * g.S, pos.n, f[i]);
         });
     } else if (kind == WAVE_MIXED) {
-        // the plane reads are issued before the node's metadata arrives
-        // (measured faster than waiting for it, despite reading solid slots)
+        // the info word is requested first, the plane reads are issued
+        // without waiting for it
+        const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
         T f[L::Q];
-        if (pos.in) pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
-        const uint32_t info = pos.in ? nm.info[pos.n] : 0x80000000u;
-        if (!is_solid(info)) {
-            const NodeLinks nl = node_links(nm, info, pos.n);
+        if (pos.in) {
+            pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
+            const bool sol = is_solid(info);
+            const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, wv.y);
             apply_links<L, T>(waA, p, nl, f);
             T fpre[L::Q];
             unroll<L::Q>([&](auto I) {
@@ -82,10 +87,11 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             });
             Macro<L, T> mac;
             collide<L, T>(f, p, mac);
-            ux_local = (double)mac.u[0];
+            if (!sol) ux_local = (double)mac.u[0];
+            const T nan = (T)__builtin_nan("");
             unroll<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                st_nt(B + (size_t)i * g.S, pos.n, f[i]);
+                st_nt(B + (size_t)i * g.S, pos.n, sol ? nan : f[i]);
             });
             if (nl.mask) link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0);
         }
@@ -124,7 +130,7 @@ k_step_rows(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ wa
     {
         const NodePos q = pos_of(rg * R);
         if (q.in) pull_planes<L, T, XB>(A, g, q, p, NodeLinks{0u, 0u}, buf[0]);
-        info[0] = q.in ? nm.info[q.n] : 0x80000000u;
+        info[0] = q.in ? nm.info[q.n] : kInfoSolid;
     }
     unroll<R>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
@@ -133,11 +139,12 @@ k_step_rows(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ wa
         if constexpr (r + 1 < R) {
             const NodePos q = pos_of(row + 1);
             if (q.in) pull_planes<L, T, XB>(A, g, q, p, NodeLinks{0u, 0u}, buf[nb]);
-            info[nb] = q.in ? nm.info[q.n] : 0x80000000u;
+            info[nb] = q.in ? nm.info[q.n] : kInfoSolid;
         }
         const NodePos pos = pos_of(row);
-        const uint32_t kind = row < nrows ? nm.wkind[(row * g.bpr + xb) * (BX / 64) + wid]
-                                          : (uint32_t)WAVE_IDLE;
+        const uint2 wv = row < nrows ? nm.wave[(row * g.bpr + xb) * (BX / 64) + wid]
+                                     : uint2{WAVE_IDLE, 0u};
+        const uint32_t kind = wv.x;
         T (&f)[L::Q] = buf[cb];
         if (kind == WAVE_PLAIN) {
             Macro<L, T> mac;
@@ -147,8 +154,9 @@ k_step_rows(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ wa
                 constexpr int i = decltype(I)::value;
                 st_nt(B + (size_t)i * g.S, pos.n, f[i]);
             });
-        } else if (kind == WAVE_MIXED && !is_solid(info[cb])) {
-            const NodeLinks nl = node_links(nm, info[cb], pos.n);
+        } else if (kind == WAVE_MIXED && pos.in) {
+            const bool sol = is_solid(info[cb]);
+            const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info[cb], wv.y);
             apply_links<L, T>(waA, p, nl, f);
             T fpre[L::Q];
             unroll<L::Q>([&](auto I) {
@@ -157,10 +165,11 @@ k_step_rows(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ wa
             });
             Macro<L, T> mac;
             collide<L, T>(f, p, mac);
-            ux_local += (double)mac.u[0];
+            if (!sol) ux_local += (double)mac.u[0];
+            const T nan = (T)__builtin_nan("");
             unroll<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                st_nt(B + (size_t)i * g.S, pos.n, f[i]);
+                st_nt(B + (size_t)i * g.S, pos.n, sol ? nan : f[i]);
             });
             if (nl.mask) link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0);
         }
@@ -182,7 +191,7 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
     if (!pos.in) return;
     const uint32_t info = nm.info[pos.n];
     if (is_solid(info)) return;
-    const NodeLinks nl = node_links(nm, info, pos.n);
+    const NodeLinks nl = node_links(nm, g, info, pos.n);
     double f[L::Q];
     if (df) {
         unroll<L::Q>([&](auto I) {
@@ -243,7 +252,7 @@ k_observe(const T* __restrict__ A, const T* __restrict__ wa, NodeMeta nm,
             for (int i = 0; i < L::Q; ++i) df[(size_t)i * g.N + pos.n] = nan;
         return;
     }
-    const NodeLinks nl = node_links(nm, info, pos.n);
+    const NodeLinks nl = node_links(nm, g, info, pos.n);
     T f[L::Q];
     pull<L, T, XB, true>(A, wa, g, pos, p, nl, f);
     if (df) {
@@ -274,10 +283,10 @@ __global__ void __launch_bounds__(BX)
 k_mass(const T* __restrict__ A, const T* __restrict__ wa, NodeMeta nm,
        Grid g, Params<L, T> p, double* __restrict__ partials) {
     const NodePos pos = node_of_thread(g);
-    const uint32_t info = pos.in ? nm.info[pos.n] : 0x80000000u;
+    const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
     double r = 0, j[3] = {0, 0, 0};
     if (!is_solid(info)) {
-        const NodeLinks nl = node_links(nm, info, pos.n);
+        const NodeLinks nl = node_links(nm, g, info, pos.n);
         T f[L::Q];
         pull<L, T, XB, true>(A, wa, g, pos, p, nl, f);
         unroll<L::Q>([&](auto I) {
@@ -431,7 +440,7 @@ int64_t step_blocks(const Engine& e) {
     return g.nblocks;
 }
 
-NodeMeta meta(const Engine& e) { return NodeMeta{e.d_info, e.d_base, e.d_wkind}; }
+NodeMeta meta(const Engine& e) { return NodeMeta{e.d_info, e.d_wave}; }
 int64_t link_blocks(const Engine& e) { return (e.n_links + BX - 1) / BX; }
 
 template <class L, class T>

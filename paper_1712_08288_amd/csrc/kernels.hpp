@@ -306,23 +306,45 @@ struct NodeLinks {
     uint32_t base;   // index of the node's first link
 };
 
-// Per-node and per-wave metadata of the geometry.
+// Per-node and per-wave metadata of the geometry.  Links are sorted by node,
+// then direction, so the links of one 64-node wave of a node launch are
+// contiguous: a node's first link is its wave's first link plus the count of
+// links at the wave's earlier nodes, kept in bits 19..30 of the info word
+// (at most 64 * (Q - 1) = 1152 links per wave).
 struct NodeMeta {
-    const uint32_t* __restrict__ info;   // bit 31: solid; bits 0..Q-1: cut-link directions
-    const uint32_t* __restrict__ base;   // first link of the node (links sorted by direction)
-    const uint32_t* __restrict__ wkind;  // per 64-node wave of a node launch:
-                                         // 0 mixed, 1 all fluid without links, 2 no fluid
+    const uint32_t* __restrict__ info;   // bit 31: solid; bits 19..30: link offset
+                                         // within the wave; bits 0..Q-1: cut-link directions
+    const uint2* __restrict__ wave;      // per wave: x = kind (0 mixed, 1 all fluid
+                                         // without links, 2 no fluid), y = first link
 };
 
 enum WaveKind : uint32_t { WAVE_MIXED = 0, WAVE_PLAIN = 1, WAVE_IDLE = 2 };
 
+constexpr uint32_t kInfoSolid = 0x80000000u;
+constexpr uint32_t kInfoMask = (1u << 19) - 1u;
+constexpr int kInfoOffsetShift = 19;
+constexpr uint32_t kInfoOffsetMax = 0xFFFu;
+
 __device__ __forceinline__ bool is_solid(uint32_t info) { return (info >> 31) != 0; }
 
-__device__ __forceinline__ NodeLinks node_links(const NodeMeta& nm, uint32_t info, uint32_t n) {
+// the wave of a node launch that holds node n (kBlock-thread blocks, bpr per row)
+__device__ __forceinline__ uint32_t wave_of_node(const Grid& g, uint32_t n) {
+    const uint32_t row = n / g.nx, x = n - row * g.nx;
+    return row * g.bpr * (BX / 64) + x / 64;
+}
+
+// links of a node whose wave's first link index is known
+__device__ __forceinline__ NodeLinks node_links(uint32_t info, uint32_t wave_base) {
     NodeLinks r;
-    r.mask = info & 0x7FFFFFFFu;
-    r.base = r.mask ? nm.base[n] : 0u;
+    r.mask = info & kInfoMask;
+    r.base = wave_base + ((info >> kInfoOffsetShift) & kInfoOffsetMax);
     return r;
+}
+
+__device__ __forceinline__ NodeLinks node_links(const NodeMeta& nm, const Grid& g,
+                                                uint32_t info, uint32_t n) {
+    if (!(info & kInfoMask)) return NodeLinks{0u, 0u};
+    return node_links(info, nm.wave[wave_of_node(g, n)].y);
 }
 
 __device__ __forceinline__ uint32_t link_index(const NodeLinks& nl, int i) {
