@@ -103,7 +103,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
     if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
-    const uint32_t kind = wv.x;
+    const uint32_t kind = wave_kind(wv);
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;

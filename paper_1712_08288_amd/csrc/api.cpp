@@ -363,10 +363,6 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
         const int gsteps = std::atoi(v);
         e.graph_steps = gsteps > 0 ? (gsteps + 1) / 2 * 2 : 0;
     }
-    if (const char* v = std::getenv("LBM_ROWS_PER_BLOCK")) {
-        const int r = std::atoi(v);
-        e.rows_per_block = (r == 2 || r == 4) ? r : 1;
-    }
     for (int k = 0; k < Q; ++k) e.s[k] = s[k];
     e.rho0 = rho0;
     for (int a = 0; a < 3; ++a) e.g[a] = (g && a < D) ? g[a] : 0.0;
@@ -544,7 +540,8 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
                     info[n] = mask[n] | ((uint32_t)(k - k0) << 19);
                     k += __builtin_popcount(mask[n]);
                 }
-                wave[lb * wpb + w] = make_uint2(!any_fluid ? 2u : (all_plain ? 1u : 0u), (uint32_t)k0);
+                const uint32_t kind = !any_fluid ? 2u : (all_plain ? 1u : 0u);
+                wave[lb * wpb + w] = make_uint2(kind | ((uint32_t)(k - k0) << 2), (uint32_t)k0);
             }
         }
         if (k != n_links) return fail(h, LBM_EGEOM, "link count mismatch");

@@ -32,7 +32,6 @@ struct Engine {
     int64_t nx = 0, ny = 0, nz = 0, N = 0;
     int64_t S = 0;           // stride (values) between direction planes, >= N
     bool xcd_remap = false;  // deal contiguous row slabs to each XCD (measured slower)
-    int rows_per_block = 1;  // step kernel: rows swept per block (1, 2 or 4)
     int graph_steps = 0;     // >0: replay captured graphs of this many steps
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // by starting buffer
     double s[19] = {0};

@@ -17,28 +17,91 @@ static_assert(BX == kBlock && BX % 64 == 0, "node launches use kBlock-thread blo
 // ----------------------------------------------------------------------------
 // the step: pull, collide, store, and evaluate Eq. (213) for the node's links
 
-// Eq. (213) for every cut link of one node, from its pre-collision values
-// (fpre) and post-collision values (f), into the link slots of the next step
+// The links of one wave are contiguous (sorted by node, then direction), so
+// the wave handles its first 64 cooperatively: lane l carries the wave's
+// link l, and values move between that lane and the lane of the link's
+// fluid node through a per-wave LDS slab.  Slot reads, coefficient reads and
+// slot writes are then coalesced, and the slot reads need no per-node
+// metadata, so they are issued with the plane reads.  Links past the 64th
+// (rare: long wall rows) are read and written by their node's lane directly;
+// straight-line code keeps the register count of the step at its minimum.
+template <class T>
+struct LinkStage {
+    T v[4][64];
+};
+
+// order the wave's LDS writes before the other lanes' reads (the LDS executes
+// one wave's instructions in order; this keeps the compiler from moving them)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pulled values of cut-link directions: f_i(x_f, t) = wa[k].  nl.base is the
+// node's first link relative to the wave's first link wbase; wa0 =
+// wa[wbase + lane] for lanes below the wave's link count (else 0), read in
+// advance by every lane.
 template <class L, class T>
-__device__ __forceinline__ void link_tail(const NodeLinks& nl, const T (&fpre)[L::Q],
-                                          const T (&f)[L::Q],
-                                          const LinkCoef* __restrict__ lkcoef,
-                                          T* __restrict__ waB, double c0) {
-    uint32_t k = nl.base;
-    unroll<L::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int ib = TAB<L>.opp[i];
-        if constexpr (i > 0) {
-            const uint32_t bit = (nl.mask >> i) & 1u;
-            if (bit) {
-                const LinkCoef c = lkcoef[k];
-                const double v = c0 * (double)fpre[i] + c.c1 * (double)fpre[ib] +
-                                 c.c2 * (double)f[i] + c.c3 * (double)f[ib] + c.wall;
-                waB[k] = (T)v;
+__device__ __forceinline__ void wave_link_values(const T* __restrict__ wa, uint32_t wbase,
+                                                 uint32_t lane, T wa0, const NodeLinks& nl,
+                                                 LinkStage<T>& st, T (&f)[L::Q]) {
+    st.v[0][lane] = wa0;
+    wave_lds_sync();
+    if (nl.mask) {
+        uint32_t k = nl.base;
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0) {
+                const uint32_t bit = (nl.mask >> i) & 1u;
+                if (bit) f[i] = k < 64u ? st.v[0][k] : wa[wbase + k];
+                k += bit;
             }
-            k += bit;
-        }
-    });
+        });
+    }
+    wave_lds_sync();
+}
+
+// Eq. (213) for every cut link of the wave, from the pre-collision (fpre)
+// and post-collision (f) values at its fluid node, into the link slots of
+// the next step; nlw links in the wave.
+template <class L, class T>
+__device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fpre)[L::Q],
+                                               const T (&f)[L::Q],
+                                               const LinkCoef* __restrict__ lkcoef,
+                                               T* __restrict__ waB, double c0d, uint32_t wbase,
+                                               uint32_t nlw, uint32_t lane, LinkStage<T>& st) {
+    if (nl.mask) {
+        uint32_t k = nl.base;
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            constexpr int ib = TAB<L>.opp[i];
+            if constexpr (i > 0) {
+                const uint32_t bit = (nl.mask >> i) & 1u;
+                if (bit) {
+                    if (k < 64u) {
+                        st.v[0][k] = fpre[i];
+                        st.v[1][k] = fpre[ib];
+                        st.v[2][k] = f[i];
+                        st.v[3][k] = f[ib];
+                    } else {
+                        const LinkCoef c = lkcoef[wbase + k];
+                        const double v = c0d * (double)fpre[i] + c.c1 * (double)fpre[ib] +
+                                         c.c2 * (double)f[i] + c.c3 * (double)f[ib] + c.wall;
+                        waB[wbase + k] = (T)v;
+                    }
+                }
+                k += bit;
+            }
+        });
+    }
+    wave_lds_sync();
+    if (lane < nlw) {
+        const LinkCoef c = lkcoef[wbase + lane];
+        const double v = c0d * (double)st.v[0][lane] + c.c1 * (double)st.v[1][lane] +
+                         c.c2 * (double)st.v[2][lane] + c.c3 * (double)st.v[3][lane] + c.wall;
+        waB[wbase + lane] = (T)v;
+    }
 }
 
 // Waves are classified on the host (one scalar load per wave): a wave whose
@@ -53,12 +116,13 @@ __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
        T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
        Grid g, Params<L, T> p, double* __restrict__ acc_ux, double w_ux) {
+    __shared__ LinkStage<T> stage[BX / 64];
     const NodePos pos = node_of_thread(g);
     uint32_t lb = blockIdx.x;
     if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
-    const uint32_t kind = wv.x;
+    const uint32_t kind = wave_kind(wv);
     double ux_local = 0.0;
     if (kind == WAVE_PLAIN) {
         T f[L::Q];
@@ -71,112 +135,42 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             st_nt(B + (size_t)i * g.S, pos.n, f[i]);
         });
     } else if (kind == WAVE_MIXED) {
-        // the info word is requested first, the plane reads are issued
-        // without waiting for it
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t nlw = wave_links(wv), wbase = wv.y;
+        // slot reads and the info word first, the plane reads without
+        // waiting for either
+        const T wa0 = lane < nlw ? waA[wbase + lane] : T(0);
         const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
         T f[L::Q];
         if (pos.in) {
             pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
-            const bool sol = is_solid(info);
-            const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, wv.y);
-            apply_links<L, T>(waA, p, nl, f);
-            T fpre[L::Q];
-            unroll<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                fpre[i] = f[i];
-            });
-            Macro<L, T> mac;
-            collide<L, T>(f, p, mac);
+        } else {
+            unroll<L::Q>([&](auto I) { f[decltype(I)::value] = T(0); });
+        }
+        const bool sol = is_solid(info);
+        const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, 0u);
+        wave_link_values<L, T>(waA, wbase, lane, wa0, nl, stage[wid], f);
+        if (p.c1d) complete_two_node<L, T>(p.c1d + wbase, nl, f);
+        T fpre[L::Q];
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            fpre[i] = f[i];
+        });
+        Macro<L, T> mac;
+        collide<L, T>(f, p, mac);
+        if (pos.in) {
             if (!sol) ux_local = (double)mac.u[0];
             const T nan = (T)__builtin_nan("");
             unroll<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 st_nt(B + (size_t)i * g.S, pos.n, sol ? nan : f[i]);
             });
-            if (nl.mask) link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0);
         }
+        wave_link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0, wbase, nlw, lane, stage[wid]);
     }
     if (acc_ux) {   // uniform over the launch
         const double s = block_sum(ux_local);
         if (threadIdx.x == 0 && lb < g.nblocks) acc_ux[lb] += w_ux * s;
-    }
-}
-
-// The same step with each block sweeping R consecutive rows of one x-chunk:
-// the plane reads (and link-mask word) of row r+1 are issued before row r is
-// collided, so a wave keeps loads in flight through its compute phase.
-template <class L, class T, int XB, int R>
-__global__ void __launch_bounds__(BX)
-k_step_rows(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
-            T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
-            Grid g, Params<L, T> p, double* __restrict__ acc_ux, double w_ux) {
-    const uint32_t nrows = g.ny * g.nz;
-    const uint32_t rg = blockIdx.x / g.bpr;              // group of R rows
-    const uint32_t xb = blockIdx.x - rg * g.bpr;
-    const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t ix = xb * BX + threadIdx.x;
-    auto pos_of = [&](uint32_t row) {
-        NodePos q;
-        q.ix = ix;
-        q.iy = row % g.ny;
-        q.iz = row / g.ny;
-        q.in = row < nrows && ix < g.nx;
-        q.n = ix + g.nx * row;
-        return q;
-    };
-    double ux_local = 0.0;
-    T buf[2][L::Q];
-    uint32_t info[2];
-    {
-        const NodePos q = pos_of(rg * R);
-        if (q.in) pull_planes<L, T, XB>(A, g, q, p, NodeLinks{0u, 0u}, buf[0]);
-        info[0] = q.in ? nm.info[q.n] : kInfoSolid;
-    }
-    unroll<R>([&](auto RR) {
-        constexpr int r = decltype(RR)::value;
-        constexpr int cb = r & 1, nb = cb ^ 1;
-        const uint32_t row = rg * R + r;
-        if constexpr (r + 1 < R) {
-            const NodePos q = pos_of(row + 1);
-            if (q.in) pull_planes<L, T, XB>(A, g, q, p, NodeLinks{0u, 0u}, buf[nb]);
-            info[nb] = q.in ? nm.info[q.n] : kInfoSolid;
-        }
-        const NodePos pos = pos_of(row);
-        const uint2 wv = row < nrows ? nm.wave[(row * g.bpr + xb) * (BX / 64) + wid]
-                                     : uint2{WAVE_IDLE, 0u};
-        const uint32_t kind = wv.x;
-        T (&f)[L::Q] = buf[cb];
-        if (kind == WAVE_PLAIN) {
-            Macro<L, T> mac;
-            collide<L, T>(f, p, mac);
-            ux_local += (double)mac.u[0];
-            unroll<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                st_nt(B + (size_t)i * g.S, pos.n, f[i]);
-            });
-        } else if (kind == WAVE_MIXED && pos.in) {
-            const bool sol = is_solid(info[cb]);
-            const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info[cb], wv.y);
-            apply_links<L, T>(waA, p, nl, f);
-            T fpre[L::Q];
-            unroll<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                fpre[i] = f[i];
-            });
-            Macro<L, T> mac;
-            collide<L, T>(f, p, mac);
-            if (!sol) ux_local += (double)mac.u[0];
-            const T nan = (T)__builtin_nan("");
-            unroll<L::Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                st_nt(B + (size_t)i * g.S, pos.n, sol ? nan : f[i]);
-            });
-            if (nl.mask) link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0);
-        }
-    });
-    if (acc_ux) {   // uniform over the launch; one partial per (row group, x-chunk)
-        const double s = block_sum(ux_local);
-        if (threadIdx.x == 0) acc_ux[blockIdx.x] += w_ux * s;
     }
 }
 
@@ -432,12 +426,7 @@ unsigned launch_blocks(const Grid& g) {
 }
 
 int64_t step_blocks(const Engine& e) {
-    const Grid g = make_grid(e);
-    if (e.rows_per_block > 1) {
-        const int64_t nrows = (int64_t)g.ny * g.nz;
-        return (int64_t)g.bpr * ((nrows + e.rows_per_block - 1) / e.rows_per_block);
-    }
-    return g.nblocks;
+    return make_grid(e).nblocks;
 }
 
 NodeMeta meta(const Engine& e) { return NodeMeta{e.d_info, e.d_wave}; }
@@ -488,21 +477,6 @@ hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        if (e.rows_per_block > 1) {
-            const uint32_t nrows = g.ny * g.nz;
-            const int R = e.rows_per_block;
-            const unsigned nb = g.bpr * ((nrows + R - 1) / R);
-            auto launch = [&](auto rr) {
-                constexpr int RR = decltype(rr)::value;
-                hipLaunchKernelGGL((k_step_rows<L, T, XB, RR>), dim3(nb), dim3(BX), 0, e.stream,
-                                   (const T*)in.f, (T*)out.f, (const T*)in.wa, (T*)out.wa,
-                                   meta(e), e.d_lkcoef, g, make_params<L, T>(e), obj.acc_ux,
-                                   obj.w_ux);
-            };
-            if (R == 2) launch(std::integral_constant<int, 2>{});
-            else launch(std::integral_constant<int, 4>{});
-            return hipGetLastError();
-        }
         hipLaunchKernelGGL((k_step<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
                            (T*)out.wa, meta(e), e.d_lkcoef, g,

@@ -314,8 +314,9 @@ struct NodeLinks {
 struct NodeMeta {
     const uint32_t* __restrict__ info;   // bit 31: solid; bits 19..30: link offset
                                          // within the wave; bits 0..Q-1: cut-link directions
-    const uint2* __restrict__ wave;      // per wave: x = kind (0 mixed, 1 all fluid
-                                         // without links, 2 no fluid), y = first link
+    const uint2* __restrict__ wave;      // per wave: x = kind (bits 0..1: 0 mixed,
+                                         // 1 all fluid without links, 2 no fluid) and
+                                         // link count (bits 2..31), y = first link
 };
 
 enum WaveKind : uint32_t { WAVE_MIXED = 0, WAVE_PLAIN = 1, WAVE_IDLE = 2 };
@@ -326,6 +327,8 @@ constexpr int kInfoOffsetShift = 19;
 constexpr uint32_t kInfoOffsetMax = 0xFFFu;
 
 __device__ __forceinline__ bool is_solid(uint32_t info) { return (info >> 31) != 0; }
+__device__ __forceinline__ uint32_t wave_kind(uint2 w) { return w.x & 3u; }
+__device__ __forceinline__ uint32_t wave_links(uint2 w) { return w.x >> 2; }
 
 // the wave of a node launch that holds node n (kBlock-thread blocks, bpr per row)
 __device__ __forceinline__ uint32_t wave_of_node(const Grid& g, uint32_t n) {
@@ -373,9 +376,30 @@ __device__ __forceinline__ void pull_planes(const T* __restrict__ A, const Grid&
     });
 }
 
+// Eq. (211): a cut-link slot holds the terms at t only; the pull completes it
+// with c1 f_ibar(x, t), the value just advected from x + e_i.  c1d is indexed
+// like nl.base.
+template <class L, class T>
+__device__ __forceinline__ void complete_two_node(const double* __restrict__ c1d,
+                                                  const NodeLinks& nl, T (&f)[L::Q]) {
+    if (!nl.mask) return;
+    uint32_t kk = nl.base;
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ib = TAB<L>.opp[i];
+        if constexpr (i > 0) {
+            const uint32_t bit = (nl.mask >> i) & 1u;
+            if (bit) {
+                const double c = c1d[kk];
+                if (c != 0.0) f[i] = (T)((double)f[i] + c * (double)f[ib]);
+            }
+            kk += bit;
+        }
+    });
+}
+
 // Cut-link directions take their link slot (links are sorted by direction,
-// so a running index replaces a popcount); with Eq. (211) the slot is
-// completed by c1 f_ibar(x, t), the value just advected from x + e_i.
+// so a running index replaces a popcount).
 template <class L, class T>
 __device__ __forceinline__ void apply_links(const T* __restrict__ wa, const Params<L, T>& p,
                                             const NodeLinks& nl, T (&f)[L::Q]) {
@@ -389,21 +413,7 @@ __device__ __forceinline__ void apply_links(const T* __restrict__ wa, const Para
             k += bit;
         }
     });
-    if (p.c1d) {
-        uint32_t kk = nl.base;
-        unroll<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int ib = TAB<L>.opp[i];
-            if constexpr (i > 0) {
-                const uint32_t bit = (nl.mask >> i) & 1u;
-                if (bit) {
-                    const double c = p.c1d[kk];
-                    if (c != 0.0) f[i] = (T)((double)f[i] + c * (double)f[ib]);
-                }
-                kk += bit;
-            }
-        });
-    }
+    if (p.c1d) complete_two_node<L, T>(p.c1d, nl, f);
 }
 
 // Pull the pre-collision state f(x, t) of one fluid node.
