@@ -86,6 +86,62 @@ __device__ __forceinline__ void block_accumulate(const double (&v)[NC], double* 
     }
 }
 
+// Lattice data of a direction known only at run time (link lanes).
+template <class L>
+__device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w) {
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if (i == d) {
+            e[0] = L::E[i][0];
+            e[1] = L::E[i][1];
+            e[2] = L::E[i][2];
+            w = L::W[i];
+        }
+    });
+}
+
+// Link k = (y, i) of a mixed wave, handled by the lane of its node y: the
+// contribution of its adjoint a_k to mu and to lambda(y, t), and its
+// gradients.  Used for links past the 64th of a wave (the first 64 go
+// through the wave's LDS slab).
+template <class L, class T, int i>
+__device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict__ lam_in,
+                                                uint32_t n, uint32_t S,
+                                                const LinkCoef* __restrict__ lkcoef,
+                                                const LinkDeriv* __restrict__ lkderiv,
+                                                const double* __restrict__ lkc4,
+                                                const int32_t* __restrict__ lktag,
+                                                double* __restrict__ gq, double* __restrict__ gphi,
+                                                const Params<L, T>& p, const AdjArgs& a,
+                                                const T (&f)[L::Q], const T (&fp)[L::Q],
+                                                T (&mu)[L::Q], T (&dir)[L::Q]) {
+    constexpr int ib = TAB<L>.opp[i];
+    double ak = (double)ld(lam_in + (size_t)i * S, n);
+    if (a.obj_kind == 1 && L::E[i][0] != 0 && lktag[k] == a.obj_tag) {
+        // drag: (e_ibar)_x (f'_ibar(y,t) + f_i(y,t+1))
+        const double dfx = -(double)L::E[i][0] * a.w_force;
+        ak += dfx;
+        mu[ib] += (T)dfx;
+    }
+    const LinkCoef c = lkcoef[k];
+    const LinkDeriv dc = lkderiv[k];
+    mu[i] += (T)(c.c2 * ak);
+    mu[ib] += (T)(c.c3 * ak);
+    dir[i] += (T)(p.c0 * ak);
+    dir[ib] += (T)(c.c1 * ak);
+    gq[k] += ak * (dc.d1 * (double)f[ib] + dc.d2 * (double)fp[i] + dc.d3 * (double)fp[ib] +
+                   dc.dwall);
+    const double c4w = lkc4[k] * 3.0 * L::W[i] * p.rho0_d * ak;
+#pragma unroll
+    for (int al = 0; al < L::D; ++al)
+        if (L::E[i][al] != 0) gphi[(size_t)k * L::D + al] += c4w * L::E[i][al];
+}
+
+// Mixed waves handle their cut links cooperatively (see LinkStage): the
+// link lanes read the link data and a_k = lambda_i(y, t+1) (plus the drag
+// term) with coalesced loads and hand c2 a_k, c3 a_k (+ drag), c0 a_k and
+// c1 a_k to the node's lane through LDS; the node's lane hands back
+// f_ibar(y,t), f'_i(y,t) and f'_ibar(y,t) for the link lanes' gradients.
 template <class L, class T, int XB, bool WANT_DS>
 __global__ void __launch_bounds__(BX)
 k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
@@ -93,17 +149,22 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
           NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
           const LinkDeriv* __restrict__ lkderiv,
           const double* __restrict__ lkc4, const int32_t* __restrict__ lktag,
+          const uint8_t* __restrict__ lkdir, const int32_t* __restrict__ lknode,
           double* __restrict__ gq, double* __restrict__ gphi,
           double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
     constexpr int Q = L::Q, D = L::D, NP = NPAIR<L>;
     constexpr int NC = D + Q;                 // layout of the per-block sums
     constexpr int NR = WANT_DS ? NC : D;      // columns reduced here
+    __shared__ LinkStage<T> stage[BX / 64];
     const NodePos pos = node_of_thread(g);
     uint32_t lb = blockIdx.x;
     if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
     const uint32_t kind = wave_kind(wv);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nlw = wave_links(wv), wbase = wv.y;
+    LinkStage<T>& st = stage[wid];
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
@@ -120,14 +181,20 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
             constexpr int i = decltype(I)::value;
             lg[i] = ld(lam_in + (size_t)i * g.S, i == 0 ? pos.n : ps.template dst<L, i>());
         });
+    } else {
+        unroll<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            f[i] = T(0);
+            lg[i] = T(0);
+        });
     }
 
-    // one fluid node; PLAIN: the whole wave is fluid without cut links
-    auto node = [&](auto plain_c, uint32_t info) {
+    // one fluid node; PLAIN: the whole wave is fluid without cut links.  In
+    // a mixed wave nl.base is relative to the wave's first link and f already
+    // holds the link slots.
+    auto node = [&](auto plain_c, const NodeLinks& nl) {
         constexpr bool PLAIN = decltype(plain_c)::value;
-        const NodeLinks nl = PLAIN ? NodeLinks{0u, 0u} : node_links(info, wv.y);
         // forward state f(y, t) and its velocity
-        apply_links<L, T>(wa, p, nl, f);
         T sp[NP], dp[NP];
         pair_split<L, T>(f, sp, dp);
         T rho, j[3];
@@ -171,26 +238,19 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
                 if constexpr (i > 0) {
                     const uint32_t bit = (nl.mask >> i) & 1u;
                     if (bit) {
-                        double ak = (double)ld(lam_in + (size_t)i * g.S, pos.n);
-                        if (a.obj_kind == 1 && L::E[i][0] != 0 && lktag[k] == a.obj_tag) {
-                            // drag: (e_ibar)_x (f'_ibar(y,t) + f_i(y,t+1))
-                            const double dfx = -(double)L::E[i][0] * a.w_force;
-                            ak += dfx;
-                            mu[ib] += (T)dfx;
+                        if (k < 64u) {
+                            mu[i] += st.v[0][k];
+                            mu[ib] += st.v[1][k];
+                            dir[i] += st.v[2][k];
+                            dir[ib] += st.v[3][k];
+                            st.v[0][k] = f[ib];
+                            st.v[1][k] = fp[i];
+                            st.v[2][k] = fp[ib];
+                        } else {
+                            own_link_direct<L, T, i>(wbase + k, lam_in, pos.n, g.S, lkcoef,
+                                                     lkderiv, lkc4, lktag, gq, gphi, p, a, f,
+                                                     fp, mu, dir);
                         }
-                        const LinkCoef c = lkcoef[k];
-                        const LinkDeriv dc = lkderiv[k];
-                        mu[i] += (T)(c.c2 * ak);
-                        mu[ib] += (T)(c.c3 * ak);
-                        dir[i] += (T)(p.c0 * ak);
-                        dir[ib] += (T)(c.c1 * ak);
-                        gq[k] += ak * (dc.d1 * (double)f[ib] + dc.d2 * (double)fp[i] +
-                                       dc.d3 * (double)fp[ib] + dc.dwall);
-                        const double c4w = lkc4[k] * 3.0 * L::W[i] * p.rho0_d * ak;
-#pragma unroll
-                        for (int al = 0; al < D; ++al)
-                            if (L::E[i][al] != 0)
-                                gphi[(size_t)k * D + al] += c4w * L::E[i][al];
                     }
                     k += bit;
                 }
@@ -272,19 +332,63 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
     };
 
     if (kind == WAVE_PLAIN) {
-        node(std::true_type{}, 0u);
+        node(std::true_type{}, NodeLinks{0u, 0u});
     } else if (kind == WAVE_MIXED) {
         const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
-        if (!is_solid(info)) node(std::false_type{}, info);
-    }
-    // the solid lanes of a mixed wave store NaN (nothing reads lambda at
-    // solid nodes) so that the wave writes whole lines of lam_out: partial
-    // lines cost HBM read-modify-write cycles
-    if (kind == WAVE_MIXED && pos.in && is_solid(nm.info[pos.n])) {
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));
-        });
+        const bool sol = is_solid(info);
+        const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, 0u);
+        // forward state: the link slots of the recorded step
+        const T wa0 = lane < nlw ? wa[wbase + lane] : T(0);
+        wave_link_values<L, T>(wa, wbase, lane, wa0, nl, st, f);
+        if (p.c1d) complete_two_node<L, T>(p.c1d + wbase, nl, f);
+        // link lanes: a_k and the pieces of mu and lambda(y, t) it feeds
+        double ak = 0.0;
+        int ld_dir = 0;
+        if (lane < nlw && lane < 64u) {
+            const uint32_t k = wbase + lane;
+            ld_dir = lkdir[k];
+            int e[3];
+            double w;
+            dir_data<L>(ld_dir, e, w);
+            ak = (double)lam_in[(size_t)ld_dir * g.S + (uint32_t)lknode[k]];
+            double dfx = 0.0;
+            if (a.obj_kind == 1 && e[0] != 0 && lktag[k] == a.obj_tag) {
+                // drag: (e_ibar)_x (f'_ibar(y,t) + f_i(y,t+1))
+                dfx = -(double)e[0] * a.w_force;
+                ak += dfx;
+            }
+            const LinkCoef c = lkcoef[k];
+            st.v[0][lane] = (T)(c.c2 * ak);
+            st.v[1][lane] = (T)(c.c3 * ak + dfx);
+            st.v[2][lane] = (T)(p.c0 * ak);
+            st.v[3][lane] = (T)(c.c1 * ak);
+        }
+        wave_lds_sync();
+        if (!sol) node(std::false_type{}, nl);
+        wave_lds_sync();
+        // link lanes: per-link gradients from the node's values
+        if (lane < nlw && lane < 64u) {
+            const uint32_t k = wbase + lane;
+            const LinkDeriv dc = lkderiv[k];
+            gq[k] += ak * (dc.d1 * (double)st.v[0][lane] + dc.d2 * (double)st.v[1][lane] +
+                           dc.d3 * (double)st.v[2][lane] + dc.dwall);
+            int e[3];
+            double w;
+            dir_data<L>(ld_dir, e, w);
+            const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * ak;
+#pragma unroll
+            for (int al = 0; al < D; ++al)
+                if (e[al] != 0) gphi[(size_t)k * D + al] += c4w * e[al];
+        }
+        // the solid lanes store NaN (nothing reads lambda at solid nodes) so
+        // that the wave writes whole lines of lam_out: partial lines cost
+        // HBM read-modify-write cycles
+        if (pos.in && sol) {
+            unroll<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));
+            });
+        }
     }
 
     // lb is uniform over the block, so the barrier inside is block-uniform
@@ -401,7 +505,8 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const void* lam_i
         hipLaunchKernelGGL(kern, dim3(g.chunk ? g.chunk * NXCD : g.nblocks), dim3(BX), 0,
                            e.stream, (const T*)fwd.f, (const T*)fwd.wa,
                            (const T*)lam_in, (T*)lam_out,
-                           NodeMeta{e.d_info, e.d_wave}, e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag, e.d_gq,
+                           NodeMeta{e.d_info, e.d_wave}, e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag,
+                           e.d_lkdir, e.d_lknode, e.d_gq,
                            e.d_gphi, e.d_gglob, g, adj_params<L, T>(e), a);
         return hipGetLastError();
     });

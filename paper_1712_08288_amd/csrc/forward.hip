@@ -25,42 +25,6 @@ static_assert(BX == kBlock && BX % 64 == 0, "node launches use kBlock-thread blo
 // metadata, so they are issued with the plane reads.  Links past the 64th
 // (rare: long wall rows) are read and written by their node's lane directly;
 // straight-line code keeps the register count of the step at its minimum.
-template <class T>
-struct LinkStage {
-    T v[4][64];
-};
-
-// order the wave's LDS writes before the other lanes' reads (the LDS executes
-// one wave's instructions in order; this keeps the compiler from moving them)
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Pulled values of cut-link directions: f_i(x_f, t) = wa[k].  nl.base is the
-// node's first link relative to the wave's first link wbase; wa0 =
-// wa[wbase + lane] for lanes below the wave's link count (else 0), read in
-// advance by every lane.
-template <class L, class T>
-__device__ __forceinline__ void wave_link_values(const T* __restrict__ wa, uint32_t wbase,
-                                                 uint32_t lane, T wa0, const NodeLinks& nl,
-                                                 LinkStage<T>& st, T (&f)[L::Q]) {
-    st.v[0][lane] = wa0;
-    wave_lds_sync();
-    if (nl.mask) {
-        uint32_t k = nl.base;
-        unroll<L::Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (i > 0) {
-                const uint32_t bit = (nl.mask >> i) & 1u;
-                if (bit) f[i] = k < 64u ? st.v[0][k] : wa[wbase + k];
-                k += bit;
-            }
-        });
-    }
-    wave_lds_sync();
-}
 
 // Eq. (213) for every cut link of the wave, from the pre-collision (fpre)
 // and post-collision (f) values at its fluid node, into the link slots of

@@ -416,6 +416,47 @@ __device__ __forceinline__ void apply_links(const T* __restrict__ wa, const Para
     if (p.c1d) complete_two_node<L, T>(p.c1d, nl, f);
 }
 
+// Per-wave cooperative handling of cut links.  The links of one wave of a
+// node launch are contiguous (sorted by node, then direction); lane l carries
+// the wave's link l of the first 64, and values move between that lane and
+// the lane of the link's fluid node through a per-wave LDS slab.
+template <class T>
+struct LinkStage {
+    T v[4][64];
+};
+
+// order the wave's LDS writes before the other lanes' reads (the LDS executes
+// one wave's instructions in order; this keeps the compiler from moving them)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pulled values of cut-link directions: f_i(x_f, t) = wa[k].  nl.base is the
+// node's first link relative to the wave's first link wbase; wa0 =
+// wa[wbase + lane] for lanes below the wave's link count (else 0), read in
+// advance by every lane.
+template <class L, class T>
+__device__ __forceinline__ void wave_link_values(const T* __restrict__ wa, uint32_t wbase,
+                                                 uint32_t lane, T wa0, const NodeLinks& nl,
+                                                 LinkStage<T>& st, T (&f)[L::Q]) {
+    st.v[0][lane] = wa0;
+    wave_lds_sync();
+    if (nl.mask) {
+        uint32_t k = nl.base;
+        unroll<L::Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0) {
+                const uint32_t bit = (nl.mask >> i) & 1u;
+                if (bit) f[i] = k < 64u ? st.v[0][k] : wa[wbase + k];
+                k += bit;
+            }
+        });
+    }
+    wave_lds_sync();
+}
+
 // Pull the pre-collision state f(x, t) of one fluid node.
 template <class L, class T, int XB, bool PRED = false>
 __device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restrict__ wa,
