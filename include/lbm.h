@@ -52,9 +52,11 @@ enum {
 };
 
 /* lattices: velocity orderings are reported by lbm_lattice_info().
- * D2Q9 is ordered as in the paper's Appendix; D3Q19 is rest, the six axis
- * vectors (+x,-x,+y,-y,+z,-z), then the twelve edge vectors. */
-enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+ * D2Q9 and D3Q15 are ordered as in the paper's Appendix (D3Q15: rest, the
+ * six axis vectors, then the eight corner vectors, with the Appendix's
+ * transformation matrix); D3Q19 is rest, the six axis vectors
+ * (+x,-x,+y,-y,+z,-z), then the twelve edge vectors. */
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q15 = 2 };
 
 /* precision: FP64 stores and computes delta f in double; FP32 stores and
  * computes delta f in float.  In both, the per-link coefficients, the
@@ -108,6 +110,16 @@ int lbm_set_scheme(lbm_t *h, int l_rule, double b);
  * bracket of Eq. (213) is modified the same way.  Must precede
  * lbm_set_geometry.  Errors: ESTATE. */
 int lbm_set_two_node(lbm_t *h, int on);
+
+/* Time-dependent wall data of the separable form phi(x_b, t) =
+ * phi(x_b, 0) * lambda^t (t in steps): the step from t to t+1 uses the wall
+ * term of Eq. (210)/(213) scaled by lambda^t (phi at time t, as in Eq. (210)).
+ * The Taylor-Green vortex of Section 3.2 has such data, lambda =
+ * exp(-8 pi^2 nu dt).  The adjoint applies the same factor, so dwall_u of
+ * lbm_grad is the gradient with respect to phi(x_b, 0).  lambda = 1 (the
+ * default) is constant data; any other value disables lbm_step's graph
+ * replay.  EINVAL unless lambda is finite and positive. */
+int lbm_set_wall_decay(lbm_t *h, double lambda);
 
 /* Choose the x boundary (see above); drho is used by LBM_X_PRESSURE only.
  * Must precede lbm_set_geometry.  Errors: EINVAL, ESTATE. */

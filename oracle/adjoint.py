@@ -15,8 +15,8 @@ Its reverse, for lambda(t+1) = dJ/df(., t+1):
   J_eq the derivative of Eq. (42) (formed densely here), applied transposed.
 
 Gradients: of the coefficients of Eq. (213) through gamma (l follows the
-rule), of the wall velocity phi, of the body force g and of the relaxation
-rates s.  Pinned by complex-step differentiation of the forward oracle
+rule), of the wall velocity phi (of phi(x_b, 0) when the wall data decay as
+phi(0) * wall_decay**t), of the body force g and of the relaxation rates s.  Pinned by complex-step differentiation of the forward oracle
 (tests/test_oracle_adjoint.py), which is exact to round-off because the
 step is a rational function of these parameters.
 """
@@ -50,7 +50,9 @@ class Objective:
 
 
 def forward(o, f0, steps, obj):
-    """Run the oracle and accumulate the objective; returns (J, states)."""
+    """Run the oracle from f0 at time 0 and accumulate the objective;
+    returns (J, states)."""
+    o.time = 0
     J = 0.0
     states = [f0]
     f = f0
@@ -130,9 +132,10 @@ def reverse(o, states, obj, rule=None):
         np.add.at(direct, (i, xf), c0 * a_link)
         np.add.at(direct, (ib, xf), np.where(defer, 0.0, c1 * a_link))
         # per-link gradients
+        ws = o.wall_scale(t)
         gq += a_link * (d0 * f[i, xf] + d1 * f_ib + d2 * fp[i, xf]
-                        + d3 * fp[ib, xf] + d4 * o.wall_term)
-        gphi += (a_link * c4)[:, None] * unit_e
+                        + d3 * fp[ib, xf] + d4 * o.wall_term * ws)
+        gphi += (a_link * c4 * ws)[:, None] * unit_e
         # body force and rates
         muf = np.where(fluid[None, :], mu, 0.0)
         gg += (3.0 * o.w[:, None] * o.rho0 * muf).T.sum(0) @ o.e

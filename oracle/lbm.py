@@ -38,8 +38,18 @@ from . import scheme as _scheme
 class Oracle:
     def __init__(self, geom, s, rho0=1.0, g=None, dp=0.0, l_rule="min",
                  b=1.0, deviation=True, q=None, wall_u=None,
-                 allow_nonconvex=False, nodes=None, two_node=False):
-        """two_node: use Eq. (211) (Remark (2)) instead of Eq. (210): the
+                 allow_nonconvex=False, nodes=None, two_node=False, collision=None,
+                 wall_decay=1.0):
+        """collision: None for the MRT operator of the Appendix with rates s;
+        ("trt", s_plus, s_minus) for the two-relaxation-time operator and
+        ("bgk", s_nu) for the single-relaxation-time one (Remark (1): the
+        boundary scheme does not depend on the collision operator).  TRT
+        relaxes the even and odd halves f^+- = (f_i +- f_ibar)/2 towards the
+        halves of f^eq at s_plus and s_minus; BGK is s_plus = s_minus = s_nu.
+        wall_decay: wall data phi(x_b, t) = phi(x_b, 0) * wall_decay**t, t
+        counted in steps from the last init_* call (the Taylor-Green data of
+        Section 3.2 decay this way); the step from t uses phi at t (Eq. (210)).
+        two_node: use Eq. (211) (Remark (2)) instead of Eq. (210): the
         time-lagged f_ibar(x_f, t) is replaced by its advected value
         f'_ibar(x_f + e_i, t) whenever that neighbour is fluid; links whose
         neighbour x_f + e_i is solid keep Eq. (210).
@@ -67,6 +77,14 @@ class Oracle:
         self.rho_base = rho0 if deviation else 0.0
         self.l_rule, self.b = l_rule, b
         self.two_node = two_node
+        if collision is not None:
+            if collision[0] == "bgk":
+                collision = ("trt", collision[1], collision[1])
+            if collision[0] != "trt" or len(collision) != 3:
+                raise ValueError("collision must be None, ('bgk', s) or ('trt', s_plus, s_minus)")
+        self.collision = collision
+        self.wall_decay = wall_decay
+        self.time = 0
         n_all = nx * ny * nz
         self.window = nodes is not None
         self.nodes = (np.arange(n_all, dtype=np.int64) if nodes is None
@@ -156,8 +174,15 @@ class Oracle:
 
     # ---------------------------------------------------------------- the step
     def collide(self, f):
-        """Eq. (22a) with the MRT operator of the Appendix plus forcing."""
+        """Eq. (22a) with the MRT operator of the Appendix (or the TRT / BGK
+        operator chosen at construction) plus forcing."""
         feq = self.equilibrium(self.density_deviation(f), self.velocity(f))
+        if self.collision is not None:
+            _, s_plus, s_minus = self.collision
+            neq = f - feq
+            even = 0.5 * (neq + neq[self.opp])
+            odd = 0.5 * (neq - neq[self.opp])
+            return f - s_plus * even - s_minus * odd + self.F[:, None]
         m_neq = self.M @ (f - feq)
         return f - self.Minv @ (self.s[:, None] * m_neq) + self.F[:, None]
 
@@ -183,14 +208,18 @@ class Oracle:
             # a cut link (x_f + e_i solid): then the single-node form
             f_ib = np.where(self.lk_ibar_is_link, f_ib, fn[ib, xf])
         fn[i, xf] = (c0 * f[i, xf] + c1 * f_ib + c2 * fp[i, xf]
-                     + c3 * fp[ib, xf] + c4 * self.wall_term)
+                     + c3 * fp[ib, xf] + c4 * self.wall_term * self.wall_scale(self.time))
         return fn
+
+    def wall_scale(self, t):
+        return 1.0 if self.wall_decay == 1.0 else self.wall_decay ** t
 
     def step(self, f):
         fp = self.collide(f)
         fn = self.stream(fp)
         self.boundary(f, fp, fn)
         fn[:, ~self.fluid] = np.nan
+        self.time += 1
         return fn, fp
 
     def run(self, f, steps, observe=None):
@@ -210,6 +239,7 @@ class Oracle:
         f = self.equilibrium(rho - self.rho_base, np.asarray(u).T)
         f = f.astype(np.result_type(f, np.float64))
         f[:, ~self.fluid] = np.nan
+        self.time = 0
         return f
 
     def init_deviation(self, df):
@@ -217,6 +247,7 @@ class Oracle:
         f = np.array(df, dtype=np.result_type(df, np.float64)) + (
             self.w * self.rho0 - self.base)[:, None]
         f[:, ~self.fluid] = np.nan
+        self.time = 0
         return f
 
     def as_deviation(self, f):

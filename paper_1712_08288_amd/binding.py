@@ -41,6 +41,7 @@ _create = _sig("lbm_create", _i, [C.POINTER(_p), _i, _i, _i64, _i64, _i64, _dp, 
 _set_scheme = _sig("lbm_set_scheme", _i, [_p, _i, _d])
 _set_xbc = _sig("lbm_set_x_boundary", _i, [_p, _i, _d])
 _set_two_node = _sig("lbm_set_two_node", _i, [_p, _i])
+_set_wall_decay = _sig("lbm_set_wall_decay", _i, [_p, C.c_double])
 _set_geometry = _sig("lbm_set_geometry", _i, [_p, _p, _i64, _p, _p, _p, _p, _p])
 _update_links = _sig("lbm_update_links", _i, [_p, _p, _p])
 _set_params = _sig("lbm_set_parameters", _i, [_p, _p, _p])
@@ -71,7 +72,8 @@ _stream_copy = _sig("lbm_stream_copy", _i, [_p, _p, _i64, _i32, _i32, _p])
 _last_err = _sig("lbm_last_error", C.c_char_p, [_p])
 _destroy = _sig("lbm_destroy", _i, [_p])
 
-EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_x_boundary",
+EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_decay",
+            "lbm_set_x_boundary",
             "lbm_set_geometry", "lbm_update_links", "lbm_set_parameters", "lbm_init",
             "lbm_init_deviation", "lbm_step", "lbm_time", "lbm_moments",
             "lbm_get_distribution", "lbm_reduce", "lbm_force",
@@ -82,7 +84,7 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_x_bound
             "lbm_last_step_ms", "lbm_stream_copy", "lbm_last_error",
             "lbm_destroy"]
 
-LATTICES = {"D2Q9": 0, "D3Q19": 1}
+LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q15": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 RULES = {"gamma": 0, "1.5gamma": 1, "2gamma": 2, "gamma2": 3,
          "gamma2+gamma": 4, "zero": 5, "min": 6}
@@ -123,6 +125,29 @@ def lattice_info(lattice):
     if rc:
         raise LBMError(rc, "lattice_info")
     return e.astype(np.int64), w, M
+
+
+def collision_rates(lattice, kind, s_nu, magic=3.0 / 16.0):
+    """Rates that turn the library's MRT collision into BGK or TRT (the
+    boundary scheme does not depend on the collision operator, Remark (1)).
+
+    Every moment row is even or odd under e -> -e, so relaxing the even rows
+    at s_plus = s_nu and the odd rows at s_minus is exactly the TRT operator
+    on the halves (f_i +- f_ibar)/2; s_minus follows from the "magic"
+    product (1/s_plus - 1/2)(1/s_minus - 1/2) = magic.  BGK is s_minus =
+    s_plus.  The conserved rows get s_nu as well (their non-equilibrium part
+    is zero, so any value is equivalent)."""
+    e, _, M = lattice_info(lattice)
+    Q = len(e)
+    opp = np.array([int(np.nonzero((e == -e[i]).all(1))[0][0]) for i in range(Q)])
+    even = np.all(M[:, opp] == M, axis=1)
+    if kind == "bgk":
+        s_minus = s_nu
+    elif kind == "trt":
+        s_minus = 1.0 / (0.5 + magic / (1.0 / s_nu - 0.5))
+    else:
+        raise ValueError("kind must be 'bgk' or 'trt'")
+    return np.where(even, float(s_nu), float(s_minus))
 
 
 def stream_copy(dst, src, nbytes, mode=0, reps=10):
@@ -187,6 +212,10 @@ class Solver:
 
     def set_two_node(self, on=True):
         self._chk(_set_two_node(self._h, 1 if on else 0), "set_two_node")
+
+    def set_wall_decay(self, lam=1.0):
+        """Wall data phi(x_b, t) = phi(x_b, 0) * lam**t (t in steps)."""
+        self._chk(_set_wall_decay(self._h, float(lam)), "set_wall_decay")
 
     def set_x_boundary(self, kind="periodic", drho=0.0):
         self._chk(_set_xbc(self._h, X_BC[kind], float(drho)), "set_x_boundary")

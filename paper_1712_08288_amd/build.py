@@ -1,7 +1,7 @@
 """Compile the HIP engine into paper_1712_08288_amd/_lib/liblbm.so for gfx950.
 
 Run as `python -m paper_1712_08288_amd.build` or through
-`__graft_entry__.build()`.  Always recompiles.
+`__graft_entry__.build()`.  Always recompiles (sources in parallel).
 """
 
 import os
@@ -31,10 +31,7 @@ def hipcc():
     return exe
 
 
-def build(verbose=False):
-    os.makedirs(OUT_DIR, exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
@@ -44,6 +41,24 @@ def build(verbose=False):
         raise RuntimeError("hipcc failed:\n" + msgs)
     if verbose and msgs.strip():
         print(msgs)
+
+
+def build(verbose=False):
+    """Compile each source to an object (in parallel), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OUT_DIR, exist_ok=True)
+    cc = hipcc()
+    objs = [os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+    cmds = [[cc] + [f for f in FLAGS if f != "-shared"] + ["-c", "-o", o, os.path.join(CSRC, src)]
+            for src, o in zip(SOURCES, objs)]
+    workers = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0") or 0) or os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for fut in [ex.submit(_run, c, verbose) for c in cmds]:
+            fut.result()
+    tmp = LIB + ".tmp"
+    _run([cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
+    for o in objs:
+        os.remove(o)
     os.replace(tmp, LIB)
     return LIB
 

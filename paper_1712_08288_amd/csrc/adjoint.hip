@@ -130,8 +130,8 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
     dir[i] += (T)(p.c0 * ak);
     dir[ib] += (T)(c.c1 * ak);
     gq[k] += ak * (dc.d1 * (double)f[ib] + dc.d2 * (double)fp[i] + dc.d3 * (double)fp[ib] +
-                   dc.dwall);
-    const double c4w = lkc4[k] * 3.0 * L::W[i] * p.rho0_d * ak;
+                   p.wall_scale * dc.dwall);
+    const double c4w = lkc4[k] * 3.0 * L::W[i] * p.rho0_d * p.wall_scale * ak;
 #pragma unroll
     for (int al = 0; al < L::D; ++al)
         if (L::E[i][al] != 0) gphi[(size_t)k * L::D + al] += c4w * L::E[i][al];
@@ -265,7 +265,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
         T r[Q];
         unroll<Q>([&](auto K) {
             constexpr int kk = decltype(K)::value;
-            r[kk] = qm[kk] * p.rate[kk];
+            r[kk] = L::conserved(kk) ? T(0) : qm[kk] * p.rate[kk];
         });
         T e0, ev[NP], od[NP];
         back_transform<L, T>(r, e0, ev, od);
@@ -371,11 +371,11 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
             const uint32_t k = wbase + lane;
             const LinkDeriv dc = lkderiv[k];
             gq[k] += ak * (dc.d1 * (double)st.v[0][lane] + dc.d2 * (double)st.v[1][lane] +
-                           dc.d3 * (double)st.v[2][lane] + dc.dwall);
+                           dc.d3 * (double)st.v[2][lane] + p.wall_scale * dc.dwall);
             int e[3];
             double w;
             dir_data<L>(ld_dir, e, w);
-            const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * ak;
+            const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * p.wall_scale * ak;
 #pragma unroll
             for (int al = 0; al < D; ++al)
                 if (e[al] != 0) gphi[(size_t)k * D + al] += c4w * e[al];
@@ -455,6 +455,7 @@ static Params<L, T> adj_params(const Engine& e) {
     p.inv_rho0 = (T)(1.0 / e.rho0);
     p.c0 = 1.0 - e.b;
     p.rho0_d = e.rho0;
+    p.wall_scale = e.wall_decay == 1.0 ? 1.0 : e.wall_scale;
     p.c1d = e.two_node ? e.d_lkc1d : nullptr;
     return p;
 }
@@ -485,6 +486,8 @@ static hipError_t adj_dispatch(const Engine& e, F&& f) {
     };
     if (e.lattice == 0)
         return e.precision == 0 ? by_xbc(D2Q9{}, double{}) : by_xbc(D2Q9{}, float{});
+    if (e.lattice == 2)
+        return e.precision == 0 ? by_xbc(D3Q15{}, double{}) : by_xbc(D3Q15{}, float{});
     return e.precision == 0 ? by_xbc(D3Q19{}, double{}) : by_xbc(D3Q19{}, float{});
 }
 

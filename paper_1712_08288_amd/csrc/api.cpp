@@ -40,19 +40,30 @@ int fail(lbm_t* h, int code, const std::string& msg) {
     } while (0)
 
 // ---- lattice tables on the host (the same constexpr definitions) -------------
-int lat_Q(int lattice) { return lattice == 0 ? lbe::D2Q9::Q : lbe::D3Q19::Q; }
-int lat_D(int lattice) { return lattice == 0 ? lbe::D2Q9::D : lbe::D3Q19::D; }
+// host-side lattice data by runtime id (LBM_D2Q9, LBM_D3Q19, LBM_D3Q15)
+template <class F>
+auto with_lattice(int lattice, F&& f) {
+    if (lattice == LBM_D2Q9) return f(lbe::D2Q9{});
+    if (lattice == LBM_D3Q15) return f(lbe::D3Q15{});
+    return f(lbe::D3Q19{});
+}
+int lat_Q(int lattice) {
+    return with_lattice(lattice, [](auto l) { return decltype(l)::Q; });
+}
+int lat_D(int lattice) {
+    return with_lattice(lattice, [](auto l) { return decltype(l)::D; });
+}
 int lat_e(int lattice, int i, int a) {
-    return lattice == 0 ? lbe::D2Q9::E[i][a] : lbe::D3Q19::E[i][a];
+    return with_lattice(lattice, [&](auto l) { return decltype(l)::E[i][a]; });
 }
 double lat_w(int lattice, int i) {
-    return lattice == 0 ? lbe::D2Q9::W[i] : lbe::D3Q19::W[i];
+    return with_lattice(lattice, [&](auto l) { return decltype(l)::W[i]; });
 }
 int lat_M(int lattice, int k, int i) {
-    return lattice == 0 ? lbe::TAB<lbe::D2Q9>.M[k][i] : lbe::TAB<lbe::D3Q19>.M[k][i];
+    return with_lattice(lattice, [&](auto l) { return lbe::TAB<decltype(l)>.M[k][i]; });
 }
 bool lat_conserved(int lattice, int k) {
-    return lattice == 0 ? lbe::D2Q9::conserved(k) : lbe::D3Q19::conserved(k);
+    return with_lattice(lattice, [&](auto l) { return decltype(l)::conserved(k); });
 }
 
 // ---- the free parameter l(gamma) (paper, Section 3 and Eq. (212)) ------------
@@ -296,6 +307,7 @@ int zero(lbm_t* h, void* p, size_t bytes) {
 // snapshots), with the objective accumulated when `accumulate`
 int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumulate) {
     Engine& e = h->e;
+    e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)e.t);
     lbe::StepObjective so;
     const bool in_window = accumulate && e.obj_kind != LBM_OBJ_NONE &&
                            e.t >= e.obj_t0 && e.t < e.obj_t1;
@@ -319,7 +331,7 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
                int64_t nz, const double* s, double rho0, const double* g) {
     if (!out) return LBM_EINVAL;
     *out = nullptr;
-    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return LBM_EINVAL;
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q15) return LBM_EINVAL;
     if (precision != LBM_FP64 && precision != LBM_FP32) return LBM_EINVAL;
     if (nx < 1 || ny < 1 || nz < 1) return LBM_EINVAL;
     if (lattice == LBM_D2Q9 && nz != 1) return LBM_EINVAL;
@@ -405,6 +417,14 @@ int lbm_set_two_node(lbm_t* h, int on) {
     if (!h) return LBM_EINVAL;
     if (h->e.has_geometry) return fail(h, LBM_ESTATE, "choose the variant before the geometry");
     h->e.two_node = on != 0;
+    return LBM_OK;
+}
+
+int lbm_set_wall_decay(lbm_t* h, double lambda) {
+    if (!h) return LBM_EINVAL;
+    if (!std::isfinite(lambda) || !(lambda > 0.0))
+        return fail(h, LBM_EINVAL, "wall decay factor must be finite and positive");
+    h->e.wall_decay = lambda;
     return LBM_OK;
 }
 
@@ -680,7 +700,7 @@ int lbm_step(lbm_t* h, int64_t n) {
     // small domains are launch-bound: replay captured loops of graph_steps
     // steps while no objective window is open
     const bool obj_open = e.obj_kind != LBM_OBJ_NONE && e.t < e.obj_t1 && e.t + n > e.obj_t0;
-    if (e.graph_steps > 0 && !obj_open) {
+    if (e.graph_steps > 0 && !obj_open && e.wall_decay == 1.0) {
         while (left >= e.graph_steps) {
             if (!e.graph_exec[e.cur]) {
                 const int rc = build_graph(h, e.cur);
@@ -944,6 +964,7 @@ int lbm_adjoint(lbm_t* h) {
             ao.inv_nfluid = e.n_fluid ? 1.0 / (double)e.n_fluid : 0.0;
             if (!in_w) ao.kind = LBM_OBJ_NONE;
             hipError_t st = hipSuccess;
+            e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
             if (e.two_node) st = lbe::launch_two_node_adjoint(e, e.pool[r + 1], e.lam[lc], ao);
             if (st == hipSuccess)
                 st = lbe::launch_adjoint_step(e, e.pool[r], e.lam[lc], e.lam[lc ^ 1], ao);
@@ -1020,7 +1041,7 @@ int lbm_set_stream(lbm_t* h, void* stream) {
 
 int lbm_lattice_info(int lattice, int32_t* Q, int32_t* D, int8_t* e, double* w,
                      double* M) {
-    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return LBM_EINVAL;
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q15) return LBM_EINVAL;
     const int q = lat_Q(lattice), d = lat_D(lattice);
     if (Q) *Q = q;
     if (D) *D = d;

@@ -63,6 +63,8 @@ struct Engine {
     LinkDeriv* d_lkderiv = nullptr;
     double* d_lkc4 = nullptr;           // c4 per link (for dJ/dphi)
     bool two_node = false;              // Eq. (211) instead of Eq. (210)
+    double wall_decay = 1.0;            // wall data phi(t) = phi(0) * wall_decay^t
+    double wall_scale = 1.0;            // wall_decay^t of the step being launched
     std::vector<uint8_t> ibar_is_link;  // sorted link k: (x_f, ibar) is a link too
     double* d_lkc1d = nullptr;          // c1 applied at the next pull (Eq. (211)), else 0
     double* d_lkd1d = nullptr;          // its gamma derivative

@@ -33,7 +33,8 @@ template <class L, class T>
 __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fpre)[L::Q],
                                                const T (&f)[L::Q],
                                                const LinkCoef* __restrict__ lkcoef,
-                                               T* __restrict__ waB, double c0d, uint32_t wbase,
+                                               T* __restrict__ waB, double c0d, double ws,
+                                               uint32_t wbase,
                                                uint32_t nlw, uint32_t lane, LinkStage<T>& st) {
     if (nl.mask) {
         uint32_t k = nl.base;
@@ -51,7 +52,7 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
                     } else {
                         const LinkCoef c = lkcoef[wbase + k];
                         const double v = c0d * (double)fpre[i] + c.c1 * (double)fpre[ib] +
-                                         c.c2 * (double)f[i] + c.c3 * (double)f[ib] + c.wall;
+                                         c.c2 * (double)f[i] + c.c3 * (double)f[ib] + ws * c.wall;
                         waB[wbase + k] = (T)v;
                     }
                 }
@@ -63,7 +64,7 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
     if (lane < nlw) {
         const LinkCoef c = lkcoef[wbase + lane];
         const double v = c0d * (double)st.v[0][lane] + c.c1 * (double)st.v[1][lane] +
-                         c.c2 * (double)st.v[2][lane] + c.c3 * (double)st.v[3][lane] + c.wall;
+                         c.c2 * (double)st.v[2][lane] + c.c3 * (double)st.v[3][lane] + ws * c.wall;
         waB[wbase + lane] = (T)v;
     }
 }
@@ -130,7 +131,8 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
                 st_nt(B + (size_t)i * g.S, pos.n, sol ? nan : f[i]);
             });
         }
-        wave_link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0, wbase, nlw, lane, stage[wid]);
+        wave_link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0, p.wall_scale, wbase, nlw, lane,
+                             stage[wid]);
     }
     if (acc_ux) {   // uniform over the launch
         const double s = block_sum(ux_local);
@@ -413,6 +415,7 @@ static Params<L, T> make_params(const Engine& e) {
     p.inv_rho0 = (T)(1.0 / e.rho0);
     p.c0 = 1.0 - e.b;
     p.rho0_d = e.rho0;
+    p.wall_scale = e.wall_decay == 1.0 ? 1.0 : e.wall_scale;
     p.c1d = e.two_node ? e.d_lkc1d : nullptr;
     return p;
 }
@@ -431,6 +434,8 @@ static hipError_t dispatch(const Engine& e, F&& f) {
     };
     if (e.lattice == 0)
         return e.precision == 0 ? by_xbc(D2Q9{}, double{}) : by_xbc(D2Q9{}, float{});
+    if (e.lattice == 2)
+        return e.precision == 0 ? by_xbc(D3Q15{}, double{}) : by_xbc(D3Q15{}, float{});
     return e.precision == 0 ? by_xbc(D3Q19{}, double{}) : by_xbc(D3Q19{}, float{});
 }
 

@@ -95,6 +95,7 @@ struct Params {
     T rho0, inv_rho0;
     double c0;        // 1 - b of Eq. (213)
     double rho0_d;
+    double wall_scale;  // factor on the wall terms at this step (decaying data)
     const double* c1d;  // Eq. (211): per-link c1 added at the pull, or null
 };
 

@@ -4,6 +4,10 @@
 // moment rows are the Lallemand-Luo polynomials 1, 3e^2-4,
 // (9e^4-21e^2+8)/2, e_x, (3e^2-5)e_x, e_y, (3e^2-5)e_y, e_x^2-e_y^2, e_x e_y,
 // which reproduce the matrix printed in the Appendix.
+// D3Q15: velocity order, weights and transformation matrix of the paper's
+// Appendix (D3Q15 model); its rows are the polynomials 1, e^2-2,
+// (15e^4-55e^2+32)/2, e_a and (5e^2-13)e_a/2 for a = x, y, z, 3e_x^2-e^2,
+// e_y^2-e_z^2, e_x e_y, e_y e_z, e_x e_z and e_x e_y e_z.
 // D3Q19: rest, axis and edge vectors, weights 1/3, 1/18, 1/36; rows are the
 // d'Humieres et al. (2002) moment polynomials (the reference the paper
 // cites for its 3D MRT models).
@@ -78,6 +82,42 @@ struct D3Q19 {
             case 16: return (ey * ey - ez * ez) * ex;
             case 17: return (ez * ez - ex * ex) * ey;
             default: return (ex * ex - ey * ey) * ez;
+        }
+    }
+    static constexpr bool conserved(int k) {
+        return k == 0 || k == 3 || k == 5 || k == 7;
+    }
+};
+
+struct D3Q15 {
+    static constexpr int Q = 15;
+    static constexpr int D = 3;
+    static constexpr int E[15][3] = {
+        {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+        {0, 0, 1},  {0, 0, -1},  {1, 1, 1},  {-1, 1, 1}, {1, -1, 1},
+        {-1, -1, 1}, {1, 1, -1}, {-1, 1, -1}, {1, -1, -1}, {-1, -1, -1}};
+    static constexpr double W[15] = {2.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,
+                                     1.0 / 9,  1.0 / 9,  1.0 / 72, 1.0 / 72, 1.0 / 72,
+                                     1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72};
+    static constexpr int moment(int k, int i) {
+        const int ex = E[i][0], ey = E[i][1], ez = E[i][2];
+        const int e2 = ex * ex + ey * ey + ez * ez;
+        switch (k) {
+            case 0: return 1;
+            case 1: return e2 - 2;
+            case 2: return (15 * e2 * e2 - 55 * e2 + 32) / 2;
+            case 3: return ex;
+            case 4: return (5 * e2 - 13) * ex / 2;
+            case 5: return ey;
+            case 6: return (5 * e2 - 13) * ey / 2;
+            case 7: return ez;
+            case 8: return (5 * e2 - 13) * ez / 2;
+            case 9: return 3 * ex * ex - e2;
+            case 10: return ey * ey - ez * ez;
+            case 11: return ex * ey;
+            case 12: return ey * ez;
+            case 13: return ex * ez;
+            default: return ex * ey * ez;
         }
     }
     static constexpr bool conserved(int k) {
@@ -174,6 +214,15 @@ constexpr bool rows_have_parity() {
 }
 static_assert(rows_have_parity<D2Q9>(), "D2Q9 rows must be even or odd");
 static_assert(rows_have_parity<D3Q19>(), "D3Q19 rows must be even or odd");
+static_assert(rows_have_parity<D3Q15>(), "D3Q15 rows must be even or odd");
+
+// the printed D3Q15 matrix: spot checks of rows 2, 4 and 14 (0-based)
+static_assert(TAB<D3Q15>.M[2][0] == 16 && TAB<D3Q15>.M[2][1] == -4 && TAB<D3Q15>.M[2][7] == 1,
+              "D3Q15 row 2");
+static_assert(TAB<D3Q15>.M[4][1] == -4 && TAB<D3Q15>.M[4][2] == 4 && TAB<D3Q15>.M[4][8] == -1,
+              "D3Q15 row 4");
+static_assert(TAB<D3Q15>.M[14][7] == 1 && TAB<D3Q15>.M[14][8] == -1 && TAB<D3Q15>.M[14][11] == -1,
+              "D3Q15 row 14");
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1.
 template <class F, int... I>

@@ -5,6 +5,7 @@ import numpy as np
 
 from oracle.lbm import Oracle
 from workloads import states
+from workloads.velocities import VELOCITIES
 
 
 def require_gpu():
@@ -25,7 +26,7 @@ def pair(geom, s, steps, precision="fp64", init="deviation", seed=1, amp=1e-3,
     initial state; return (gpu deviations, oracle deviations, fluid mask,
     solver, oracle, oracle state)."""
     from paper_1712_08288_amd import binding
-    Q = 9 if geom.lattice == "D2Q9" else 19
+    Q = len(VELOCITIES[geom.lattice])
     sv = binding.solver_for(geom, s, rho0=rho0, g=g, precision=precision,
                             l_rule=l_rule, b=b, dp=dp, two_node=two_node)
     o = Oracle(geom, s, rho0=rho0, g=g, dp=dp, l_rule=l_rule, b=b, two_node=two_node)

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(binding):
     assert sorted(binding.EXPORTED) == names
 
 
-@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q15", "D3Q19"])
 def test_lattice_tables_agree(binding, lattice):
     from oracle import lattice as L
     from workloads.velocities import VELOCITIES

@@ -33,6 +33,8 @@ def _gpu_grad(geom, s, kw, obj, steps, every, df0, precision="fp64"):
     sv = binding.solver_for(geom, s, precision=precision, g=kw.get("g"),
                             dp=kw.get("dp", 0.0), l_rule=kw.get("l_rule", "min"),
                             b=kw.get("b", 1.0), two_node=kw.get("two_node", False))
+    if kw.get("wall_decay", 1.0) != 1.0:
+        sv.set_wall_decay(kw["wall_decay"])
     sv.init_deviation(df0)
     sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1)
     sv.run_checkpointed(steps, every)
@@ -59,6 +61,19 @@ CASES = [
     ("d3q19_meanux_two_node_seam", lambda: G.random_spheres(20, 14, 12, 2, 2.2, 3.4, seed=4, x_bc="pressure"),
      lambda: configs.d3q19_rates(0.65), dict(dp=1e-3, l_rule="gamma", two_node=True),
      Objective("mean_ux", t0=0, t1=8), 8),
+    ("d2q9_drag_decaying_walls", lambda: G.random_cylinders(40, 29, 2, 3.1, 5.2, seed=6).with_wall_u(
+        np.tile([0.03, -0.01], (G.random_cylinders(40, 29, 2, 3.1, 5.2, seed=6).n_links, 1))),
+     lambda: configs.d2q9_rates(0.7), dict(g=(1e-4, 0, 0), l_rule="gamma2", wall_decay=0.95),
+     Objective("force_x", tag=1, t0=2, t1=12), 12),
+    ("d3q15_meanux_seam", lambda: G.random_spheres(20, 14, 12, 2, 2.2, 3.4, seed=4, x_bc="pressure",
+                                                    lattice="D3Q15"),
+     lambda: configs.d3q15_paper_rates(1.3), dict(g=(2e-5, 1e-5, 0), dp=1e-3, l_rule="gamma2"),
+     Objective("mean_ux", t0=1, t1=8), 8),
+    ("d3q15_drag_periodic_two_node", lambda: G.random_spheres(18, 15, 13, 2, 2.4, 3.6, seed=11,
+                                                              lattice="D3Q15"),
+     lambda: configs.d3q15_paper_rates(1.1), dict(g=(3e-5, 0, 0), l_rule="1.5gamma", b=0.95,
+                                                   two_node=True),
+     Objective("force_x", tag=1, t0=2, t1=9), 9),
 ]
 
 
@@ -67,7 +82,7 @@ def test_adjoint_matches_oracle_reverse(case):
     name, mk_geom, mk_s, kw, obj, steps = case
     geom, s = mk_geom(), mk_s()
     print("case", name, flush=True)
-    Q = 9 if geom.lattice == "D2Q9" else 19
+    Q = len(VELOCITIES[geom.lattice])
     df0 = states.random_deviation(Q, geom.n_nodes, seed=3, amp=2e-3)
     if geom.x_bc == "outflow":
         df0 = states.outlet_consistent(df0, geom.shape, VELOCITIES[geom.lattice])

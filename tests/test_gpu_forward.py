@@ -44,6 +44,11 @@ def cases():
         configs.d3q19_rates(0.6), dict(g=(1e-5, 2e-6, -1e-6), l_rule="gamma", b=0.7), 12
     yield "d3q19_wide_rows", G.random_spheres(300, 5, 6, 2, 1.5, 2.2, seed=9), \
         configs.d3q19_rates(0.9), dict(l_rule="gamma2+gamma"), 8
+    yield "d3q15_periodic_force", G.random_spheres(37, 21, 19, 2, 3.0, 5.0, seed=8, lattice="D3Q15"), \
+        configs.d3q15_paper_rates(1.4), dict(g=(1e-5, 2e-6, -1e-6), l_rule="gamma2", b=0.8), 12
+    yield "d3q15_seam_spheres", G.random_spheres(40, 24, 20, 3, 3.0, 5.5, seed=7, x_bc="pressure",
+                                                 lattice="D3Q15"), \
+        configs.d3q15_paper_rates(0.9), dict(dp=1e-3, l_rule="2gamma"), 12
 
 
 CASES = list(cases())
@@ -65,8 +70,11 @@ def test_distribution_matches_oracle(case, precision):
     sv.close()
 
 
+TWO_NODE = [CASES[0], CASES[1], CASES[3], CASES[7]]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[3]], ids=[CASES[0][0], CASES[1][0], CASES[3][0]])
+@pytest.mark.parametrize("case", TWO_NODE, ids=[c[0] for c in TWO_NODE])
 def test_two_node_scheme_matches_oracle(case, precision):
     """Eq. (211): the c1 term applied at the next pull from x_f + e_i."""
     name, geom, s, kw, steps = case
@@ -261,3 +269,59 @@ def test_graph_replay_matches_plain_launches(monkeypatch):
             assert np.array_equal(a[:, fl], b[:, fl])
         else:
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["bgk", "trt"])
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q15", "D3Q19"])
+def test_bgk_trt_rates_match_oracle_collision(lattice, kind, precision):
+    """The MRT kernel with the binding's BGK / TRT rates against the oracle's
+    direct BGK / TRT collision (Remark (1))."""
+    from paper_1712_08288_amd import binding
+    from oracle.lbm import Oracle
+    geom = (G.random_cylinders(50, 37, 3, 3.0, 5.0, seed=21) if lattice == "D2Q9" else
+            G.random_spheres(26, 19, 17, 2, 2.5, 4.0, seed=22, lattice=lattice, x_bc="pressure"))
+    s_nu = 1.35
+    rates = binding.collision_rates(lattice, kind, s_nu)
+    # the oracle side from the definition: s_minus from the magic product 3/16
+    col = ("bgk", s_nu) if kind == "bgk" else \
+        ("trt", s_nu, 1.0 / (0.5 + (3.0 / 16.0) / (1.0 / s_nu - 0.5)))
+    dp = 0.0 if lattice == "D2Q9" else 1e-3
+    g = (1e-5, 3e-6, -2e-6)
+    sv = binding.solver_for(geom, rates, g=g, precision=precision, l_rule="gamma2", dp=dp)
+    o = Oracle(geom, rates, g=g, l_rule="gamma2", dp=dp, collision=col)
+    Q = len(rates)
+    df0 = states.random_deviation(Q, geom.n_nodes, seed=5, amp=1e-3)
+    sv.init_deviation(df0)
+    f = o.init_deviation(df0)
+    sv.step(10)
+    f = o.run(f, 10)
+    fl = geom.solid == 0
+    assert rel_l2(sv.distribution(), o.as_deviation(f), fl) < TOL[precision]
+    sv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_decaying_wall_data_matches_oracle(precision):
+    """phi(x_b, t) = phi(x_b, 0) * lambda^t on moving walls (graph replay is
+    off for lambda != 1); 130 steps cross the 64-step graph length."""
+    from paper_1712_08288_amd import binding
+    from oracle.lbm import Oracle
+    geom = G.random_cylinders(48, 40, 3, 3.5, 6.0, seed=17)
+    wu = np.zeros_like(geom.wall_u)
+    wu[:, 0], wu[:, 1] = 0.02, -0.015
+    geom = geom.with_wall_u(wu)
+    s = configs.d2q9_paper_rates(1.2)
+    lam = 0.995
+    sv = binding.solver_for(geom, s, precision=precision, l_rule="gamma")
+    sv.set_wall_decay(lam)
+    o = Oracle(geom, s, l_rule="gamma", wall_decay=lam)
+    df0 = states.random_deviation(9, geom.n_nodes, seed=4, amp=1e-3)
+    sv.init_deviation(df0)
+    f = o.init_deviation(df0)
+    sv.step(61)
+    sv.step(69)
+    f = o.run(f, 130)
+    fl = geom.solid == 0
+    assert rel_l2(sv.distribution(), o.as_deviation(f), fl) < TOL[precision] * 3
+    sv.close()

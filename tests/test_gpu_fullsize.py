@@ -43,7 +43,7 @@ def _samples(geom, n_random=24, n_link=16, seed=0):
 def _run(w, precision, seed=17):
     from paper_1712_08288_amd import binding
     geom = w.geometry()
-    Q = 9 if geom.lattice == "D2Q9" else 19
+    Q = len(VELOCITIES[geom.lattice])
     print("workload", w.name, precision, geom.shape, "links", geom.n_links, flush=True)
     df0 = states.random_deviation(Q, geom.n_nodes, seed=seed, amp=1e-3)
     if geom.x_bc == "outflow":

@@ -115,3 +115,16 @@ def test_two_node_gradient_seam_d3q19():
     obj = Objective("mean_ux", t0=0, t1=5)
     _check(geom, configs.d3q19_rates(0.65),
            dict(dp=1e-3, l_rule="gamma", two_node=True), obj, 5, n_q=8)
+
+
+def test_decaying_wall_data_gradient():
+    """Wall data phi(x_b, t) = phi(x_b, 0) * lambda^t (the Taylor-Green
+    boundary of Section 3.2): gradients with respect to phi(x_b, 0)."""
+    geom = G.random_cylinders(22, 17, 2, 2.4, 3.6, seed=6)
+    wu = np.zeros_like(geom.wall_u)
+    wu[:, 0] = 0.03
+    wu[:, 1] = -0.01
+    geom = geom.with_wall_u(wu)
+    obj = Objective("force_x", tag=1, t0=1, t1=7)
+    _check(geom, configs.d2q9_rates(0.7),
+           dict(g=(1e-4, 0, 0), l_rule="gamma2", wall_decay=0.93), obj, 7, n_q=10)

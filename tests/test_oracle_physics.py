@@ -26,7 +26,8 @@ def run_steady(o, f, chunk=200, tol=1e-9, max_steps=200_000):
     raise AssertionError("no steady state")
 
 
-def poiseuille_error(ny_mesh, gamma, s_nu, rule, nu=0.03, lattice="D2Q9", two_node=False):
+def poiseuille_error(ny_mesh, gamma, s_nu, rule, nu=0.03, lattice="D2Q9", two_node=False,
+                     collision=None):
     """Paper Section 3.1: h = H/(N_y - 2 + 2 gamma), dt = eta h^2 with
     eta = (1/s_nu - 1/2)/(3 nu); body force G = 0.8 nu, H = 1.  In lattice
     units the force is G dt^2 / h."""
@@ -37,7 +38,7 @@ def poiseuille_error(ny_mesh, gamma, s_nu, rule, nu=0.03, lattice="D2Q9", two_no
     geom = G.poiseuille_channel(ny_mesh, gamma, nx=2, lattice=lattice,
                                 nz=1 if lattice == "D2Q9" else 2)
     s = configs.d2q9_paper_rates(s_nu) if lattice == "D2Q9" else configs.d3q19_rates(1.0 / s_nu)
-    o = Oracle(geom, s, g=(G_lat, 0, 0), l_rule=rule, two_node=two_node)
+    o = Oracle(geom, s, g=(G_lat, 0, 0), l_rule=rule, two_node=two_node, collision=collision)
     x, y, z = geom.coords()
     H = geom.meta["H"]
     nu_lat = (1.0 / s_nu - 0.5) / 3.0
@@ -107,16 +108,19 @@ def test_couette_second_order(rule):
     assert errs[-1] < 2e-3
 
 
-def test_hagen_poiseuille_d3q19_second_order():
-    """Section 3.3 adapted to D3Q19: pipe of radius R along x, force G, the
-    analytic u = U(1 - r^2/R^2), U = G R^2/(4 nu)."""
+@pytest.mark.parametrize("lattice", ["D3Q19", "D3Q15"])
+def test_hagen_poiseuille_second_order(lattice):
+    """Section 3.3: pipe of radius R along x, force G, the analytic
+    u = U(1 - r^2/R^2), U = G R^2/(4 nu); D3Q15 with the Section 3 rates
+    (the paper's own 3D test), D3Q19 with the d'Humieres et al. rates."""
     errs, radii = [], [4.0, 8.0, 16.0]
     for R in radii:
-        geom = G.pipe(R, nx=1)
+        geom = G.pipe(R, nx=1, lattice=lattice)
         s_nu = 1.0
         nu = (1 / s_nu - 0.5) / 3
         Gf = 1e-6
-        o = Oracle(geom, configs.d3q19_rates(1 / s_nu), g=(Gf, 0, 0), l_rule="gamma2")
+        rates = configs.d3q19_rates(1 / s_nu) if lattice == "D3Q19" else configs.d3q15_paper_rates(s_nu)
+        o = Oracle(geom, rates, g=(Gf, 0, 0), l_rule="gamma2")
         x, y, z = geom.coords()
         c = geom.meta["center"]
         r = np.sqrt((y - c[1]) ** 2 + (z - c[2]) ** 2)

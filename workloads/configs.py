@@ -27,6 +27,13 @@ def d2q9_paper_rates(s_nu, literal=False):
     return np.array([1, 1.8, 1.2, 1, 0.5, 1, 0.5, s_nu, s_nu], dtype=np.float64)
 
 
+def d3q15_paper_rates(s_nu):
+    """Rates of the paper's Section 3 for D3Q15, in its Appendix row order
+    (rho, e, eps, jx, qx, jy, qy, jz, qz, pxx, pww, pxy, pyz, pxz, mxyz)."""
+    return np.array([1, 1.8, 1.2, 1, 0.5, 1, 0.5, 1, 0.5,
+                     s_nu, s_nu, s_nu, s_nu, s_nu, 1.5], dtype=np.float64)
+
+
 def d3q19_rates(tau):
     """d'Humieres et al. (2002) rates for D3Q19: s_e = 1.19, s_eps = s_pi =
     1.4, s_q = 1.2, s_m = 1.98, viscous rows 1/tau; conserved rows 0."""
