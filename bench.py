@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per k_step<D3Q19, float> launch on this workload from rocprofv3
 # FETCH_SIZE/WRITE_SIZE (scaled by a copy of known size), valid for the
 # kernel sources with this hash (profiles/k_step_d3q19_fp32_spheres256.md).
-MEASURED_TRAFFIC = {"sources_sha256_16": "3f2795966002f949", "bytes": 2673772701}
+MEASURED_TRAFFIC = {"sources_sha256_16": "a0cacbf4e9982eca", "bytes": 2672630030}
 KERNEL_SOURCES = ["paper_1712_08288_amd/csrc/forward.hip",
                   "paper_1712_08288_amd/csrc/kernels.hpp",
                   "paper_1712_08288_amd/csrc/lattice.hpp"]
@@ -136,7 +136,7 @@ def _rel(a, b):
 
 
 def _progress(what):
-    print("[bench --all] " + what, file=sys.stderr, flush=True)
+    print("[bench] " + what, file=sys.stderr, flush=True)
 
 
 def all_configs(binding, torch):
@@ -323,6 +323,38 @@ def all_configs(binding, torch):
     return out
 
 
+def run_study(name):
+    """One of the paper's Section 3 sweeps on the GPU; one JSON line per
+    (rule, gamma, s_nu, ...) group with the errors and the fitted order."""
+    from paper_1712_08288_amd import studies
+    log = _progress
+    t0 = time.time()
+    if name == "poiseuille":
+        out = studies.poiseuille_study(log=log, max_size_by_snu={1.99: 41})
+    elif name == "taylor_green":
+        out = studies.taylor_green_study(log=log)
+    elif name == "hagen_poiseuille":
+        out = studies.hagen_poiseuille_study(lattice="D3Q15", log=log, max_size_by_snu={1.99: 40})
+    elif name == "hagen_poiseuille_d3q19":
+        out = studies.hagen_poiseuille_study(lattice="D3Q19", log=log, max_size_by_snu={1.99: 40})
+    elif name == "b":
+        out = studies.b_study(log=log)
+    elif name == "b_bgk":   # does b < 1 stabilise BGK / TRT where they fail at b = 1?
+        out = []
+        for col in ("bgk", "trt"):
+            out += studies.b_study(bs=(1.0, 0.9, 0.7, 0.5, 0.3), s_nus=(1.99,), rules=("gamma",),
+                                   sizes=(11, 21, 41), gamma=0.25, collision=col, log=log)
+    else:   # collisions: BGK, TRT and MRT (and Eq. (211)) on the same sweep
+        out = []
+        for kw in (dict(collision="bgk"), dict(collision="trt"), dict(two_node=True)):
+            out += studies.poiseuille_study(rules=["gamma", "gamma2"], gammas=(0.25, 0.75),
+                                            s_nus=(0.5, 1.0, 1.5, 1.99), sizes=(11, 21, 41, 61),
+                                            max_size_by_snu={1.99: 41}, log=log, **kw)
+    for r in out:
+        print(json.dumps({"study": name, **r}), flush=True)
+    _progress("study %s: %d groups in %.0f s" % (name, len(out), time.time() - t0))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +364,9 @@ def main():
     ap.add_argument("--every", type=int, default=8)
     ap.add_argument("--n", type=int, default=256, help="lattice edge (256 = the benchmark)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--study", choices=["poiseuille", "taylor_green", "hagen_poiseuille",
+                                        "hagen_poiseuille_d3q19", "b", "b_bgk", "collisions"],
+                    help="run one of the paper's Section 3 sweeps on the GPU instead")
     ap.add_argument("--all", action="store_true",
                     help="also measure every workload (C1-C5) into 'per_config'")
     ap.add_argument("--only", choices=["fwd32", "fwd64", "adjoint32", "copy"],
@@ -348,6 +383,10 @@ def main():
     torch.cuda.set_device(0)
     from paper_1712_08288_amd import binding
     from workloads import configs
+
+    if args.study:
+        run_study(args.study)
+        return
 
     if args.only == "copy":
         # reference copies of known size: HBM ceiling and counter scaling

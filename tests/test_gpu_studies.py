@@ -1,0 +1,54 @@
+"""Section 3's convergence claims on the GPU, on small subsets of the sweeps
+(the full sweeps run with `python bench.py --study ...`).  The paper reports
+orders "around 2" for every rule, gamma and s_nu; bounds here are wide
+enough for three-point fits on coarse meshes."""
+
+import pytest
+
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_poiseuille_second_order_on_gpu():
+    from paper_1712_08288_amd import studies
+    out = studies.poiseuille_study(rules=["gamma", "gamma2", "2gamma"], gammas=(0.25, 0.75),
+                                   s_nus=(1.0,), sizes=(11, 21, 41))
+    for r in out:
+        print(r["rule"], r["gamma"], r["errors"], r["order"], flush=True)
+        assert all(st == "converged" for st in r["status"]), r
+        assert 1.85 < r["order"] < 2.15, r
+
+
+def test_poiseuille_bgk_trt_two_node_on_gpu():
+    from paper_1712_08288_amd import studies
+    for kw in (dict(collision="bgk"), dict(collision="trt"), dict(two_node=True)):
+        out = studies.poiseuille_study(rules=["gamma"], gammas=(0.25,), s_nus=(1.2,),
+                                       sizes=(11, 21, 41), **kw)
+        for r in out:
+            print(kw, r["errors"], r["order"], flush=True)
+            assert 1.85 < r["order"] < 2.15, r
+
+
+def test_taylor_green_second_order_on_gpu():
+    from paper_1712_08288_amd import studies
+    out = studies.taylor_green_study(rules=["gamma", "gamma2"], s_nus=(1.0,), inv_hs=(40, 80, 120))
+    for r in out:
+        print(r["rule"], r["errors"], r["order"], flush=True)
+        assert all(st == "done" for st in r["status"]), r
+        assert 1.6 < r["order"] < 2.6, r
+
+
+def test_hagen_poiseuille_d3q15_second_order_on_gpu():
+    from paper_1712_08288_amd import studies
+    out = studies.hagen_poiseuille_study(rules=["gamma", "1.5gamma"], s_nus=(1.0,),
+                                         inv_hs=(10, 20, 40), lattice="D3Q15")
+    for r in out:
+        print(r["rule"], r["errors"], r["order"], flush=True)
+        assert all(st == "converged" for st in r["status"]), r
+        assert 1.6 < r["order"] < 2.6, r
