@@ -309,15 +309,19 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
             finish(std::integral_constant<int, ib>{}, ev[pp] - od[pp]);
         });
 
-        // dJ/dg += 3 rho0 sum_i w_i e_i mu_i (pair form: w_i e_i (mu_i - mu_ibar))
+        // dJ/dg += 3 rho0 sum_i w_i e_i mu_i (pair form: w_i e_i (mu_i - mu_ibar)),
+        // summed over the node in T, accumulated over nodes in double
+        T sg[3] = {0, 0, 0};
         unroll<NP>([&](auto P) {
             constexpr int pp = decltype(P)::value;
             constexpr int i = DER<L>.pi[pp];
-            const double t = 3.0 * L::W[i] * p.rho0_d * (double)dmu[pp];
-#pragma unroll
-            for (int al = 0; al < D; ++al)
-                if (L::E[i][al] != 0) acc[al] += L::E[i][al] * t;
+            const T t = T(L::W[i]) * dmu[pp];
+            macc<L::E[i][0]>(sg[0], t);
+            macc<L::E[i][1]>(sg[1], t);
+            macc<L::E[i][2]>(sg[2], t);
         });
+#pragma unroll
+        for (int al = 0; al < D; ++al) acc[al] += 3.0 * p.rho0_d * (double)sg[al];
         if constexpr (WANT_DS) {
             // dJ/ds_k -= (M mu)_k (M (f - f^eq))_k / |M_k|^2
             T m[Q];
@@ -445,6 +449,8 @@ static Params<L, T> adj_params(const Engine& e) {
     Params<L, T> p;
     for (int k = 0; k < L::Q; ++k)
         p.rate[k] = (T)(L::conserved(k) ? 0.0 : e.s[k] / (double)TAB<L>.norm[k]);
+    for (int a = 0; a < 3; ++a) p.G[a] = (T)(3.0 * e.rho0 * (a < L::D ? e.g[a] : 0.0));
+    p.drho = (T)(e.xbc == XBC_PRESSURE ? e.drho : 0.0);
     for (int i = 0; i < L::Q; ++i) {
         double eg = 0;
         for (int a = 0; a < L::D; ++a) eg += L::E[i][a] * e.g[a];

@@ -879,23 +879,34 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
     Engine& e = h->e;
     if (!e.initialized) return fail(h, LBM_ESTATE, "initialise before running");
     if (n < 1 || every < 1) return fail(h, LBM_EINVAL, "n and every must be >= 1");
-    free_run(e);
+    // checkpoint buffers are kept between runs of the same length (the
+    // replay pool and adjoint arrays are kept by lbm_adjoint likewise)
     const int64_t nck = (n + every - 1) / every;
-    e.ckpt.resize(nck);
-    for (auto& s : e.ckpt) {
-        int rc = alloc_snap(h, s);
-        if (rc) {
-            free_run(e);
-            return rc;
+    if ((int64_t)e.ckpt.size() != nck) {
+        free_run(e);
+        e.ckpt.resize(nck);
+        for (auto& s : e.ckpt) {
+            int rc = alloc_snap(h, s);
+            if (rc) {
+                free_run(e);
+                return rc;
+            }
         }
     }
     e.run_t0 = e.t;
     e.run_n = n;
     e.run_every = every;
+    // a checkpoint takes the current state's buffers (the state it must
+    // keep) and hands its own, unused ones to the ping-pong pair: no copies
+    drop_graphs(e);
     for (int64_t s = 0; s < n; ++s) {
         int rc;
-        if (s % every == 0 && (rc = copy_snap(h, e.ckpt[s / every], e.buf[e.cur]))) return rc;
-        if ((rc = forward_step(h, e.buf[e.cur], e.buf[e.cur ^ 1], true))) return rc;
+        const Snapshot* in = &e.buf[e.cur];
+        if (s % every == 0) {
+            std::swap(e.ckpt[s / every], e.buf[e.cur]);
+            in = &e.ckpt[s / every];
+        }
+        if ((rc = forward_step(h, *in, e.buf[e.cur ^ 1], true))) return rc;
         e.cur ^= 1;
         ++e.t;
         e.stepped = true;
@@ -919,9 +930,11 @@ int lbm_adjoint(lbm_t* h) {
     }
     if ((int64_t)e.pool.size() != e.run_every + 1) {
         for (auto& s : e.pool) free_snap(s);
+        // pool[r] holds the replayed state r of a segment; state 0 is the
+        // checkpoint itself, so pool[0] stays empty
         e.pool.assign(e.run_every + 1, Snapshot{});
-        for (auto& s : e.pool)
-            if ((rc = alloc_snap(h, s))) return rc;
+        for (size_t k = 1; k < e.pool.size(); ++k)
+            if ((rc = alloc_snap(h, e.pool[k]))) return rc;
     }
     const int NC = e.D + e.Q;
     const int64_t nb = lbe::step_blocks(e);
@@ -946,10 +959,11 @@ int lbm_adjoint(lbm_t* h) {
     for (int64_t j = nseg - 1; j >= 0; --j) {
         const int64_t t_seg = e.run_t0 + j * e.run_every;
         const int64_t len = std::min(e.run_every, e.run_n - j * e.run_every);
-        if ((rc = copy_snap(h, e.pool[0], e.ckpt[j]))) return rc;
+        // the segment's states: the checkpoint itself, then the replayed ones
+        auto state = [&](int64_t r) -> const Snapshot& { return r == 0 ? e.ckpt[j] : e.pool[r]; };
         for (int64_t r = 0; r < len; ++r) {
-            e.t = t_seg + r;   // forward_step reads e.t only for the objective window
-            if ((rc = forward_step(h, e.pool[r], e.pool[r + 1], false))) {
+            e.t = t_seg + r;   // forward_step reads e.t for the objective window and wall data
+            if ((rc = forward_step(h, state(r), e.pool[r + 1], false))) {
                 e.t = t_saved;
                 return rc;
             }
@@ -967,7 +981,7 @@ int lbm_adjoint(lbm_t* h) {
             e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
             if (e.two_node) st = lbe::launch_two_node_adjoint(e, e.pool[r + 1], e.lam[lc], ao);
             if (st == hipSuccess)
-                st = lbe::launch_adjoint_step(e, e.pool[r], e.lam[lc], e.lam[lc ^ 1], ao);
+                st = lbe::launch_adjoint_step(e, state(r), e.lam[lc], e.lam[lc ^ 1], ao);
             if (st != hipSuccess) {
                 e.t = t_saved;
                 return fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));

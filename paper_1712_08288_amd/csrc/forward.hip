@@ -91,9 +91,9 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
     double ux_local = 0.0;
     if (kind == WAVE_PLAIN) {
         T f[L::Q];
-        pull<L, T, XB>(A, waA, g, pos, p, NodeLinks{0u, 0u}, f);
+        pull<L, T, XB, false, kStepTables<T>>(A, waA, g, pos, p, NodeLinks{0u, 0u}, f);
         Macro<L, T> mac;
-        collide<L, T>(f, p, mac);
+        collide<L, T, false, kStepTables<T>>(f, p, mac);
         ux_local = (double)mac.u[0];
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
@@ -108,7 +108,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
         T f[L::Q];
         if (pos.in) {
-            pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
+            pull_planes<L, T, XB, false, kStepTables<T>>(A, g, pos, p, NodeLinks{0u, 0u}, f);
         } else {
             unroll<L::Q>([&](auto I) { f[decltype(I)::value] = T(0); });
         }
@@ -122,7 +122,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             fpre[i] = f[i];
         });
         Macro<L, T> mac;
-        collide<L, T>(f, p, mac);
+        collide<L, T, false, kStepTables<T>>(f, p, mac);
         if (pos.in) {
             if (!sol) ux_local = (double)mac.u[0];
             const T nan = (T)__builtin_nan("");
@@ -186,8 +186,8 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
         T v = (T)f[i];
         if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
             const int sg = seam_sign<L, i>(pos.ix, g.nx);
-            if (sg > 0) v -= p.seam[i];
-            else if (sg < 0) v += p.seam[i];
+            if (sg > 0) v -= seam_of<L, i, false>(p);
+            else if (sg < 0) v += seam_of<L, i, false>(p);
         }
         A[(size_t)i * g.S + pl.template src<L, i>()] = v;
     });
@@ -405,6 +405,8 @@ static Params<L, T> make_params(const Engine& e) {
         const double r = L::conserved(k) ? 0.0 : e.s[k] / (double)TAB<L>.norm[k];
         p.rate[k] = (T)r;
     }
+    for (int a = 0; a < 3; ++a) p.G[a] = (T)(3.0 * e.rho0 * (a < L::D ? e.g[a] : 0.0));
+    p.drho = (T)(e.xbc == XBC_PRESSURE ? e.drho : 0.0);
     for (int i = 0; i < L::Q; ++i) {
         double eg = 0;
         for (int a = 0; a < L::D; ++a) eg += L::E[i][a] * e.g[a];

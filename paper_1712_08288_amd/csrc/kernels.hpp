@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "lattice.hpp"
 
@@ -90,8 +91,10 @@ __device__ __forceinline__ int seam_sign(uint32_t ix, uint32_t nx) {
 template <class L, class T>
 struct Params {
     T rate[L::Q];     // s_k / |M_k|^2, zero for conserved rows
-    T force[L::Q];    // 3 w_i rho0 e_i.g
-    T seam[L::Q];     // w_i drho (pressure-jump boundary)
+    T G[3];           // 3 rho0 g: the forcing term is F_i = w_i e_i.G
+    T drho;           // pressure-jump boundary: the seam term is w_i drho
+    T force[L::Q];    // the same two terms tabulated per population
+    T seam[L::Q];
     T rho0, inv_rho0;
     double c0;        // 1 - b of Eq. (213)
     double rho0_d;
@@ -106,6 +109,33 @@ __device__ __forceinline__ void macc(T& acc, T v) {
     else if constexpr (C == -1) acc -= v;
     else if constexpr (C != 0) acc = fma(T(C), v, acc);
 }
+
+// Forcing term F_i = 3 w_i rho0 e_i.g of population I, and the seam term
+// w_i drho: from the tables (FTAB) or from the few runtime scalars they depend
+// on.  A kernel loads only the arguments it uses into scalar registers; the
+// scalars keep the adjoint and the FP64 step free of scalar-register spills,
+// the tables keep the FP32 step's arithmetic lowest (both measured).
+template <class L, int I, bool FTAB, class T>
+__device__ __forceinline__ T force_of(const Params<L, T>& p) {
+    if constexpr (FTAB) {
+        return p.force[I];
+    } else {
+        T eg = T(0);
+        macc<L::E[I][0]>(eg, p.G[0]);
+        macc<L::E[I][1]>(eg, p.G[1]);
+        macc<L::E[I][2]>(eg, p.G[2]);
+        return T(L::W[I]) * eg;
+    }
+}
+template <class L, int I, bool FTAB, class T>
+__device__ __forceinline__ T seam_of(const Params<L, T>& p) {
+    if constexpr (FTAB) return p.seam[I];
+    else return T(L::W[I]) * p.drho;
+}
+
+// the step kernel's choice of the two forms above
+template <class T>
+inline constexpr bool kStepTables = std::is_same<T, float>::value;
 
 template <class L, class T>
 struct Macro {
@@ -255,7 +285,7 @@ __device__ __forceinline__ void back_transform(const T (&r)[L::Q], T& e0,
 // (the rates arrive already divided by |M_k|^2).  m^eq is the projection of
 // Eq. (42), so M f - m^eq = M (f - f^eq) exactly in real arithmetic.
 // Optionally returns the non-equilibrium moments (M (f - f^eq))_k.
-template <class L, class T, bool KEEP_NEQ = false>
+template <class L, class T, bool KEEP_NEQ = false, bool FTAB = false>
 __device__ __forceinline__ void collide(T (&f)[L::Q], const Params<L, T>& p,
                                         Macro<L, T>& mac, T* neq = nullptr) {
     constexpr int NP = NPAIR<L>;
@@ -282,7 +312,7 @@ __device__ __forceinline__ void collide(T (&f)[L::Q], const Params<L, T>& p,
         constexpr int pp = decltype(P)::value;
         constexpr int i = DER<L>.pi[pp];
         constexpr int ib = TAB<L>.opp[i];
-        const T o = od[pp] - p.force[i];    // F_ibar = -F_i
+        const T o = od[pp] - force_of<L, i, FTAB>(p);    // F_ibar = -F_i
         f[i] = f[i] - ev[pp] - o;
         f[ib] = f[ib] - ev[pp] + o;
     });
@@ -357,7 +387,7 @@ __device__ __forceinline__ uint32_t link_index(const NodeLinks& nl, int i) {
 
 // Read the planes of a pull: f_i = A_i(x - e_i) (+ seam term).  With PRED
 // the planes of cut-link directions are not read.
-template <class L, class T, int XB, bool PRED = false>
+template <class L, class T, int XB, bool PRED = false, bool FTAB = false>
 __device__ __forceinline__ void pull_planes(const T* __restrict__ A, const Grid& g,
                                             const NodePos& pos, const Params<L, T>& p,
                                             const NodeLinks& nl, T (&f)[L::Q]) {
@@ -371,8 +401,8 @@ __device__ __forceinline__ void pull_planes(const T* __restrict__ A, const Grid&
         f[i] = ld(A + (size_t)i * g.S, pl.template src<L, i>());
         if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
             const int sg = seam_sign<L, i>(pos.ix, g.nx);
-            if (sg > 0) f[i] += p.seam[i];
-            else if (sg < 0) f[i] -= p.seam[i];
+            if (sg > 0) f[i] += seam_of<L, i, FTAB>(p);
+            else if (sg < 0) f[i] -= seam_of<L, i, FTAB>(p);
         }
     });
 }
@@ -459,12 +489,12 @@ __device__ __forceinline__ void wave_link_values(const T* __restrict__ wa, uint3
 }
 
 // Pull the pre-collision state f(x, t) of one fluid node.
-template <class L, class T, int XB, bool PRED = false>
+template <class L, class T, int XB, bool PRED = false, bool FTAB = false>
 __device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restrict__ wa,
                                      const Grid& g, const NodePos& pos,
                                      const Params<L, T>& p, const NodeLinks& nl,
                                      T (&f)[L::Q]) {
-    pull_planes<L, T, XB, PRED>(A, g, pos, p, nl, f);
+    pull_planes<L, T, XB, PRED, FTAB>(A, g, pos, p, nl, f);
     apply_links<L, T>(wa, p, nl, f);
 }
 
@@ -494,8 +524,8 @@ __device__ __forceinline__ T pull_one(const T* __restrict__ A, const Grid& g,
             const uint32_t src = (uint32_t)sx + g.nx * ((uint32_t)sy + g.ny * (uint32_t)sz);
             out = A[(size_t)ii * g.S + src];
             if (XB == XBC_PRESSURE) {
-                if (sg > 0) out += p.seam[ii];
-                else if (sg < 0) out -= p.seam[ii];
+                if (sg > 0) out += seam_of<L, ii, false>(p);
+                else if (sg < 0) out -= seam_of<L, ii, false>(p);
             }
         }
     });
