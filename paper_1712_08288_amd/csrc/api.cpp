@@ -959,9 +959,18 @@ int lbm_adjoint(lbm_t* h) {
     for (int64_t j = nseg - 1; j >= 0; --j) {
         const int64_t t_seg = e.run_t0 + j * e.run_every;
         const int64_t len = std::min(e.run_every, e.run_n - j * e.run_every);
-        // the segment's states: the checkpoint itself, then the replayed ones
-        auto state = [&](int64_t r) -> const Snapshot& { return r == 0 ? e.ckpt[j] : e.pool[r]; };
-        for (int64_t r = 0; r < len; ++r) {
+        // the segment's states: the checkpoint itself, then the replayed
+        // ones.  The adjoint of step r reads state r; Eq. (211)'s pre-pass
+        // also reads state r + 1, which for r = len - 1 is the next
+        // checkpoint (replayed only for the last segment).  So the replay
+        // stops at state len - 1 unless that last state is needed.
+        auto state = [&](int64_t r) -> const Snapshot& {
+            if (r == 0) return e.ckpt[j];
+            if (r == len && j + 1 < nseg) return e.ckpt[j + 1];
+            return e.pool[r];
+        };
+        const int64_t nrep = e.two_node && j + 1 == nseg ? len : len - 1;
+        for (int64_t r = 0; r < nrep; ++r) {
             e.t = t_seg + r;   // forward_step reads e.t for the objective window and wall data
             if ((rc = forward_step(h, state(r), e.pool[r + 1], false))) {
                 e.t = t_saved;
@@ -979,7 +988,7 @@ int lbm_adjoint(lbm_t* h) {
             if (!in_w) ao.kind = LBM_OBJ_NONE;
             hipError_t st = hipSuccess;
             e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
-            if (e.two_node) st = lbe::launch_two_node_adjoint(e, e.pool[r + 1], e.lam[lc], ao);
+            if (e.two_node) st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
             if (st == hipSuccess)
                 st = lbe::launch_adjoint_step(e, state(r), e.lam[lc], e.lam[lc ^ 1], ao);
             if (st != hipSuccess) {
