@@ -64,3 +64,15 @@ def test_create_rejects_bad_arguments_before_touching_a_device(binding):
 
 def test_lattice_info_rejects_unknown_lattice(binding):
     assert binding._lib.lbm_lattice_info(5, None, None, None, None, None) == -1
+
+
+def test_create_rejects_planes_of_4gib_or_more(binding):
+    """One direction plane must stay below 4 GiB (32-bit byte offsets):
+    rejected at create, before any device call."""
+    lib = binding._lib
+    h = ctypes.c_void_p()
+    s = (ctypes.c_double * 19)(*([1.0] * 19))
+    g = (ctypes.c_double * 3)(0, 0, 0)
+    EINVAL = -1
+    assert lib.lbm_create(ctypes.byref(h), 1, 1, 1024, 1024, 1024, s, 1.0, g) == EINVAL
+    assert lib.lbm_create(ctypes.byref(h), 1, 0, 1024, 1024, 512, s, 1.0, g) == EINVAL

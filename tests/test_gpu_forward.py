@@ -325,3 +325,57 @@ def test_decaying_wall_data_matches_oracle(precision):
     fl = geom.solid == 0
     assert rel_l2(sv.distribution(), o.as_deviation(f), fl) < TOL[precision] * 3
     sv.close()
+
+
+# ----------------------------------------------------------------------------
+# edge cases
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_domain_without_cut_links(precision):
+    """No solid node and no link: every wave is plain."""
+    geom = G.empty("D3Q19", (70, 9, 7))
+    got, want, fl, sv, o, f = pair(geom, configs.d3q19_rates(0.8), 15, precision=precision,
+                                   g=(2e-5, -1e-5, 3e-6))
+    assert geom.n_links == 0
+    assert rel_l2(got, want, fl) < TOL[precision]
+    sv.close()
+
+
+@pytest.mark.parametrize("lattice", ["D3Q19", "D3Q15"])
+def test_single_column_pipe(lattice):
+    """nx = 1: every x pull wraps onto the node's own column."""
+    geom = G.pipe(5.3, nx=1, lattice=lattice)
+    s = configs.d3q19_rates(0.9) if lattice == "D3Q19" else configs.d3q15_paper_rates(1.1)
+    got, want, fl, sv, o, f = pair(geom, s, 20, g=(1e-5, 0, 0), l_rule="gamma")
+    assert rel_l2(got, want, fl) < TOL["fp64"]
+    sv.close()
+
+
+@pytest.mark.parametrize("two_node", [False, True])
+def test_one_node_wide_gap(two_node):
+    """A channel one node wide: every fluid node has cut links in both +y and
+    -y (the single-node scheme needs no second fluid node; Eq. (211) falls
+    back to Eq. (210) on links whose x_f + e_i is solid)."""
+    geom = G.build("D2Q9", (40, 3, 1),
+                   planes=[G.PlaneWall(1, -1, 0, 1 - 0.37), G.PlaneWall(1, +1, 2, 1 + 0.81)])
+    assert (geom.solid == 0).sum() == 40
+    got, want, fl, sv, o, f = pair(geom, configs.d2q9_rates(0.7), 30, g=(1e-5, 0, 0),
+                                   l_rule="gamma2", two_node=two_node)
+    assert rel_l2(got, want, fl) < TOL["fp64"]
+    sv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_degenerate_link_fractions_and_small_b(precision):
+    """gamma at the ends of (0, 1] (1e-9 and exactly 1) and b = 0.1."""
+    geom = G.random_cylinders(60, 41, 3, 3.5, 6.0, seed=27)
+    q = geom.q.copy()
+    q[::5] = 1e-9
+    q[1::5] = 1.0
+    geom = geom.with_q(q)
+    for rule in ("gamma", "min"):
+        got, want, fl, sv, o, f = pair(geom, configs.d2q9_rates(0.65), 20, precision=precision,
+                                       g=(1e-5, 0, 0), l_rule=rule, b=0.1)
+        assert rel_l2(got, want, fl) < TOL[precision], rule
+        sv.close()
