@@ -209,16 +209,40 @@ int lbm_objective(lbm_t *h, double *J);
 
 /* Run n steps from the current state keeping a snapshot every `every` steps
  * in library-owned device memory, so that lbm_adjoint() can later replay
- * each segment (sqrt(n) checkpointing when every ~ sqrt(n)).  Memory:
- * (n/every + 1) + (every + 1) states of lbm_state_bytes().  The objective
+ * each segment (sqrt(n) checkpointing when every ~ sqrt(n); every = 1 keeps
+ * every state and needs no replay).  A snapshot is taken by exchanging
+ * buffers with the current state, without a copy, and the snapshot buffers
+ * are kept for the next run with the same snapshot count.  Memory: ceil(n /
+ * every) snapshots, plus `every` replay states and two adjoint arrays
+ * allocated by lbm_adjoint(), all of lbm_state_bytes().  The objective
  * accumulates as in lbm_step.  Errors: ESTATE, EINVAL, ENOMEM. */
 int lbm_run_checkpointed(lbm_t *h, int64_t n, int64_t every);
 
 /* Reverse sweep over the last lbm_run_checkpointed() run: for each segment
- * from the last, restore its snapshot, replay it recording every state, and
- * run the adjoint steps backwards, accumulating in double the gradients of
- * the objective.  Leaves the forward state at the end of the run. */
+ * from the last, replay it from its snapshot as far as the adjoint reads it
+ * (every state but the segment's last; Eq. (211) also reads the next
+ * snapshot), and run the adjoint steps backwards, accumulating in double
+ * the gradients of the objective.  The wall-data factor of
+ * lbm_set_wall_decay applies at each step's time.  Leaves the forward state
+ * at the end of the run; can be called again on the same run.  Errors:
+ * ESTATE (no run), ENOMEM, EDEVICE. */
 int lbm_adjoint(lbm_t *h);
+
+/* The same reverse sweep in pieces: n more adjoint steps backwards (fewer
+ * when the sweep reaches the run's first step; n = 0 only starts it).  The
+ * first call after lbm_run_checkpointed() starts a sweep from the run's end
+ * (zeroing the gradient sums); lbm_adjoint() always starts a new one.
+ * Between calls lbm_get_adjoint() returns lambda at the sweep's current
+ * time and lbm_grad() the sums so far; the whole sweep in any number of
+ * pieces gives the same values, bit for bit, as lbm_adjoint().  Changing
+ * links, parameters or the objective before the sweep ends makes it
+ * inconsistent with the recorded run.  Errors: as lbm_adjoint, EINVAL for
+ * n < 0. */
+int lbm_adjoint_step(lbm_t *h, int64_t n);
+
+/* Steps the current reverse sweep still has to go (0 when it has reached
+ * the run's first step), or -1 when no sweep has started. */
+int64_t lbm_adjoint_remaining(const lbm_t *h);
 
 /* Choose whether lbm_adjoint() accumulates dJ/ds for the relaxation rates
  * (a block reduction of Q extra sums per step; default on).  When off,

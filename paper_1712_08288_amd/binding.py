@@ -42,6 +42,8 @@ _set_scheme = _sig("lbm_set_scheme", _i, [_p, _i, _d])
 _set_xbc = _sig("lbm_set_x_boundary", _i, [_p, _i, _d])
 _set_two_node = _sig("lbm_set_two_node", _i, [_p, _i])
 _set_wall_decay = _sig("lbm_set_wall_decay", _i, [_p, C.c_double])
+_adj_step = _sig("lbm_adjoint_step", _i, [_p, C.c_int64])
+_adj_remaining = _sig("lbm_adjoint_remaining", C.c_int64, [_p])
 _set_geometry = _sig("lbm_set_geometry", _i, [_p, _p, _i64, _p, _p, _p, _p, _p])
 _update_links = _sig("lbm_update_links", _i, [_p, _p, _p])
 _set_params = _sig("lbm_set_parameters", _i, [_p, _p, _p])
@@ -79,7 +81,7 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_get_distribution", "lbm_reduce", "lbm_force",
             "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
             "lbm_set_objective", "lbm_objective", "lbm_run_checkpointed",
-            "lbm_adjoint", "lbm_set_rate_gradient", "lbm_grad", "lbm_get_adjoint", "lbm_set_stream",
+            "lbm_adjoint", "lbm_adjoint_step", "lbm_adjoint_remaining", "lbm_set_rate_gradient", "lbm_grad", "lbm_get_adjoint", "lbm_set_stream",
             "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
             "lbm_last_step_ms", "lbm_stream_copy", "lbm_last_error",
             "lbm_destroy"]
@@ -318,6 +320,13 @@ class Solver:
 
     def adjoint(self):
         self._chk(_adjoint(self._h), "adjoint")
+
+    def adjoint_step(self, n):
+        """n more steps of the reverse sweep (resumable)."""
+        self._chk(_adj_step(self._h, int(n)), "adjoint_step")
+
+    def adjoint_remaining(self):
+        return int(_adj_remaining(self._h))
 
     def set_rate_gradient(self, on=True):
         self._chk(_set_rate_grad(self._h, 1 if on else 0), "set_rate_gradient")

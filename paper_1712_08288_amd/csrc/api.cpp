@@ -325,6 +325,117 @@ int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumul
 }  // namespace
 
 // =============================================================================
+// -- reverse sweep ---------------------------------------------------------
+// The sweep runs over the steps of the last checkpointed run from the last
+// one backwards; adj_next is the next step to reverse (relative to run_t0),
+// adj_seg the segment whose states the replay pool holds, and lam[0] holds
+// lambda at the sweep's current time between calls.
+
+namespace {
+
+int adjoint_begin(lbm_t* h) {
+    Engine& e = h->e;
+    if (e.run_t0 < 0 || e.ckpt.empty())
+        return fail(h, LBM_ESTATE, "no checkpointed run to reverse");
+    int rc;
+    const size_t lam_bytes = f_bytes(e);
+    for (auto& l : e.lam) {
+        if (!l && hipMalloc(&l, lam_bytes) != hipSuccess) {
+            l = nullptr;
+            return fail(h, LBM_ENOMEM, "adjoint array allocation failed");
+        }
+    }
+    if ((int64_t)e.pool.size() != e.run_every + 1) {
+        for (auto& s : e.pool) free_snap(s);
+        // pool[r] holds the replayed state r of a segment; state 0 is the
+        // checkpoint itself, so pool[0] stays empty
+        e.pool.assign(e.run_every + 1, Snapshot{});
+        for (size_t k = 1; k < e.pool.size(); ++k)
+            if ((rc = alloc_snap(h, e.pool[k]))) return rc;
+    }
+    const int NC = e.D + e.Q;
+    const int64_t nb = lbe::step_blocks(e);
+    const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
+    if (!e.d_gq || e.gglob_len != nb || e.gq_len != (int64_t)L1) {
+        free_dev(e.d_gq);
+        free_dev(e.d_gphi);
+        free_dev(e.d_gglob);
+        if (hipMalloc((void**)&e.d_gq, L1 * 8) != hipSuccess ||
+            hipMalloc((void**)&e.d_gphi, L1 * e.D * 8) != hipSuccess ||
+            hipMalloc((void**)&e.d_gglob, (size_t)nb * NC * 8) != hipSuccess)
+            return fail(h, LBM_ENOMEM, "gradient accumulator allocation failed");
+        e.gglob_len = nb;
+        e.gq_len = (int64_t)L1;
+    }
+    if ((rc = zero(h, e.d_gq, L1 * 8))) return rc;
+    if ((rc = zero(h, e.d_gphi, L1 * e.D * 8))) return rc;
+    if ((rc = zero(h, e.d_gglob, (size_t)nb * NC * 8))) return rc;
+    if ((rc = zero(h, e.lam[0], lam_bytes))) return rc;
+    e.adj_next = e.run_n - 1;
+    e.adj_seg = -1;
+    e.adj_started = true;
+    e.have_grad = true;   // partial sums are available from here on
+    return LBM_OK;
+}
+
+// n more reverse steps (fewer at the start of the run)
+int adjoint_steps(lbm_t* h, int64_t n) {
+    Engine& e = h->e;
+    const int64_t nseg = (int64_t)e.ckpt.size();
+    const int64_t t_saved = e.t;
+    int lc = 0;   // lam[lc] holds lambda(t+1)
+    int rc = LBM_OK;
+    for (; n > 0 && e.adj_next >= 0; --n, --e.adj_next) {
+        const int64_t j = e.adj_next / e.run_every;
+        const int64_t r = e.adj_next - j * e.run_every;
+        const int64_t t_seg = e.run_t0 + j * e.run_every;
+        const int64_t len = std::min(e.run_every, e.run_n - j * e.run_every);
+        // the segment's states: the checkpoint itself, then the replayed
+        // ones.  The adjoint of step r reads state r; Eq. (211)'s pre-pass
+        // also reads state r + 1, which for r = len - 1 is the next
+        // checkpoint (replayed only for the last segment).  So the replay
+        // stops at state len - 1 unless that last state is needed.
+        auto state = [&](int64_t k) -> const Snapshot& {
+            if (k == 0) return e.ckpt[j];
+            if (k == len && j + 1 < nseg) return e.ckpt[j + 1];
+            return e.pool[k];
+        };
+        if (e.adj_seg != j) {
+            const int64_t nrep = e.two_node && j + 1 == nseg ? len : len - 1;
+            for (int64_t k = 0; k < nrep; ++k) {
+                e.t = t_seg + k;   // forward_step reads e.t for the objective window and wall data
+                if ((rc = forward_step(h, state(k), e.pool[k + 1], false))) break;
+            }
+            if (rc) break;
+            e.adj_seg = j;
+        }
+        const int64_t t = t_seg + r;
+        lbe::AdjointObjective ao;
+        ao.kind = e.obj_kind;
+        ao.tag = e.obj_tag;
+        const bool in_w = e.obj_kind != LBM_OBJ_NONE && t >= e.obj_t0 && t < e.obj_t1;
+        ao.weight = in_w ? 1.0 / (double)(e.obj_t1 - e.obj_t0) : 0.0;
+        ao.inv_nfluid = e.n_fluid ? 1.0 / (double)e.n_fluid : 0.0;
+        if (!in_w) ao.kind = LBM_OBJ_NONE;
+        hipError_t st = hipSuccess;
+        e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
+        if (e.two_node) st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
+        if (st == hipSuccess)
+            st = lbe::launch_adjoint_step(e, state(r), e.lam[lc], e.lam[lc ^ 1], ao);
+        if (st != hipSuccess) {
+            rc = fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));
+            break;
+        }
+        lc ^= 1;
+    }
+    e.t = t_saved;
+    // keep lambda at the sweep's current time in lam[0]
+    if (lc != 0) std::swap(e.lam[0], e.lam[1]);
+    return rc;
+}
+
+}  // namespace
+
 extern "C" {
 
 int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
@@ -593,6 +704,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     e.has_geometry = true;
     e.initialized = false;
     e.have_grad = false;
+    e.adj_started = false;
     return sync(h);
 }
 
@@ -912,97 +1024,31 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
         e.stepped = true;
     }
     e.have_grad = false;
+    e.adj_started = false;
     return LBM_OK;
 }
 
+
 int lbm_adjoint(lbm_t* h) {
     if (!h) return LBM_EINVAL;
-    Engine& e = h->e;
-    if (e.run_t0 < 0 || e.ckpt.empty())
-        return fail(h, LBM_ESTATE, "no checkpointed run to reverse");
-    int rc;
-    const size_t lam_bytes = f_bytes(e);
-    for (auto& l : e.lam) {
-        if (!l && hipMalloc(&l, lam_bytes) != hipSuccess) {
-            l = nullptr;
-            return fail(h, LBM_ENOMEM, "adjoint array allocation failed");
-        }
-    }
-    if ((int64_t)e.pool.size() != e.run_every + 1) {
-        for (auto& s : e.pool) free_snap(s);
-        // pool[r] holds the replayed state r of a segment; state 0 is the
-        // checkpoint itself, so pool[0] stays empty
-        e.pool.assign(e.run_every + 1, Snapshot{});
-        for (size_t k = 1; k < e.pool.size(); ++k)
-            if ((rc = alloc_snap(h, e.pool[k]))) return rc;
-    }
-    const int NC = e.D + e.Q;
-    const int64_t nb = lbe::step_blocks(e);
-    free_dev(e.d_gq);
-    free_dev(e.d_gphi);
-    free_dev(e.d_gglob);
-    const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
-    if (hipMalloc((void**)&e.d_gq, L1 * 8) != hipSuccess ||
-        hipMalloc((void**)&e.d_gphi, L1 * e.D * 8) != hipSuccess ||
-        hipMalloc((void**)&e.d_gglob, (size_t)nb * NC * 8) != hipSuccess)
-        return fail(h, LBM_ENOMEM, "gradient accumulator allocation failed");
-    e.gglob_len = nb;
-    if ((rc = zero(h, e.d_gq, L1 * 8))) return rc;
-    if ((rc = zero(h, e.d_gphi, L1 * e.D * 8))) return rc;
-    if ((rc = zero(h, e.d_gglob, (size_t)nb * NC * 8))) return rc;
-    if ((rc = zero(h, e.lam[0], lam_bytes))) return rc;
-    if ((rc = zero(h, e.lam[1], lam_bytes))) return rc;
+    const int rc = adjoint_begin(h);
+    if (rc) return rc;
+    return adjoint_steps(h, h->e.run_n);
+}
 
-    int lc = 0;   // lam[lc] holds lambda(t+1)
-    const int64_t nseg = (int64_t)e.ckpt.size();
-    const int64_t t_saved = e.t;
-    for (int64_t j = nseg - 1; j >= 0; --j) {
-        const int64_t t_seg = e.run_t0 + j * e.run_every;
-        const int64_t len = std::min(e.run_every, e.run_n - j * e.run_every);
-        // the segment's states: the checkpoint itself, then the replayed
-        // ones.  The adjoint of step r reads state r; Eq. (211)'s pre-pass
-        // also reads state r + 1, which for r = len - 1 is the next
-        // checkpoint (replayed only for the last segment).  So the replay
-        // stops at state len - 1 unless that last state is needed.
-        auto state = [&](int64_t r) -> const Snapshot& {
-            if (r == 0) return e.ckpt[j];
-            if (r == len && j + 1 < nseg) return e.ckpt[j + 1];
-            return e.pool[r];
-        };
-        const int64_t nrep = e.two_node && j + 1 == nseg ? len : len - 1;
-        for (int64_t r = 0; r < nrep; ++r) {
-            e.t = t_seg + r;   // forward_step reads e.t for the objective window and wall data
-            if ((rc = forward_step(h, state(r), e.pool[r + 1], false))) {
-                e.t = t_saved;
-                return rc;
-            }
-        }
-        for (int64_t r = len - 1; r >= 0; --r) {
-            const int64_t t = t_seg + r;
-            lbe::AdjointObjective ao;
-            ao.kind = e.obj_kind;
-            ao.tag = e.obj_tag;
-            const bool in_w = e.obj_kind != LBM_OBJ_NONE && t >= e.obj_t0 && t < e.obj_t1;
-            ao.weight = in_w ? 1.0 / (double)(e.obj_t1 - e.obj_t0) : 0.0;
-            ao.inv_nfluid = e.n_fluid ? 1.0 / (double)e.n_fluid : 0.0;
-            if (!in_w) ao.kind = LBM_OBJ_NONE;
-            hipError_t st = hipSuccess;
-            e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
-            if (e.two_node) st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
-            if (st == hipSuccess)
-                st = lbe::launch_adjoint_step(e, state(r), e.lam[lc], e.lam[lc ^ 1], ao);
-            if (st != hipSuccess) {
-                e.t = t_saved;
-                return fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));
-            }
-            lc ^= 1;
-        }
+int lbm_adjoint_step(lbm_t* h, int64_t n) {
+    if (!h) return LBM_EINVAL;
+    if (n < 0) return fail(h, LBM_EINVAL, "n must be >= 0");
+    if (!h->e.adj_started) {
+        const int rc = adjoint_begin(h);
+        if (rc) return rc;
     }
-    e.t = t_saved;
-    // lambda(run_t0) now in lam[lc]; keep it in lam[0]
-    if (lc != 0) std::swap(e.lam[0], e.lam[1]);
-    e.have_grad = true;
-    return LBM_OK;
+    return adjoint_steps(h, n);
+}
+
+int64_t lbm_adjoint_remaining(const lbm_t* h) {
+    if (!h || !h->e.adj_started) return -1;
+    return h->e.adj_next + 1;
 }
 
 int lbm_set_rate_gradient(lbm_t* h, int on) {

@@ -93,6 +93,12 @@ struct Engine {
     double* d_gglob = nullptr;          // per-block partials of dJ/dg (D) and dJ/ds (Q)
     int64_t gglob_len = 0;
     bool have_grad = false;
+    // reverse sweep in progress: next step to reverse (relative to the run's
+    // first step), segment held by the replay pool
+    bool adj_started = false;
+    int64_t adj_next = -1;
+    int64_t adj_seg = -1;
+    int64_t gq_len = 0;
     bool want_ds = true;                // accumulate dJ/ds in the adjoint
 
     // scratch for reductions and host transfers

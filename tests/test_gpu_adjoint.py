@@ -199,3 +199,38 @@ def test_autograd_function_matches_adjoint():
     assert np.isclose(float(tau.grad), dtau, rtol=1e-12)
     sv.close()
     sv2.close()
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[4]], ids=[CASES[0][0], CASES[4][0]])
+def test_reverse_sweep_in_pieces_is_bitwise_the_full_sweep(case):
+    """lbm_adjoint_step: the reverse sweep in uneven pieces (crossing segment
+    boundaries) gives the gradients and lambda(0) of lbm_adjoint, bit for
+    bit; the remaining-step count follows the sweep."""
+    name, mk_geom, mk_s, kw, obj, steps = case
+    geom, s = mk_geom(), mk_s()
+    Q = len(VELOCITIES[geom.lattice])
+    df0 = states.random_deviation(Q, geom.n_nodes, seed=8, amp=2e-3)
+    sv, J, full = _gpu_grad(geom, s, kw, obj, steps, 3, df0)
+    sv.close()
+    from paper_1712_08288_amd import binding
+    sv = binding.solver_for(geom, s, precision="fp64", g=kw.get("g"), dp=kw.get("dp", 0.0),
+                            l_rule=kw.get("l_rule", "min"), b=kw.get("b", 1.0),
+                            two_node=kw.get("two_node", False))
+    sv.init_deviation(df0)
+    sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1)
+    sv.run_checkpointed(steps, 3)
+    assert sv.adjoint_remaining() == -1
+    done = 0
+    for piece in (2, 0, 5, 1, steps):
+        sv.adjoint_step(piece)
+        done = min(steps, done + piece)
+        assert sv.adjoint_remaining() == steps - done
+    gr = sv.grad()
+    gr["lam0"] = sv.get_adjoint()
+    for key in ("q", "wall_u", "g", "s", "lam0"):
+        assert np.array_equal(gr[key], full[key]), key
+    # a new lbm_adjoint restarts the sweep
+    sv.adjoint()
+    assert sv.adjoint_remaining() == 0
+    assert np.array_equal(sv.grad()["q"], full["q"])
+    sv.close()
