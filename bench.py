@@ -94,27 +94,52 @@ def copy_ceiling(binding, torch, nbytes=1 << 31, reps=20, all_modes=False):
     return out
 
 
-def cpu_baseline(geom, w, slab=48, steps=20):
+def cpu_baseline(geom, w, slab=48, steps=20, threads=None):
     """Oracle on the z-slab 0 <= z < slab of the same workload (window mode:
-    reads across the slab faces see NaN and are not used)."""
+    reads across the slab faces see NaN and are not used; slab=None runs the
+    whole domain).  threads limits the BLAS threads (None: all)."""
     from oracle.lbm import Oracle
+    import contextlib
     try:
         import threadpoolctl
-        threads = max(i["num_threads"] for i in threadpoolctl.threadpool_info())
+        ctl = threadpoolctl.threadpool_limits(threads) if threads else contextlib.nullcontext()
     except Exception:
-        threads = 1
-    nx, ny, nz = geom.shape
-    nodes = np.arange(nx * ny * min(slab, nz), dtype=np.int64)
-    o = Oracle(geom, w.s, dp=w.dp, l_rule=w.l_rule, nodes=nodes)
-    f = o.init_equilibrium()
-    t0 = time.perf_counter()
-    o.run(f, steps)
-    dt = time.perf_counter() - t0
-    return {"value": round(len(nodes) * steps / dt / 1e6, 4), "unit": "MLUPS",
-            "cores": int(threads), "kind": "oracle",
-            "sample": "%d steps on the %dx%dx%d z-slab (%d nodes) of the same "
-                      "geometry, numpy float64 (BLAS threads %d), %.1f s"
-                      % (steps, nx, ny, min(slab, nz), len(nodes), threads, dt)}
+        threadpoolctl, ctl = None, contextlib.nullcontext()
+    with ctl:
+        used = (max(i["num_threads"] for i in threadpoolctl.threadpool_info())
+                if threadpoolctl else 1)
+        nx, ny, nz = geom.shape
+        plane = nx * ny if nz > 1 else nx          # slab: z-planes (3D) or rows (2D)
+        depth = nz if nz > 1 else ny
+        zs = depth if slab is None else min(slab, depth)
+        nodes = None if zs == depth else np.arange(plane * zs, dtype=np.int64)
+        n = plane * zs
+        o = Oracle(geom, w.s, g=w.g, dp=w.dp, l_rule=w.l_rule, nodes=nodes)
+        f = o.init_equilibrium()
+        t0 = time.perf_counter()
+        o.run(f, steps)
+        dt = time.perf_counter() - t0
+    fluid = int((geom.solid.reshape(-1)[:n] == 0).sum())
+    return {"value": round(n * steps / dt / 1e6, 4), "unit": "MLUPS",
+            "fluid_mlups": round(fluid * steps / dt / 1e6, 4),
+            "cores": int(used), "kind": "oracle",
+            "sample": "%d steps on %s (%d nodes) of the same geometry, numpy float64 "
+                      "(BLAS threads %d), %.1f s"
+                      % (steps, "the whole %dx%dx%d domain" % (nx, ny, nz) if nodes is None
+                         else ("the %dx%dx%d z-slab" % (nx, ny, zs) if nz > 1
+                               else "the %dx%d row slab" % (nx, zs)), n, used, dt)}
+
+
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "cores_available": len(os.sched_getaffinity(0))}
 
 
 def _timed_steps(sv, n):
@@ -172,8 +197,11 @@ def all_configs(binding, torch):
         e = analytic.relative_l2(u, analytic.couette_velocity(geom), geom.solid == 0)
         errs.append(e)
         if n == 64:
+            by = algorithmic_bytes(9, 8, geom.n_nodes, geom.n_fluid, geom.n_links)
             out["c1_couette_64"] = {"steps": w.steps, "ms_per_step": round(ms, 5),
                                     "mlups": round(geom.n_nodes / (ms * 1e-3) / 1e6, 1),
+                                    "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                    "note": "0.6 MB working set: launch-bound, not an HBM measurement",
                                     "u_rel_l2_vs_analytic": e}
     out["c1_refinement"] = {"sizes": sizes, "u_rel_l2": errs,
                             "fitted_order": float(-np.polyfit(np.log(sizes), np.log(errs), 1)[0])}
@@ -217,6 +245,10 @@ def all_configs(binding, torch):
     t0, t1 = w.extra["obj_window"]
     every = int(round(np.sqrt(w.steps)))
     res = {"n_links": geom.n_links, "checkpoint_every": every}
+    for prec in ("fp64", "fp32"):
+        sv, r = fwd(w, geom, prec, 500)
+        sv.close()
+        res["forward_" + prec] = r
     for prec in ("fp64", "fp32"):
         sv = binding.solver_for(geom, w.s, precision=prec, l_rule=w.l_rule)
         sv.init()
@@ -282,6 +314,8 @@ def all_configs(binding, torch):
     # C5: 384x256x256 porous medium, FP32, 2000 steps + adjoint, every 64
     w = configs.c5_porous()
     geom = w.geometry()
+    sv, c5_fwd = fwd(w, geom, "fp32", 200)
+    sv.close()
     sv = binding.solver_for(geom, w.s, g=w.g, precision="fp32", l_rule=w.l_rule)
     sv.set_rate_gradient(False)
     sv.init()
@@ -300,6 +334,7 @@ def all_configs(binding, torch):
     out["c5_porous_384x256x256"] = {
         "n_fluid": geom.n_fluid, "n_links": geom.n_links, "J_mean_ux": J,
         "dJ_dgx": float(gr["g"][0]), "J_over_gx": J / w.g[0],
+        "forward": c5_fwd,
         "forward_ms_per_step": round((b - a) * 1e3 / w.steps, 4),
         "reverse_ms_per_step": round((c - b) * 1e3 / w.steps, 4)}
     del geom
@@ -320,6 +355,24 @@ def all_configs(binding, torch):
         "J_rel_err_fp32": abs(gsets["fp32"][0] - gsets["fp64"][0]) / abs(gsets["fp64"][0]),
         "dJ_dg_rel_err_fp32": _rel(gsets["fp32"][1]["g"], gsets["fp64"][1]["g"]),
         "dJ_dq_rel_l2_fp32": _rel(gsets["fp32"][1]["q"], gsets["fp64"][1]["q"])}
+
+    # the FP64 oracle on the host's cores at every workload (bounded samples;
+    # a baseline, not the target): all available cores and one core
+    _progress("CPU oracle per workload")
+    cpu = {"host": host_info()}
+    samples = [("c1_couette_64", configs.c1_couette(64), None, 500),
+               ("c2_cylinders_2048", configs.c2_cylinders(), 256, 10),
+               ("c3_spheres_256", configs.c3_spheres(), 48, 10),
+               ("c4_cylinder_1024x512", configs.c4_cylinder(), None, 10),
+               ("c5_porous_384x256x256", configs.c5_porous(), 24, 5),
+               ("c5_crop_96x64x64", configs.c5_crop(), None, 20)]
+    for name, w, slab, steps in samples:
+        geom = w.geometry()
+        cpu[name] = {"all_cores": cpu_baseline(geom, w, slab=slab, steps=steps),
+                     "one_core": cpu_baseline(geom, w, slab=slab, steps=max(2, steps // 2),
+                                              threads=1)}
+        del geom
+    out["cpu_oracle"] = cpu
     return out
 
 
