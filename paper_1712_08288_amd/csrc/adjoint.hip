@@ -142,7 +142,7 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
 // term) with coalesced loads and hand c2 a_k, c3 a_k (+ drag), c0 a_k and
 // c1 a_k to the node's lane through LDS; the node's lane hands back
 // f_ibar(y,t), f'_i(y,t) and f'_ibar(y,t) for the link lanes' gradients.
-template <class L, class T, int XB, bool WANT_DS>
+template <class L, class T, int XB, bool WANT_DS, bool ROWS>
 __global__ void __launch_bounds__(BX)
 k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
@@ -156,7 +156,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
     constexpr int NC = D + Q;                 // layout of the per-block sums
     constexpr int NR = WANT_DS ? NC : D;      // columns reduced here
     __shared__ LinkStage<T> stage[BX / 64];
-    const NodePos pos = node_of_thread(g);
+    const NodePos pos = node_of_thread<ROWS>(g);
     uint32_t lb = blockIdx.x;
     if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -473,8 +473,8 @@ static Grid adj_grid(const Engine& e) {
     g.nz = (uint32_t)e.nz;
     g.N = (uint32_t)e.N;
     g.S = (uint32_t)e.S;
-    g.bpr = (uint32_t)((e.nx + BX - 1) / BX);
-    g.nblocks = g.bpr * g.ny * g.nz;
+    g.nblocks = (uint32_t)((e.N + BX - 1) / BX);
+    g.bpr = e.nx % BX == 0 ? (uint32_t)(e.nx / BX) : 0u;
     g.chunk = e.xcd_remap ? (g.nblocks + NXCD - 1) / NXCD : 0;
     return g;
 }
@@ -510,7 +510,8 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const void* lam_i
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        auto kern = a.want_ds ? k_adjoint<L, T, XB, true> : k_adjoint<L, T, XB, false>;
+        auto kern = a.want_ds ? (g.bpr ? k_adjoint<L, T, XB, true, true> : k_adjoint<L, T, XB, true, false>)
+                              : (g.bpr ? k_adjoint<L, T, XB, false, true> : k_adjoint<L, T, XB, false, false>);
         hipLaunchKernelGGL(kern, dim3(g.chunk ? g.chunk * NXCD : g.nblocks), dim3(BX), 0,
                            e.stream, (const T*)fwd.f, (const T*)fwd.wa,
                            (const T*)lam_in, (T*)lam_out,

@@ -641,39 +641,33 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     }
     // per node: bit 31 solid, else the link-direction mask and, in bits
     // 19..30, the number of links at earlier nodes of its wave; per 64-node
-    // wave of a node launch (rows in chunks of kBlock threads): its kind --
-    // idle (no fluid), plain (64 fluid nodes without links) or mixed -- and
-    // the index of its first link (links are sorted by node)
+    // wave of a node launch (64 consecutive node indices): its kind -- idle
+    // (no fluid), plain (64 fluid nodes without links) or mixed -- with its
+    // link count, and the index of its first link (links are sorted by node)
     std::vector<uint32_t> info(N);
     std::vector<uint2> wave;
     {
-        const int64_t bpr = (e.nx + lbe::kBlock - 1) / lbe::kBlock;
-        const int64_t nb = bpr * e.ny * e.nz;
-        const int wpb = lbe::kBlock / lbe::kWave;
-        wave.assign(nb * wpb, make_uint2(2u, 0u));
+        const int64_t nwave = (N + lbe::kBlock - 1) / lbe::kBlock * (lbe::kBlock / lbe::kWave);
+        wave.assign(nwave, make_uint2(2u, 0u));
         int64_t k = 0;
-        for (int64_t lb = 0; lb < nb; ++lb) {
-            const int64_t row = lb / bpr, xb = lb % bpr;
-            for (int w = 0; w < wpb; ++w) {
-                const int64_t x0 = xb * lbe::kBlock + w * lbe::kWave;
-                const int64_t nin = std::max<int64_t>(0, std::min<int64_t>(lbe::kWave, e.nx - x0));
-                bool any_fluid = false, all_plain = nin == lbe::kWave;
-                const int64_t k0 = k;
-                for (int64_t l = 0; l < nin; ++l) {
-                    const int64_t n = row * e.nx + x0 + l;
-                    if (solid[n]) {
-                        info[n] = 0x80000000u;
-                        all_plain = false;
-                        continue;
-                    }
-                    any_fluid = true;
-                    all_plain = all_plain && mask[n] == 0u;
-                    info[n] = mask[n] | ((uint32_t)(k - k0) << 19);
-                    k += __builtin_popcount(mask[n]);
+        for (int64_t w = 0; w < nwave; ++w) {
+            const int64_t n0 = w * lbe::kWave;
+            const int64_t nin = std::max<int64_t>(0, std::min<int64_t>(lbe::kWave, N - n0));
+            bool any_fluid = false, all_plain = nin == lbe::kWave;
+            const int64_t k0 = k;
+            for (int64_t n = n0; n < n0 + nin; ++n) {
+                if (solid[n]) {
+                    info[n] = 0x80000000u;
+                    all_plain = false;
+                    continue;
                 }
-                const uint32_t kind = !any_fluid ? 2u : (all_plain ? 1u : 0u);
-                wave[lb * wpb + w] = make_uint2(kind | ((uint32_t)(k - k0) << 2), (uint32_t)k0);
+                any_fluid = true;
+                all_plain = all_plain && mask[n] == 0u;
+                info[n] = mask[n] | ((uint32_t)(k - k0) << 19);
+                k += __builtin_popcount(mask[n]);
             }
+            const uint32_t kind = !any_fluid ? 2u : (all_plain ? 1u : 0u);
+            wave[w] = make_uint2(kind | ((uint32_t)(k - k0) << 2), (uint32_t)k0);
         }
         if (k != n_links) return fail(h, LBM_EGEOM, "link count mismatch");
     }

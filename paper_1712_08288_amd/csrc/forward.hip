@@ -76,13 +76,13 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
 // the cut-link directions from their slots.  Its solid lanes store NaN into
 // their own slots, which nothing reads: a full store keeps every written
 // cache line whole (partial lines cost HBM read-modify-write cycles).
-template <class L, class T, int XB>
+template <class L, class T, int XB, bool ROWS>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
        T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
        Grid g, Params<L, T> p, double* __restrict__ acc_ux, double w_ux) {
     __shared__ LinkStage<T> stage[BX / 64];
-    const NodePos pos = node_of_thread(g);
+    const NodePos pos = node_of_thread<ROWS>(g);
     uint32_t lb = blockIdx.x;
     if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -381,8 +381,8 @@ static Grid make_grid(const Engine& e) {
     g.nz = (uint32_t)e.nz;
     g.N = (uint32_t)e.N;
     g.S = (uint32_t)e.S;
-    g.bpr = (uint32_t)((e.nx + BX - 1) / BX);
-    g.nblocks = g.bpr * g.ny * g.nz;
+    g.nblocks = (uint32_t)((e.N + BX - 1) / BX);
+    g.bpr = e.nx % BX == 0 ? (uint32_t)(e.nx / BX) : 0u;
     g.chunk = e.xcd_remap ? (g.nblocks + NXCD - 1) / NXCD : 0;
     return g;
 }
@@ -448,7 +448,8 @@ hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        hipLaunchKernelGGL((k_step<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
+        auto kern = g.bpr ? k_step<L, T, XB, true> : k_step<L, T, XB, false>;
+        hipLaunchKernelGGL(kern, dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
                            (T*)out.wa, meta(e), e.d_lkcoef, g,
                            make_params<L, T>(e), obj.acc_ux, obj.w_ux);

@@ -16,17 +16,18 @@ constexpr int NXCD = 8;            // compute dies on MI355X (blocks go round-ro
 
 enum XBC : int { XBC_PERIODIC = 0, XBC_PRESSURE = 1, XBC_OUTFLOW = 2 };
 
-// A launch covers rows of nx nodes in chunks of BX threads.  Blocks are
-// dealt to the eight XCDs round-robin by hardware; `remap` turns the block
-// id into a logical id so that each XCD sweeps one contiguous slab of rows
-// and the y/z-neighbour rows a pull touches stay in that XCD's L2.
+// A node launch covers the node indices n = x + nx (y + ny z) in order, BX
+// per block (64 per wave), whatever the row length: no lane idles except at
+// the very end.  Blocks are dealt to the eight XCDs round-robin by hardware;
+// `chunk` (when set) turns the block id into a logical id so that each XCD
+// sweeps one contiguous slab.
 struct Grid {
     uint32_t nx, ny, nz;
     uint32_t N;          // nx*ny*nz
     uint32_t S;          // stride between direction planes of device arrays (>= N)
-    uint32_t bpr;        // blocks per row
-    uint32_t nblocks;    // logical blocks = bpr*ny*nz
+    uint32_t nblocks;    // logical blocks = ceil(N / BX)
     uint32_t chunk;      // ceil(nblocks / NXCD) when remapping, else 0
+    uint32_t bpr;        // nx / BX when BX divides nx (blocks per row), else 0
 };
 
 struct NodePos {
@@ -34,17 +35,26 @@ struct NodePos {
     bool in;
 };
 
+// ROWS (only when BX divides nx): every block lies in one row, so the row,
+// y and z are block-uniform and stay in scalar registers.
+template <bool ROWS = false>
 __device__ __forceinline__ NodePos node_of_thread(const Grid& g) {
     uint32_t b = blockIdx.x;
     if (g.chunk) b = (b % NXCD) * g.chunk + b / NXCD;
     NodePos p;
-    const uint32_t row = b / g.bpr;
-    const uint32_t xb = b - row * g.bpr;
-    p.ix = xb * BX + threadIdx.x;
-    p.iy = row % g.ny;
-    p.iz = row / g.ny;
-    p.in = (b < g.nblocks) && (p.ix < g.nx);
-    p.n = p.ix + g.nx * (p.iy + g.ny * p.iz);
+    p.n = b * BX + threadIdx.x;
+    p.in = (b < g.nblocks) && (p.n < g.N);
+    if constexpr (ROWS) {
+        const uint32_t row = b / g.bpr;
+        p.ix = (b - row * g.bpr) * BX + threadIdx.x;
+        p.iz = row / g.ny;
+        p.iy = row - p.iz * g.ny;
+    } else {
+        const uint32_t row = p.n / g.nx;
+        p.ix = p.n - row * g.nx;
+        p.iz = row / g.ny;
+        p.iy = row - p.iz * g.ny;
+    }
     return p;
 }
 
@@ -361,11 +371,8 @@ __device__ __forceinline__ bool is_solid(uint32_t info) { return (info >> 31) !=
 __device__ __forceinline__ uint32_t wave_kind(uint2 w) { return w.x & 3u; }
 __device__ __forceinline__ uint32_t wave_links(uint2 w) { return w.x >> 2; }
 
-// the wave of a node launch that holds node n (kBlock-thread blocks, bpr per row)
-__device__ __forceinline__ uint32_t wave_of_node(const Grid& g, uint32_t n) {
-    const uint32_t row = n / g.nx, x = n - row * g.nx;
-    return row * g.bpr * (BX / 64) + x / 64;
-}
+// the wave of a node launch that holds node n
+__device__ __forceinline__ uint32_t wave_of_node(const Grid&, uint32_t n) { return n / 64; }
 
 // links of a node whose wave's first link index is known
 __device__ __forceinline__ NodeLinks node_links(uint32_t info, uint32_t wave_base) {
