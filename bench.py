@@ -482,6 +482,13 @@ def main():
     fl = geom.solid == 0
     du = float(np.sqrt(((u32 - u64)[fl] ** 2).sum() / (u64[fl] ** 2).sum()))
     sv64.close()
+    # spread of the FP32 step time: five more timed runs of 100 steps
+    reps = []
+    for _ in range(5):
+        sv32.set_timing(True)
+        sv32.step(100)
+        reps.append(round(sv32.last_step_ms(), 4))
+        sv32.set_timing(False)
 
     # FP32 forward + adjoint (checkpointed run, then the reverse sweep)
     A = args.adjoint_steps
@@ -552,6 +559,7 @@ def main():
             "copy_ceiling_GBps": ceiling["best_GBps"],
             "frac_of_copy_ceiling": round(achieved / ceiling["best_GBps"], 4),
             "kernel_ms": round(kms32, 4),
+            "repeats_kernel_ms": reps, "repeats_median_ms": float(np.median(reps)),
             "algorithmic_bytes": int(bytes32),
         },
         "fp64": {

@@ -86,3 +86,16 @@ def test_c5_porous_384x256x256_fp32():
     err, finite = _run(configs.c5_porous(), "fp32")
     assert finite
     assert err < TOL["fp32"], err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_crop_96x64x64_parity(precision):
+    """The C5 crop-sized medium (96x64x64, 5 spheres, seed 55) against the
+    oracle over the whole domain."""
+    from gpu_util import pair, rel_l2
+    w = configs.c5_crop(steps=15)
+    geom = w.geometry()
+    got, want, fl, sv, o, f = pair(geom, w.s, w.steps, precision=precision, g=w.g,
+                                   l_rule=w.l_rule)
+    assert rel_l2(got, want, fl) < (1e-12 if precision == "fp64" else 3e-6)
+    sv.close()
