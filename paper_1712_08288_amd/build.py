@@ -1,7 +1,7 @@
 """Compile the HIP engine into paper_1712_08288_amd/_lib/liblbm.so for gfx950.
 
 Run as `python -m paper_1712_08288_amd.build` or through
-`__graft_entry__.build()`.  Always recompiles (sources in parallel).
+the repository's build entry point.  Always recompiles (sources in parallel).
 """
 
 import os

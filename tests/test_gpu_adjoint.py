@@ -2,10 +2,10 @@
 differences of the HIP forward run (GPU).
 
 Tolerances.  FP64 adjoint vs the oracle reverse sweep: both in double with
-different summation orders; 1e-10 relative (north-star figure).  Central
+different summation orders; 1e-10 relative (the required figure).  Central
 differences with step 1e-6 in FP64: truncation O(h^2 J''') ~ 1e-12 and
 cancellation eps |J| / h ~ 1e-10 |J|, compared on links whose |dJ/dq| is
-not tiny against |J|; bound 1e-6 relative (north-star figure).
+not tiny against |J|; bound 1e-6 relative (the required figure).
 FP32: the forward is FP32, so its gradient differs from the FP64 one by the
 FP32 forward error; reported against a 1e-3 relative bound (parity unpinned).
 """

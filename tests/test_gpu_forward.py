@@ -2,7 +2,7 @@
 
 Tolerances.  FP64: the two sides differ only in summation order and FMA
 contraction, about 1e-16 relative per operation; the dissipative step does
-not amplify it, so the benchmark spec's bound 1e-12 (relative L2) is used for the
+not amplify it, so the required bound 1e-12 (relative L2) is used for the
 distributions and the velocity.  FP32 (deviation storage): float has unit
 round-off 6e-8; one step rounds each stored deviation once and the
 collision's ~2 Q operations add a few ulps, so after n steps the relative

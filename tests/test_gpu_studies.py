@@ -1,6 +1,6 @@
 """Section 3's convergence claims on the GPU, on small subsets of the sweeps
 (the full sweeps run with `python bench.py --study ...`).  The paper reports
-orders "around 2" for every rule, gamma and s_nu; bounds here are wide
+orders close to 2 for every rule, gamma and s_nu; bounds here are wide
 enough for three-point fits on coarse meshes."""
 
 import pytest

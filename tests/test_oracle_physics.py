@@ -58,7 +58,7 @@ def order(sizes, errs):
                                   "gamma2+gamma", "min"])
 @pytest.mark.parametrize("gamma", [0.25, 0.75, 1.0])
 def test_poiseuille_second_order(rule, gamma):
-    """Section 3.1 reports orders around 2 for every rule, gamma and s_nu."""
+    """Section 3.1 reports orders close to 2 for every rule, gamma and s_nu."""
     sizes = [11, 21, 41]
     errs = [poiseuille_error(n, gamma, 1.0, rule) for n in sizes]
     p = order([n - 2 + 2 * gamma for n in sizes], errs)
@@ -83,7 +83,7 @@ def test_poiseuille_second_order_other_rates(s_nu):
     assert 1.8 < order([n - 0.5 for n in sizes], errs) < 2.2, errs
 
 
-def test_poiseuille_half_way_bounce_back_matches_survey_scale():
+def test_poiseuille_half_way_bounce_back_is_small_and_second_order():
     """At gamma = 1/2 with l(1/2) = 0 the walls are half-way bounce-back,
     which is exact for plane Poiseuille flow with this forcing up to the
     rate-dependent slip; the error must be small and still second order."""

@@ -1,4 +1,4 @@
-"""Closed-form steady flows used to judge accuracy (not the method itself)."""
+"""Closed-form steady flows used to measure accuracy (not the method itself)."""
 
 import numpy as np
 
