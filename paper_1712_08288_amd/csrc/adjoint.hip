@@ -67,6 +67,17 @@ struct AdjArgs {
     int want_ds;
 };
 
+// Per-link values one adjoint step hands to the link-gradient kernel: the
+// link adjoint a_k (with the drag term), f_ibar(y, t), and f'_i(y, t),
+// f'_ibar(y, t) as the forward step stored them at y.
+template <class T>
+struct LinkStaging {
+    double* ak;
+    T* fib;
+    T* fpi;
+    T* fpib;
+};
+
 template <int NC>
 __device__ __forceinline__ void block_accumulate(const double (&v)[NC], double* __restrict__ dst) {
     __shared__ double part[BX / 64][NC];
@@ -86,9 +97,10 @@ __device__ __forceinline__ void block_accumulate(const double (&v)[NC], double* 
     }
 }
 
-// Lattice data of a direction known only at run time (link lanes).
+// Lattice data of a direction known only at run time (link lanes): e_d, w_d
+// and the opposite direction.
 template <class L>
-__device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w) {
+__device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w, int& opp) {
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         if (i == d) {
@@ -96,25 +108,24 @@ __device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w) {
             e[1] = L::E[i][1];
             e[2] = L::E[i][2];
             w = L::W[i];
+            opp = TAB<L>.opp[i];
         }
     });
 }
 
 // Link k = (y, i) of a mixed wave, handled by the lane of its node y: the
-// contribution of its adjoint a_k to mu and to lambda(y, t), and its
-// gradients.  Used for links past the 64th of a wave (the first 64 go
-// through the wave's LDS slab).
+// contribution of its adjoint a_k to mu and to lambda(y, t), and f_ibar(y, t)
+// staged for the link-gradient kernel.  Used for links past the 64th of a
+// wave (the first 64 go through the wave's LDS slab).
 template <class L, class T, int i>
 __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict__ lam_in,
+                                                const T* __restrict__ nxt,
                                                 uint32_t n, uint32_t S,
                                                 const LinkCoef* __restrict__ lkcoef,
-                                                const LinkDeriv* __restrict__ lkderiv,
-                                                const double* __restrict__ lkc4,
                                                 const int32_t* __restrict__ lktag,
-                                                double* __restrict__ gq, double* __restrict__ gphi,
+                                                const LinkStaging<T>& sg,
                                                 const Params<L, T>& p, const AdjArgs& a,
-                                                const T (&f)[L::Q], const T (&fp)[L::Q],
-                                                T (&mu)[L::Q], T (&dir)[L::Q]) {
+                                                const T (&f)[L::Q], T (&mu)[L::Q]) {
     constexpr int ib = TAB<L>.opp[i];
     double ak = (double)ld(lam_in + (size_t)i * S, n);
     if (a.obj_kind == 1 && L::E[i][0] != 0 && lktag[k] == a.obj_tag) {
@@ -124,279 +135,390 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
         mu[ib] += (T)dfx;
     }
     const LinkCoef c = lkcoef[k];
-    const LinkDeriv dc = lkderiv[k];
     mu[i] += (T)(c.c2 * ak);
     mu[ib] += (T)(c.c3 * ak);
-    dir[i] += (T)(p.c0 * ak);
-    dir[ib] += (T)(c.c1 * ak);
-    gq[k] += ak * (dc.d1 * (double)f[ib] + dc.d2 * (double)fp[i] + dc.d3 * (double)fp[ib] +
-                   p.wall_scale * dc.dwall);
-    const double c4w = lkc4[k] * 3.0 * L::W[i] * p.rho0_d * p.wall_scale * ak;
-#pragma unroll
-    for (int al = 0; al < L::D; ++al)
-        if (L::E[i][al] != 0) gphi[(size_t)k * L::D + al] += c4w * L::E[i][al];
+    sg.ak[k] = ak;
+    sg.fib[k] = f[ib];
+    sg.fpi[k] = ld(nxt + (size_t)i * S, n);
+    sg.fpib[k] = ld(nxt + (size_t)ib * S, n);
 }
 
-// Mixed waves handle their cut links cooperatively (see LinkStage): the
+// The terms of such a link that bypass the collision: c0 a_k onto
+// lambda_i(y, t) and c1 a_k onto lambda_ibar(y, t), added to mu after its
+// moments are taken (a_k read again: these links are rare).
+template <class L, class T, int i>
+__device__ __forceinline__ void own_link_bypass(uint32_t k, const T* __restrict__ lam_in,
+                                                uint32_t n, uint32_t S,
+                                                const LinkCoef* __restrict__ lkcoef,
+                                                const int32_t* __restrict__ lktag,
+                                                const Params<L, T>& p, const AdjArgs& a,
+                                                T (&mu)[L::Q]) {
+    constexpr int ib = TAB<L>.opp[i];
+    double ak = (double)ld(lam_in + (size_t)i * S, n);
+    if (a.obj_kind == 1 && L::E[i][0] != 0 && lktag[k] == a.obj_tag)
+        ak += -(double)L::E[i][0] * a.w_force;
+    mu[i] += (T)(p.c0 * ak);
+    mu[ib] += (T)(lkcoef[k].c1 * ak);
+}
+
+// Per-link gradients of one adjoint step, link k = (y, i) with adjoint a_k
+// of f_i(y, t+1) (plus the drag term):
+//   dJ/dgamma_k += a_k (dc1 f_ibar(y,t) + dc2 f'_i(y,t) + dc3 f'_ibar(y,t) + dwall),
+//   dJ/dphi_k   += a_k c4 3 w_i rho0 e_i,
+// from the values the adjoint kernel staged (coalesced, one thread per link).
+template <class L, class T>
+__global__ void __launch_bounds__(BX)
+k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
+            const LinkDeriv* __restrict__ lkderiv, const double* __restrict__ lkc4,
+            double* __restrict__ gq, double* __restrict__ gphi, uint32_t n_links,
+            Params<L, T> p) {
+    const uint32_t k = blockIdx.x * BX + threadIdx.x;
+    if (k >= n_links) return;
+    int e[3] = {0, 0, 0}, ib = 0;
+    double w = 0.0;
+    dir_data<L>(lkdir[k], e, w, ib);
+    const double ak = sg.ak[k];
+    const LinkDeriv dc = lkderiv[k];
+    gq[k] += ak * (dc.d1 * (double)sg.fib[k] + dc.d2 * (double)sg.fpi[k] +
+                   dc.d3 * (double)sg.fpib[k] + p.wall_scale * dc.dwall);
+    const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * p.wall_scale * ak;
+#pragma unroll
+    for (int al = 0; al < L::D; ++al)
+        if (e[al] != 0) gphi[(size_t)k * L::D + al] += c4w * e[al];
+}
+
+// The waves of the adjoint launch, slot s < count (s = 4 blockIdx.x + wave in
+// the block), each as {id, kind | links << 2, first link, 0} (node
+// n = 64 id + lane) so that one scalar load brings all of it.  wpr = nx / 64
+// when 64 divides nx (each wave lies in one row), else 0.
+struct WaveList {
+    const uint4* ent;
+    uint32_t count;
+    uint32_t wpr;
+};
+
+template <bool ROWS>
+__device__ __forceinline__ NodePos node_of_wave(const Grid& g, const WaveList& wl, uint32_t w,
+                                                uint32_t lane, bool active) {
+    NodePos p;
+    p.n = w * 64u + lane;
+    p.in = active && p.n < g.N;
+    if constexpr (ROWS) {
+        const uint32_t row = w / wl.wpr;
+        p.ix = (w - row * wl.wpr) * 64u + lane;
+        p.iz = row / g.ny;
+        p.iy = row - p.iz * g.ny;
+    } else {
+        const uint32_t row = p.n / g.nx;
+        p.ix = p.n - row * g.nx;
+        p.iz = row / g.ny;
+        p.iy = row - p.iz * g.ny;
+    }
+    return p;
+}
+
+// One launch covers the non-idle waves in memory order.  Plain and mixed
+// waves take separate paths from the start.  Mixed waves handle their cut links cooperatively (see LinkStage): the
 // link lanes read the link data and a_k = lambda_i(y, t+1) (plus the drag
 // term) with coalesced loads and hand c2 a_k, c3 a_k (+ drag), c0 a_k and
 // c1 a_k to the node's lane through LDS; the node's lane hands back
-// f_ibar(y,t), f'_i(y,t) and f'_ibar(y,t) for the link lanes' gradients.
+// f_ibar(y, t), which the link lanes stage for the link-gradient kernel
+// together with a_k and the forward step's stored f'_i(y, t), f'_ibar(y, t).
 template <class L, class T, int XB, bool WANT_DS, bool ROWS>
 __global__ void __launch_bounds__(BX)
-k_adjoint(const T* __restrict__ A, const T* __restrict__ wa,
+k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict__ nxt,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
-          NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
-          const LinkDeriv* __restrict__ lkderiv,
-          const double* __restrict__ lkc4, const int32_t* __restrict__ lktag,
+          NodeMeta nm, WaveList wl, const LinkCoef* __restrict__ lkcoef,
+          const int32_t* __restrict__ lktag,
           const uint8_t* __restrict__ lkdir, const int32_t* __restrict__ lknode,
-          double* __restrict__ gq, double* __restrict__ gphi,
-          double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
+          LinkStaging<T> sg, double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
     constexpr int Q = L::Q, D = L::D, NP = NPAIR<L>;
     constexpr int NC = D + Q;                 // layout of the per-block sums
     constexpr int NR = WANT_DS ? NC : D;      // columns reduced here
     __shared__ LinkStage<T> stage[BX / 64];
-    const NodePos pos = node_of_thread<ROWS>(g);
-    uint32_t lb = blockIdx.x;
-    if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
-    const uint32_t kind = wave_kind(wv);
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t nlw = wave_links(wv), wbase = wv.y;
+    const uint32_t slot = blockIdx.x * (BX / 64) + wid;
+    const bool active = slot < wl.count;
+    const uint4 wm = active ? wl.ent[slot] : uint4{0u, 0u, 0u, 0u};
+    const uint32_t w = __builtin_amdgcn_readfirstlane(wm.x);
+    const uint32_t nlw = __builtin_amdgcn_readfirstlane(wm.y) >> 2;
+    const uint32_t wbase = __builtin_amdgcn_readfirstlane(wm.z);
+    const NodePos pos = node_of_wave<ROWS>(g, wl, w, lane, active);
     LinkStage<T>& st = stage[wid];
     double acc[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) acc[c] = 0.0;
 
-    // loads that do not depend on the node's metadata are issued first:
-    // the planes of the forward pull and the adjoint gathers
-    // lambda_i(y + e_i, t+1) (entries of solid or absent neighbours are
-    // read and then discarded)
-    T f[Q], lg[Q];
-    const Push<XB> ps(g, pos);
-    if (kind != WAVE_IDLE && pos.in) {
-        pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            lg[i] = ld(lam_in + (size_t)i * g.S, i == 0 ? pos.n : ps.template dst<L, i>());
-        });
-    } else {
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            f[i] = T(0);
-            lg[i] = T(0);
-        });
-    }
+    // One wave's work.  Plain and mixed waves take separate paths from the
+    // start (their own loads included), so that each path's registers are
+    // allocated as in a kernel of its own.  Plain waves are 64 fluid nodes
+    // inside the grid.
+    auto run = [&](auto mixed_c) {
+        constexpr bool MX = decltype(mixed_c)::value;
+        // mixed waves: the link lanes' indices come first (small coalesced
+        // loads), so that the gathers that depend on them can be issued before
+        // the node loads below return
+        const bool link_lane = MX && lane < nlw && lane < 64u;
+        const uint32_t kl = wbase + lane;
+        int ld_dir = 0;
+        uint32_t ld_node = 0;
+        if (link_lane) {
+            ld_dir = lkdir[kl];
+            ld_node = (uint32_t)lknode[kl];
+        }
 
-    // one fluid node; PLAIN: the whole wave is fluid without cut links.  In
-    // a mixed wave nl.base is relative to the wave's first link and f already
-    // holds the link slots.
-    auto node = [&](auto plain_c, const NodeLinks& nl) {
-        constexpr bool PLAIN = decltype(plain_c)::value;
-        // forward state f(y, t) and its velocity
-        T sp[NP], dp[NP];
-        pair_split<L, T>(f, sp, dp);
-        T rho, j[3];
-        conserved_of<L, T>(f[0], sp, dp, rho, j);
-        const T u[3] = {j[0] * p.inv_rho0, j[1] * p.inv_rho0, j[2] * p.inv_rho0};
-
-        // mu_i(y) = dJ/df'_i(y): lambda_i(y + e_i, t+1) where that node pulls
-        T mu[Q], dir[Q];
-        unroll<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int ib = TAB<L>.opp[i];
-            dir[i] = 0;
-            if constexpr (i == 0) {
-                mu[i] = lg[0];
-            } else {
-                bool lost = (nl.mask >> ib) & 1u;     // y + e_i is solid
-                if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == 1) lost = lost || ps.x_out;
-                mu[i] = lost ? T(0) : lg[i];
-                if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1) {
-                    if (ps.x_out) {
-                        const uint32_t n2 = ps.template dst_clamped<L, i>(pos.ix);
-                        if (!is_solid(nm.info[n2])) mu[i] += ld(lam_in + (size_t)i * g.S, n2);
-                    }
-                }
-            }
-        });
-
-        // own cut links: Eq. (213) reversed, drag terms, per-link gradients
-        if (!PLAIN && nl.mask) {
-            T fp[Q];
+        // loads that do not depend on the node's metadata: the planes of the
+        // forward pull and the adjoint gathers lambda_i(y + e_i, t+1) (entries
+        // of solid or absent neighbours are read and then discarded)
+        T f[Q], lg[Q];
+        const Push<XB> ps(g, pos);
+        if (!MX || pos.in) {
+            pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
             unroll<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                fp[i] = f[i];
+                lg[i] = ld(lam_in + (size_t)i * g.S, i == 0 ? pos.n : ps.template dst<L, i>());
             });
-            Macro<L, T> mac;
-            collide<L, T>(fp, p, mac);
-            uint32_t k = nl.base;
+        } else {
+            unroll<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                f[i] = T(0);
+                lg[i] = T(0);
+            });
+        }
+
+        // one fluid node; PLAIN: the whole wave is fluid without cut links.  In
+        // a mixed wave nl.base is relative to the wave's first link and f already
+        // holds the link slots.
+        auto node = [&](auto plain_c, const NodeLinks& nl) {
+            constexpr bool PLAIN = decltype(plain_c)::value;
+            // forward state f(y, t) and its velocity
+            T sp[NP], dp[NP];
+            pair_split<L, T>(f, sp, dp);
+            T rho, j[3];
+            conserved_of<L, T>(f[0], sp, dp, rho, j);
+            const T u[3] = {j[0] * p.inv_rho0, j[1] * p.inv_rho0, j[2] * p.inv_rho0};
+
+            // mu_i(y) = dJ/df'_i(y): lambda_i(y + e_i, t+1) where that node pulls
+            T mu[Q];
             unroll<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 constexpr int ib = TAB<L>.opp[i];
-                if constexpr (i > 0) {
-                    const uint32_t bit = (nl.mask >> i) & 1u;
-                    if (bit) {
-                        if (k < 64u) {
-                            mu[i] += st.v[0][k];
-                            mu[ib] += st.v[1][k];
-                            dir[i] += st.v[2][k];
-                            dir[ib] += st.v[3][k];
-                            st.v[0][k] = f[ib];
-                            st.v[1][k] = fp[i];
-                            st.v[2][k] = fp[ib];
-                        } else {
-                            own_link_direct<L, T, i>(wbase + k, lam_in, pos.n, g.S, lkcoef,
-                                                     lkderiv, lkc4, lktag, gq, gphi, p, a, f,
-                                                     fp, mu, dir);
+                if constexpr (i == 0) {
+                    mu[i] = lg[0];
+                } else {
+                    bool lost = (nl.mask >> ib) & 1u;     // y + e_i is solid
+                    if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == 1) lost = lost || ps.x_out;
+                    mu[i] = lost ? T(0) : lg[i];
+                    if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1) {
+                        if (ps.x_out) {
+                            const uint32_t n2 = ps.template dst_clamped<L, i>(pos.ix);
+                            if (!is_solid(nm.info[n2])) mu[i] += ld(lam_in + (size_t)i * g.S, n2);
                         }
                     }
-                    k += bit;
                 }
             });
-        }
 
-        // collision adjoint: lambda = mu - v + J^T v, v = M^T R M mu
-        T smu[NP], dmu[NP];
-        pair_split<L, T>(mu, smu, dmu);
-        T qm[Q];
-        moments_of<L, T>(mu[0], smu, dmu, qm);
-        T r[Q];
-        unroll<Q>([&](auto K) {
-            constexpr int kk = decltype(K)::value;
-            r[kk] = L::conserved(kk) ? T(0) : qm[kk] * p.rate[kk];
-        });
-        T e0, ev[NP], od[NP];
-        back_transform<L, T>(r, e0, ev, od);
-        // J^T v = as + b.e_j with as = sum w_i v_i and
-        // b = sum_i w_i v_i (3 e_i + 9 (e_i.u) e_i) - 3 u as
-        T as = T(L::W[0]) * e0;
-        T b[3] = {0, 0, 0};
-        unroll<NP>([&](auto P) {
-            constexpr int pp = decltype(P)::value;
-            constexpr int i = DER<L>.pi[pp];
-            const T w2 = T(2.0 * L::W[i]);
-            as += w2 * ev[pp];
-            T eu = 0;
-            macc<L::E[i][0]>(eu, u[0]);
-            macc<L::E[i][1]>(eu, u[1]);
-            macc<L::E[i][2]>(eu, u[2]);
-            const T t = w2 * (T(3) * od[pp] + T(9) * eu * ev[pp]);
-            macc<L::E[i][0]>(b[0], t);
-            macc<L::E[i][1]>(b[1], t);
-            macc<L::E[i][2]>(b[2], t);
-        });
-        b[0] -= T(3) * u[0] * as;
-        b[1] -= T(3) * u[1] * as;
-        b[2] -= T(3) * u[2] * as;
-        const T wux = (T)a.w_ux;
-        auto finish = [&](auto J, T v) {
-            constexpr int jd = decltype(J)::value;
-            T out = mu[jd] - v + as + dir[jd];
-            macc<L::E[jd][0]>(out, b[0]);
-            macc<L::E[jd][1]>(out, b[1]);
-            macc<L::E[jd][2]>(out, b[2]);
-            if (a.obj_kind == 2) macc<L::E[jd][0]>(out, wux);
-            st_nt(lam_out + (size_t)jd * g.S, pos.n, out);
-        };
-        finish(std::integral_constant<int, 0>{}, e0);
-        unroll<NP>([&](auto P) {
-            constexpr int pp = decltype(P)::value;
-            constexpr int i = DER<L>.pi[pp];
-            constexpr int ib = TAB<L>.opp[i];
-            finish(std::integral_constant<int, i>{}, ev[pp] + od[pp]);
-            finish(std::integral_constant<int, ib>{}, ev[pp] - od[pp]);
-        });
+            // own cut links: Eq. (213) reversed and the drag terms; f_ibar(y, t)
+            // goes back to the link lane (the gradients are taken per link)
+            if constexpr (!PLAIN) {
+                if (nl.mask) {
+                    uint32_t k = nl.base;
+                    unroll<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        constexpr int ib = TAB<L>.opp[i];
+                        if constexpr (i > 0) {
+                            const uint32_t bit = (nl.mask >> i) & 1u;
+                            if (bit) {
+                                if (k < 64u) {
+                                    mu[i] += st.v[0][k];
+                                    mu[ib] += st.v[1][k];
+                                    st.v[0][k] = f[ib];
+                                } else {
+                                    own_link_direct<L, T, i>(wbase + k, lam_in, nxt, pos.n, g.S,
+                                                             lkcoef, lktag, sg, p, a, f, mu);
+                                }
+                            }
+                            k += bit;
+                        }
+                    });
+                }
+            }
 
-        // dJ/dg += 3 rho0 sum_i w_i e_i mu_i (pair form: w_i e_i (mu_i - mu_ibar)),
-        // summed over the node in T, accumulated over nodes in double
-        T sg[3] = {0, 0, 0};
-        unroll<NP>([&](auto P) {
-            constexpr int pp = decltype(P)::value;
-            constexpr int i = DER<L>.pi[pp];
-            const T t = T(L::W[i]) * dmu[pp];
-            macc<L::E[i][0]>(sg[0], t);
-            macc<L::E[i][1]>(sg[1], t);
-            macc<L::E[i][2]>(sg[2], t);
-        });
+            // collision adjoint: lambda = mu - v + J^T v + (c0, c1 link terms),
+            // v = M^T R M mu
+            T smu[NP], dmu[NP];
+            pair_split<L, T>(mu, smu, dmu);
+            T qm[Q];
+            moments_of<L, T>(mu[0], smu, dmu, qm);
+
+            // dJ/dg += 3 rho0 sum_i w_i e_i mu_i (pair form: w_i e_i (mu_i - mu_ibar)),
+            // summed over the node in T, accumulated over nodes in double
+            // (taken here in mixed waves, so that dmu dies before the link
+            // terms below; at the end in plain waves)
+            auto add_dg = [&]() {
+                T sg3[3] = {0, 0, 0};
+                unroll<NP>([&](auto P) {
+                    constexpr int pp = decltype(P)::value;
+                    constexpr int i = DER<L>.pi[pp];
+                    const T t = T(L::W[i]) * dmu[pp];
+                    macc<L::E[i][0]>(sg3[0], t);
+                    macc<L::E[i][1]>(sg3[1], t);
+                    macc<L::E[i][2]>(sg3[2], t);
+                });
 #pragma unroll
-        for (int al = 0; al < D; ++al) acc[al] += 3.0 * p.rho0_d * (double)sg[al];
-        if constexpr (WANT_DS) {
-            // dJ/ds_k -= (M mu)_k (M (f - f^eq))_k / |M_k|^2
-            T m[Q];
-            moments_of<L, T>(f[0], sp, dp, m);
-            subtract_equilibrium<L, T>(m, rho, j, p.inv_rho0);
+                for (int al = 0; al < D; ++al) acc[al] += 3.0 * p.rho0_d * (double)sg3[al];
+            };
+            if constexpr (!PLAIN) add_dg();
+
+            // the link terms that bypass the collision (c0 a_k onto
+            // lambda_i(y, t), c1 a_k onto lambda_ibar(y, t)) join mu now that
+            // its moments are taken, so that they need no registers of their own
+            if constexpr (!PLAIN) {
+                if (nl.mask) {
+                    uint32_t k = nl.base;
+                    unroll<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        constexpr int ib = TAB<L>.opp[i];
+                        if constexpr (i > 0) {
+                            const uint32_t bit = (nl.mask >> i) & 1u;
+                            if (bit) {
+                                if (k < 64u) {
+                                    mu[i] += st.v[2][k];
+                                    mu[ib] += st.v[3][k];
+                                } else {
+                                    own_link_bypass<L, T, i>(wbase + k, lam_in, pos.n, g.S,
+                                                             lkcoef, lktag, p, a, mu);
+                                }
+                            }
+                            k += bit;
+                        }
+                    });
+                }
+            }
+            T r[Q];
             unroll<Q>([&](auto K) {
                 constexpr int kk = decltype(K)::value;
-                if constexpr (!L::conserved(kk))
-                    acc[D + kk] -= (double)qm[kk] * (double)m[kk] / (double)TAB<L>.norm[kk];
+                r[kk] = L::conserved(kk) ? T(0) : qm[kk] * p.rate[kk];
             });
+            T e0, ev[NP], od[NP];
+            back_transform<L, T>(r, e0, ev, od);
+            // J^T v = as + b.e_j with as = sum w_i v_i and
+            // b = sum_i w_i v_i (3 e_i + 9 (e_i.u) e_i) - 3 u as
+            T as = T(L::W[0]) * e0;
+            T b[3] = {0, 0, 0};
+            unroll<NP>([&](auto P) {
+                constexpr int pp = decltype(P)::value;
+                constexpr int i = DER<L>.pi[pp];
+                const T w2 = T(2.0 * L::W[i]);
+                as += w2 * ev[pp];
+                T eu = 0;
+                macc<L::E[i][0]>(eu, u[0]);
+                macc<L::E[i][1]>(eu, u[1]);
+                macc<L::E[i][2]>(eu, u[2]);
+                const T t = w2 * (T(3) * od[pp] + T(9) * eu * ev[pp]);
+                macc<L::E[i][0]>(b[0], t);
+                macc<L::E[i][1]>(b[1], t);
+                macc<L::E[i][2]>(b[2], t);
+            });
+            b[0] -= T(3) * u[0] * as;
+            b[1] -= T(3) * u[1] * as;
+            b[2] -= T(3) * u[2] * as;
+            const T wux = (T)a.w_ux;
+            auto finish = [&](auto J, T v) {
+                constexpr int jd = decltype(J)::value;
+                T out = mu[jd] - v + as;
+                macc<L::E[jd][0]>(out, b[0]);
+                macc<L::E[jd][1]>(out, b[1]);
+                macc<L::E[jd][2]>(out, b[2]);
+                if (a.obj_kind == 2) macc<L::E[jd][0]>(out, wux);
+                st_nt(lam_out + (size_t)jd * g.S, pos.n, out);
+            };
+            finish(std::integral_constant<int, 0>{}, e0);
+            unroll<NP>([&](auto P) {
+                constexpr int pp = decltype(P)::value;
+                constexpr int i = DER<L>.pi[pp];
+                constexpr int ib = TAB<L>.opp[i];
+                finish(std::integral_constant<int, i>{}, ev[pp] + od[pp]);
+                finish(std::integral_constant<int, ib>{}, ev[pp] - od[pp]);
+            });
+            if constexpr (PLAIN) add_dg();
+            if constexpr (WANT_DS) {
+                // dJ/ds_k -= (M mu)_k (M (f - f^eq))_k / |M_k|^2
+                T m[Q];
+                moments_of<L, T>(f[0], sp, dp, m);
+                subtract_equilibrium<L, T>(m, rho, j, p.inv_rho0);
+                unroll<Q>([&](auto K) {
+                    constexpr int kk = decltype(K)::value;
+                    if constexpr (!L::conserved(kk))
+                        acc[D + kk] -= (double)qm[kk] * (double)m[kk] / (double)TAB<L>.norm[kk];
+                });
+            }
+        };
+
+        if constexpr (!MX) {
+            node(std::true_type{}, NodeLinks{0u, 0u});
+        } else {
+            // link lanes: the link's adjoint a_k = lambda_i(y, t+1) and the forward
+            // step's stored f'_i(y, t), f'_ibar(y, t), staged for the link
+            // gradients at once
+            int le[3] = {0, 0, 0}, lib = 0;
+            double lw = 0.0;
+            double ak = 0.0;
+            LinkCoef c{0.0, 0.0, 0.0, 0.0};
+            if (link_lane) {
+                dir_data<L>(ld_dir, le, lw, lib);
+                c = lkcoef[kl];
+                ak = (double)lam_in[(size_t)ld_dir * g.S + ld_node];
+                sg.fpi[kl] = nxt[(size_t)ld_dir * g.S + ld_node];
+                sg.fpib[kl] = nxt[(size_t)lib * g.S + ld_node];
+            }
+            const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
+            const bool sol = is_solid(info);
+            const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, 0u);
+            // forward state: the link slots of the recorded step
+            const T wa0 = lane < nlw ? wa[wbase + lane] : T(0);
+            wave_link_values<L, T>(wa, wbase, lane, wa0, nl, st, f);
+            if (p.c1d) complete_two_node<L, T>(p.c1d + wbase, nl, f);
+            // link lanes: the pieces of mu and lambda(y, t) that a_k feeds
+            if (link_lane) {
+                double dfx = 0.0;
+                if (a.obj_kind == 1 && le[0] != 0 && lktag[kl] == a.obj_tag) {
+                    // drag: (e_ibar)_x (f'_ibar(y,t) + f_i(y,t+1))
+                    dfx = -(double)le[0] * a.w_force;
+                    ak += dfx;
+                }
+                sg.ak[kl] = ak;
+                st.v[0][lane] = (T)(c.c2 * ak);
+                st.v[1][lane] = (T)(c.c3 * ak + dfx);
+                st.v[2][lane] = (T)(p.c0 * ak);
+                st.v[3][lane] = (T)(c.c1 * ak);
+            }
+            wave_lds_sync();
+            if (!sol) node(std::false_type{}, nl);
+            wave_lds_sync();
+            // link lanes: stage f_ibar(y, t) handed back by the node's lane
+            if (link_lane) sg.fib[kl] = st.v[0][lane];
+            // the solid lanes store NaN (nothing reads lambda at solid nodes) so
+            // that the wave writes whole lines of lam_out: partial lines cost
+            // HBM read-modify-write cycles
+            if (pos.in && sol) {
+                unroll<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));
+                });
+            }
         }
     };
-
-    if (kind == WAVE_PLAIN) {
-        node(std::true_type{}, NodeLinks{0u, 0u});
-    } else if (kind == WAVE_MIXED) {
-        const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
-        const bool sol = is_solid(info);
-        const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, 0u);
-        // forward state: the link slots of the recorded step
-        const T wa0 = lane < nlw ? wa[wbase + lane] : T(0);
-        wave_link_values<L, T>(wa, wbase, lane, wa0, nl, st, f);
-        if (p.c1d) complete_two_node<L, T>(p.c1d + wbase, nl, f);
-        // link lanes: a_k and the pieces of mu and lambda(y, t) it feeds
-        double ak = 0.0;
-        int ld_dir = 0;
-        if (lane < nlw && lane < 64u) {
-            const uint32_t k = wbase + lane;
-            ld_dir = lkdir[k];
-            int e[3];
-            double w;
-            dir_data<L>(ld_dir, e, w);
-            ak = (double)lam_in[(size_t)ld_dir * g.S + (uint32_t)lknode[k]];
-            double dfx = 0.0;
-            if (a.obj_kind == 1 && e[0] != 0 && lktag[k] == a.obj_tag) {
-                // drag: (e_ibar)_x (f'_ibar(y,t) + f_i(y,t+1))
-                dfx = -(double)e[0] * a.w_force;
-                ak += dfx;
-            }
-            const LinkCoef c = lkcoef[k];
-            st.v[0][lane] = (T)(c.c2 * ak);
-            st.v[1][lane] = (T)(c.c3 * ak + dfx);
-            st.v[2][lane] = (T)(p.c0 * ak);
-            st.v[3][lane] = (T)(c.c1 * ak);
-        }
-        wave_lds_sync();
-        if (!sol) node(std::false_type{}, nl);
-        wave_lds_sync();
-        // link lanes: per-link gradients from the node's values
-        if (lane < nlw && lane < 64u) {
-            const uint32_t k = wbase + lane;
-            const LinkDeriv dc = lkderiv[k];
-            gq[k] += ak * (dc.d1 * (double)st.v[0][lane] + dc.d2 * (double)st.v[1][lane] +
-                           dc.d3 * (double)st.v[2][lane] + p.wall_scale * dc.dwall);
-            int e[3];
-            double w;
-            dir_data<L>(ld_dir, e, w);
-            const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * p.wall_scale * ak;
-#pragma unroll
-            for (int al = 0; al < D; ++al)
-                if (e[al] != 0) gphi[(size_t)k * D + al] += c4w * e[al];
-        }
-        // the solid lanes store NaN (nothing reads lambda at solid nodes) so
-        // that the wave writes whole lines of lam_out: partial lines cost
-        // HBM read-modify-write cycles
-        if (pos.in && sol) {
-            unroll<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));
-            });
-        }
+    if (active) {
+        if ((__builtin_amdgcn_readfirstlane(wm.y) & 3u) == WAVE_PLAIN)
+            run(std::false_type{});
+        else
+            run(std::true_type{});
     }
 
-    // lb is uniform over the block, so the barrier inside is block-uniform
-    if (lb < g.nblocks) block_accumulate<NR>(acc, gglob + (size_t)lb * NC);
+    // every wave of the block reaches the barrier inside
+    block_accumulate<NR>(acc, gglob + (size_t)blockIdx.x * NC);
 }
 
 // Eq. (211) links k = (x_f, i) with a deferred c1: the link value is
@@ -497,9 +619,17 @@ static hipError_t adj_dispatch(const Engine& e, F&& f) {
     return e.precision == 0 ? by_xbc(D3Q19{}, double{}) : by_xbc(D3Q19{}, float{});
 }
 
-hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const void* lam_in,
-                               void* lam_out, const AdjointObjective& obj) {
+static uint32_t wave_blocks(int64_t waves) { return (uint32_t)((waves + BX / 64 - 1) / (BX / 64)); }
+
+int64_t adjoint_blocks(const Engine& e) {
+    return std::max<int64_t>(1, (int64_t)wave_blocks(e.n_wact));
+}
+
+hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& next,
+                               const void* lam_in, void* lam_out, const AdjointObjective& obj) {
     const Grid g = adj_grid(e);
+    const uint32_t wpr = e.nx % 64 == 0 ? (uint32_t)(e.nx / 64) : 0u;
+    const WaveList waves{e.d_wact, (uint32_t)e.n_wact, wpr};
     AdjArgs a;
     a.obj_kind = obj.kind;
     a.obj_tag = obj.tag;
@@ -510,14 +640,28 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const void* lam_i
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        auto kern = a.want_ds ? (g.bpr ? k_adjoint<L, T, XB, true, true> : k_adjoint<L, T, XB, true, false>)
-                              : (g.bpr ? k_adjoint<L, T, XB, false, true> : k_adjoint<L, T, XB, false, false>);
-        hipLaunchKernelGGL(kern, dim3(g.chunk ? g.chunk * NXCD : g.nblocks), dim3(BX), 0,
-                           e.stream, (const T*)fwd.f, (const T*)fwd.wa,
-                           (const T*)lam_in, (T*)lam_out,
-                           NodeMeta{e.d_info, e.d_wave}, e.d_lkcoef, e.d_lkderiv, e.d_lkc4, e.d_lktag,
-                           e.d_lkdir, e.d_lknode, e.d_gq,
-                           e.d_gphi, e.d_gglob, g, adj_params<L, T>(e), a);
+        auto kern = a.want_ds ? (wpr ? k_adjoint<L, T, XB, true, true> : k_adjoint<L, T, XB, true, false>)
+                              : (wpr ? k_adjoint<L, T, XB, false, true> : k_adjoint<L, T, XB, false, false>);
+        const Params<L, T> prm = adj_params<L, T>(e);
+        // staging: [a_k: L doubles][f_ibar][f'_i][f'_ibar: L values of T each]
+        const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
+        LinkStaging<T> sg;
+        sg.ak = (double*)e.d_stage;
+        sg.fib = (T*)(sg.ak + L1);
+        sg.fpi = sg.fib + L1;
+        sg.fpib = sg.fpi + L1;
+        if (waves.count)
+            hipLaunchKernelGGL(kern, dim3(wave_blocks(waves.count)), dim3(BX), 0, e.stream,
+                               (const T*)fwd.f, (const T*)fwd.wa, (const T*)next.f,
+                               (const T*)lam_in, (T*)lam_out,
+                               NodeMeta{e.d_info, e.d_wave}, waves, e.d_lkcoef,
+                               e.d_lktag, e.d_lkdir, e.d_lknode, sg,
+                               e.d_gglob, g, prm, a);
+        // per-link gradients, from what the mixed waves staged
+        if (e.n_links)
+            hipLaunchKernelGGL((k_link_grad<L, T>), dim3((unsigned)((e.n_links + BX - 1) / BX)),
+                               dim3(BX), 0, e.stream, sg, e.d_lkdir, e.d_lkderiv, e.d_lkc4,
+                               e.d_gq, e.d_gphi, (uint32_t)e.n_links, prm);
         return hipGetLastError();
     });
 }

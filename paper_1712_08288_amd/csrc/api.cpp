@@ -354,13 +354,15 @@ int adjoint_begin(lbm_t* h) {
             if ((rc = alloc_snap(h, e.pool[k]))) return rc;
     }
     const int NC = e.D + e.Q;
-    const int64_t nb = lbe::step_blocks(e);
+    const int64_t nb = lbe::adjoint_blocks(e);
     const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
     if (!e.d_gq || e.gglob_len != nb || e.gq_len != (int64_t)L1) {
         free_dev(e.d_gq);
         free_dev(e.d_gphi);
         free_dev(e.d_gglob);
+        free_dev(e.d_stage);
         if (hipMalloc((void**)&e.d_gq, L1 * 8) != hipSuccess ||
+            hipMalloc(&e.d_stage, 4 * L1 * 8) != hipSuccess ||
             hipMalloc((void**)&e.d_gphi, L1 * e.D * 8) != hipSuccess ||
             hipMalloc((void**)&e.d_gglob, (size_t)nb * NC * 8) != hipSuccess)
             return fail(h, LBM_ENOMEM, "gradient accumulator allocation failed");
@@ -391,17 +393,16 @@ int adjoint_steps(lbm_t* h, int64_t n) {
         const int64_t t_seg = e.run_t0 + j * e.run_every;
         const int64_t len = std::min(e.run_every, e.run_n - j * e.run_every);
         // the segment's states: the checkpoint itself, then the replayed
-        // ones.  The adjoint of step r reads state r; Eq. (211)'s pre-pass
-        // also reads state r + 1, which for r = len - 1 is the next
-        // checkpoint (replayed only for the last segment).  So the replay
-        // stops at state len - 1 unless that last state is needed.
+        // ones.  The adjoint of step r reads states r and r + 1; for
+        // r = len - 1 that is the next checkpoint, so only the last segment
+        // replays state len.
         auto state = [&](int64_t k) -> const Snapshot& {
             if (k == 0) return e.ckpt[j];
             if (k == len && j + 1 < nseg) return e.ckpt[j + 1];
             return e.pool[k];
         };
         if (e.adj_seg != j) {
-            const int64_t nrep = e.two_node && j + 1 == nseg ? len : len - 1;
+            const int64_t nrep = j + 1 == nseg ? len : len - 1;
             for (int64_t k = 0; k < nrep; ++k) {
                 e.t = t_seg + k;   // forward_step reads e.t for the objective window and wall data
                 if ((rc = forward_step(h, state(k), e.pool[k + 1], false))) break;
@@ -421,7 +422,7 @@ int adjoint_steps(lbm_t* h, int64_t n) {
         e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
         if (e.two_node) st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
         if (st == hipSuccess)
-            st = lbe::launch_adjoint_step(e, state(r), e.lam[lc], e.lam[lc ^ 1], ao);
+            st = lbe::launch_adjoint_step(e, state(r), state(r + 1), e.lam[lc], e.lam[lc ^ 1], ao);
         if (st != hipSuccess) {
             rc = fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));
             break;
@@ -671,6 +672,11 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         }
         if (k != n_links) return fail(h, LBM_EGEOM, "link count mismatch");
     }
+    // the adjoint's wave list: the non-idle waves with their table entries
+    std::vector<uint4> wact;
+    for (size_t w = 0; w < wave.size(); ++w)
+        if ((wave[w].x & 3u) != 2u) wact.push_back(make_uint4((uint32_t)w, wave[w].x, wave[w].y, 0u));
+    e.n_wact = (int64_t)wact.size();
     std::vector<uint8_t> d8(n_links);
     std::vector<int32_t> n32(n_links);
     for (int64_t k = 0; k < n_links; ++k) {
@@ -683,6 +689,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     int rc;
     if ((rc = upload(h, e.d_info, info.data(), info.size()))) return rc;
     if ((rc = upload(h, e.d_wave, wave.data(), wave.size()))) return rc;
+    if ((rc = upload(h, e.d_wact, wact.data(), wact.size()))) return rc;
     if ((rc = upload(h, e.d_lkdir, d8.data(), d8.size()))) return rc;
     if ((rc = upload(h, e.d_lknode, n32.data(), n32.size()))) return rc;
     if ((rc = upload(h, e.d_lktag, e.tag_h.data(), e.tag_h.size()))) return rc;
@@ -1158,6 +1165,7 @@ int lbm_destroy(lbm_t* h) {
     for (auto& b : e.buf) free_snap(b);
     free_dev(e.d_info);
     free_dev(e.d_wave);
+    free_dev(e.d_wact);
     free_dev(e.d_lkdir);
     free_dev(e.d_lknode);
     free_dev(e.d_lktag);
@@ -1170,6 +1178,7 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_gq);
     free_dev(e.d_gphi);
     free_dev(e.d_gglob);
+    free_dev(e.d_stage);
     free_dev(e.d_scratch);
     if (e.ev0) (void)hipEventDestroy(e.ev0);
     if (e.ev1) (void)hipEventDestroy(e.ev1);

@@ -56,6 +56,8 @@ struct Engine {
     uint32_t* d_info = nullptr;         // per node: bit 31 solid, bits 19..30 link offset
                                         // within the wave, bits 0..Q-1 link directions
     uint2* d_wave = nullptr;            // per 64-node wave of a node launch: kind, first link
+    uint4* d_wact = nullptr;            // the adjoint's non-idle waves in memory order:
+    int64_t n_wact = 0;                 // {id, kind | links << 2, first link, 0}
     uint8_t* d_lkdir = nullptr;
     int32_t* d_lknode = nullptr;
     int32_t* d_lktag = nullptr;
@@ -90,6 +92,7 @@ struct Engine {
     void* lam[2] = {nullptr, nullptr};  // adjoint arrays (Q*N values of T)
     double* d_gq = nullptr;             // dJ/dgamma per link
     double* d_gphi = nullptr;           // dJ/dphi per link (L*D)
+    void* d_stage = nullptr;            // per link: values staged for the link gradients (4 L doubles)
     double* d_gglob = nullptr;          // per-block partials of dJ/dg (D) and dJ/ds (Q)
     int64_t gglob_len = 0;
     bool have_grad = false;
@@ -142,6 +145,7 @@ hipError_t launch_force_objective(Engine& e, const Snapshot& post, double* acc,
 hipError_t launch_sum_blocks(Engine& e, const double* partials, int64_t rows,
                              int64_t cols, double* out);
 int64_t step_blocks(const Engine& e);       // logical blocks of a node launch
+int64_t adjoint_blocks(const Engine& e);    // blocks of the two adjoint launches together
 int64_t link_blocks(const Engine& e);       // blocks of a link launch
 
 // ---- launchers (adjoint.hip) -------------------------------------------------
@@ -153,7 +157,9 @@ struct AdjointObjective {
     double weight = 0.0;         // 0 when step t is outside the window
     double inv_nfluid = 0.0;
 };
-hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd,
+// One reverse step: lambda(t) from lambda(t+1) with the forward states at t
+// (`fwd`) and t+1 (`next`), accumulating the gradients.
+hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& next,
                                const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
