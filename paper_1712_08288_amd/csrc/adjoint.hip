@@ -595,9 +595,10 @@ static Grid adj_grid(const Engine& e) {
     g.nz = (uint32_t)e.nz;
     g.N = (uint32_t)e.N;
     g.S = (uint32_t)e.S;
+    // the adjoint kernels index waves and links, not blocks of a node launch
     g.nblocks = (uint32_t)((e.N + BX - 1) / BX);
-    g.bpr = e.nx % BX == 0 ? (uint32_t)(e.nx / BX) : 0u;
-    g.chunk = e.xcd_remap ? (g.nblocks + NXCD - 1) / NXCD : 0;
+    g.bpr = 0u;
+    g.chunk = 0u;
     return g;
 }
 

@@ -45,6 +45,14 @@ def _gpu_grad(geom, s, kw, obj, steps, every, df0, precision="fp64"):
     return sv, J, gr
 
 
+def _moving_channel():
+    """D3Q19 channel whose wall rows give waves of more than 64 cut links
+    (the links past the 64th of a wave take the direct path) and moving walls
+    (non-zero wall-velocity gradients)."""
+    geom = G.poiseuille_channel(9, 0.7, nx=24, lattice="D3Q19", nz=5)
+    return geom.with_wall_u(np.tile([0.02, 0.0, -0.01], (geom.n_links, 1)))
+
+
 CASES = [
     ("d2q9_drag_periodic", lambda: G.random_cylinders(40, 29, 2, 3.1, 5.2, seed=6),
      lambda: configs.d2q9_rates(0.7), dict(g=(1e-4, 2e-5, 0), l_rule="gamma2", b=0.9),
@@ -69,6 +77,9 @@ CASES = [
                                                     lattice="D3Q15"),
      lambda: configs.d3q15_paper_rates(1.3), dict(g=(2e-5, 1e-5, 0), dp=1e-3, l_rule="gamma2"),
      Objective("mean_ux", t0=1, t1=8), 8),
+    ("d3q19_meanux_channel_many_links", _moving_channel,
+     lambda: configs.d3q19_rates(0.8), dict(g=(1e-5, 0, 2e-6), l_rule="gamma2", b=0.95),
+     Objective("mean_ux", t0=1, t1=7), 7),
     ("d3q15_drag_periodic_two_node", lambda: G.random_spheres(18, 15, 13, 2, 2.4, 3.6, seed=11,
                                                               lattice="D3Q15"),
      lambda: configs.d3q15_paper_rates(1.1), dict(g=(3e-5, 0, 0), l_rule="1.5gamma", b=0.95,
