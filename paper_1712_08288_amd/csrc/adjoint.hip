@@ -242,7 +242,8 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
     const bool active = slot < wl.count;
     const uint4 wm = active ? wl.ent[slot] : uint4{0u, 0u, 0u, 0u};
     const uint32_t w = __builtin_amdgcn_readfirstlane(wm.x);
-    const uint32_t nlw = __builtin_amdgcn_readfirstlane(wm.y) >> 2;
+    const uint32_t wx = __builtin_amdgcn_readfirstlane(wm.y);
+    const uint32_t nlw = wave_links(uint2{wx, 0u});
     const uint32_t wbase = __builtin_amdgcn_readfirstlane(wm.z);
     const NodePos pos = node_of_wave<ROWS>(g, wl, w, lane, active);
     LinkStage<T>& st = stage[wid];
@@ -273,7 +274,10 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
         // of solid or absent neighbours are read and then discarded)
         T f[Q], lg[Q];
         const Push<XB> ps(g, pos);
-        if (!MX || pos.in) {
+        // plain waves are 64 fluid nodes inside the grid; in mixed waves the
+        // lanes of quarters without fluid nodes neither read nor write
+        const bool live = !MX || (pos.in && lane_in_live_quarter(wx, lane));
+        if (live) {
             pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
             unroll<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
@@ -473,7 +477,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
                 sg.fpi[kl] = nxt[(size_t)ld_dir * g.S + ld_node];
                 sg.fpib[kl] = nxt[(size_t)lib * g.S + ld_node];
             }
-            const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
+            const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
             const bool sol = is_solid(info);
             const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, 0u);
             // forward state: the link slots of the recorded step
@@ -502,7 +506,11 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
             // the solid lanes store NaN (nothing reads lambda at solid nodes) so
             // that the wave writes whole lines of lam_out: partial lines cost
             // HBM read-modify-write cycles
+#ifndef LBM_DEAD_QUARTER_NAN
+            if (live && sol) {
+#else
             if (pos.in && sol) {
+#endif
                 unroll<Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));

@@ -668,7 +668,15 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
                 k += __builtin_popcount(mask[n]);
             }
             const uint32_t kind = !any_fluid ? 2u : (all_plain ? 1u : 0u);
-            wave[w] = make_uint2(kind | ((uint32_t)(k - k0) << 2), (uint32_t)k0);
+            uint32_t dead = 0u;   // quarters of 16 lanes without a fluid node
+            for (int qd = 0; qd < 4; ++qd) {
+                bool fluid = false;
+                for (int64_t n = n0 + 16 * qd; n < std::min<int64_t>(n0 + 16 * qd + 16, N); ++n)
+                    fluid = fluid || !solid[n];
+                if (!fluid) dead |= 1u << qd;
+            }
+            if (kind != 0u) dead = 0u;
+            wave[w] = make_uint2(kind | ((uint32_t)(k - k0) << 2) | (dead << 16), (uint32_t)k0);
         }
         if (k != n_links) return fail(h, LBM_EGEOM, "link count mismatch");
     }

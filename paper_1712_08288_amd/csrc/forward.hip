@@ -105,9 +105,10 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         // slot reads and the info word first, the plane reads without
         // waiting for either
         const T wa0 = lane < nlw ? waA[wbase + lane] : T(0);
-        const uint32_t info = pos.in ? nm.info[pos.n] : kInfoSolid;
+        const bool live = pos.in && lane_in_live_quarter(wv.x, lane);
+        const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
         T f[L::Q];
-        if (pos.in) {
+        if (live) {
             pull_planes<L, T, XB, false, kStepTables<T>>(A, g, pos, p, NodeLinks{0u, 0u}, f);
         } else {
             unroll<L::Q>([&](auto I) { f[decltype(I)::value] = T(0); });
@@ -123,7 +124,11 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         });
         Macro<L, T> mac;
         collide<L, T, false, kStepTables<T>>(f, p, mac);
+#ifndef LBM_DEAD_QUARTER_NAN
+        if (live) {
+#else
         if (pos.in) {
+#endif
             if (!sol) ux_local = (double)mac.u[0];
             const T nan = (T)__builtin_nan("");
             unroll<L::Q>([&](auto I) {

@@ -356,8 +356,10 @@ struct NodeMeta {
     const uint32_t* __restrict__ info;   // bit 31: solid; bits 19..30: link offset
                                          // within the wave; bits 0..Q-1: cut-link directions
     const uint2* __restrict__ wave;      // per wave: x = kind (bits 0..1: 0 mixed,
-                                         // 1 all fluid without links, 2 no fluid) and
-                                         // link count (bits 2..31), y = first link
+                                         // 1 all fluid without links, 2 no fluid), link
+                                         // count (bits 2..15) and the quarters of 16
+                                         // lanes without a fluid node (bits 16..19);
+                                         // y = first link
 };
 
 enum WaveKind : uint32_t { WAVE_MIXED = 0, WAVE_PLAIN = 1, WAVE_IDLE = 2 };
@@ -369,7 +371,12 @@ constexpr uint32_t kInfoOffsetMax = 0xFFFu;
 
 __device__ __forceinline__ bool is_solid(uint32_t info) { return (info >> 31) != 0; }
 __device__ __forceinline__ uint32_t wave_kind(uint2 w) { return w.x & 3u; }
-__device__ __forceinline__ uint32_t wave_links(uint2 w) { return w.x >> 2; }
+__device__ __forceinline__ uint32_t wave_links(uint2 w) { return (w.x >> 2) & 0x3FFFu; }
+// A mixed wave's lanes in a quarter without fluid nodes neither read nor
+// write: each such quarter is a whole 64-byte segment of every FP32 plane.
+__device__ __forceinline__ bool lane_in_live_quarter(uint32_t wave_x, uint32_t lane) {
+    return ((wave_x >> (16u + (lane >> 4))) & 1u) == 0u;
+}
 
 // the wave of a node launch that holds node n
 __device__ __forceinline__ uint32_t wave_of_node(const Grid&, uint32_t n) { return n / 64; }
