@@ -275,8 +275,9 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
         T f[Q], lg[Q];
         const Push<XB> ps(g, pos);
         // plain waves are 64 fluid nodes inside the grid; in mixed waves the
-        // lanes of quarters without fluid nodes neither read nor write
-        const bool live = !MX || (pos.in && lane_in_live_quarter(wx, lane));
+        // lanes of 64-byte plane segments without fluid nodes neither read nor
+        // write
+        const bool live = !MX || (pos.in && lane_in_live_segment<T>(wx, lane));
         if (live) {
             pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
             unroll<Q>([&](auto I) {
@@ -506,11 +507,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
             // the solid lanes store NaN (nothing reads lambda at solid nodes) so
             // that the wave writes whole lines of lam_out: partial lines cost
             // HBM read-modify-write cycles
-#ifndef LBM_DEAD_QUARTER_NAN
             if (live && sol) {
-#else
-            if (pos.in && sol) {
-#endif
                 unroll<Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));

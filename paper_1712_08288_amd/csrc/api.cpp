@@ -668,10 +668,10 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
                 k += __builtin_popcount(mask[n]);
             }
             const uint32_t kind = !any_fluid ? 2u : (all_plain ? 1u : 0u);
-            uint32_t dead = 0u;   // quarters of 16 lanes without a fluid node
-            for (int qd = 0; qd < 4; ++qd) {
+            uint32_t dead = 0u;   // eighths of 8 lanes without a fluid node
+            for (int qd = 0; qd < 8; ++qd) {
                 bool fluid = false;
-                for (int64_t n = n0 + 16 * qd; n < std::min<int64_t>(n0 + 16 * qd + 16, N); ++n)
+                for (int64_t n = n0 + 8 * qd; n < std::min<int64_t>(n0 + 8 * qd + 8, N); ++n)
                     fluid = fluid || !solid[n];
                 if (!fluid) dead |= 1u << qd;
             }

@@ -75,7 +75,8 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
 // if its nodes were plain (solid and cut-link slots included) and replaces
 // the cut-link directions from their slots.  Its solid lanes store NaN into
 // their own slots, which nothing reads: a full store keeps every written
-// cache line whole (partial lines cost HBM read-modify-write cycles).
+// cache line whole (partial lines cost HBM read-modify-write cycles).  Lanes
+// whose 64-byte segment of the planes holds no fluid node skip both.
 template <class L, class T, int XB, bool ROWS>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
@@ -105,7 +106,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         // slot reads and the info word first, the plane reads without
         // waiting for either
         const T wa0 = lane < nlw ? waA[wbase + lane] : T(0);
-        const bool live = pos.in && lane_in_live_quarter(wv.x, lane);
+        const bool live = pos.in && lane_in_live_segment<T>(wv.x, lane);
         const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
         T f[L::Q];
         if (live) {
@@ -124,11 +125,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         });
         Macro<L, T> mac;
         collide<L, T, false, kStepTables<T>>(f, p, mac);
-#ifndef LBM_DEAD_QUARTER_NAN
         if (live) {
-#else
-        if (pos.in) {
-#endif
             if (!sol) ux_local = (double)mac.u[0];
             const T nan = (T)__builtin_nan("");
             unroll<L::Q>([&](auto I) {

@@ -357,8 +357,8 @@ struct NodeMeta {
                                          // within the wave; bits 0..Q-1: cut-link directions
     const uint2* __restrict__ wave;      // per wave: x = kind (bits 0..1: 0 mixed,
                                          // 1 all fluid without links, 2 no fluid), link
-                                         // count (bits 2..15) and the quarters of 16
-                                         // lanes without a fluid node (bits 16..19);
+                                         // count (bits 2..15) and the eighths of 8
+                                         // lanes without a fluid node (bits 16..23);
                                          // y = first link
 };
 
@@ -372,10 +372,16 @@ constexpr uint32_t kInfoOffsetMax = 0xFFFu;
 __device__ __forceinline__ bool is_solid(uint32_t info) { return (info >> 31) != 0; }
 __device__ __forceinline__ uint32_t wave_kind(uint2 w) { return w.x & 3u; }
 __device__ __forceinline__ uint32_t wave_links(uint2 w) { return (w.x >> 2) & 0x3FFFu; }
-// A mixed wave's lanes in a quarter without fluid nodes neither read nor
-// write: each such quarter is a whole 64-byte segment of every FP32 plane.
-__device__ __forceinline__ bool lane_in_live_quarter(uint32_t wave_x, uint32_t lane) {
-    return ((wave_x >> (16u + (lane >> 4))) & 1u) == 0u;
+// A mixed wave's lanes in a 64-byte segment of a plane without fluid nodes
+// (16 lanes in FP32, 8 in FP64) neither read nor write it.  Smaller segments
+// are still written whole (NaN at solid lanes): partial writes cost HBM
+// read-modify-write cycles.
+template <class T>
+__device__ __forceinline__ bool lane_in_live_segment(uint32_t wave_x, uint32_t lane) {
+    if constexpr (sizeof(T) == 4)
+        return ((wave_x >> (16u + 2u * (lane >> 4))) & 3u) != 3u;
+    else
+        return ((wave_x >> (16u + (lane >> 3))) & 1u) == 0u;
 }
 
 // the wave of a node launch that holds node n
