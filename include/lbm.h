@@ -255,6 +255,15 @@ int lbm_set_rate_gradient(lbm_t *h, int on);
  * may be NULL.  Synchronises. */
 int lbm_grad(lbm_t *h, double *dq, double *dwall_u, double *dg, double *ds);
 
+/* The same gradients with the per-link ones left on the device: dq_dev
+ * (n_links doubles) and dwall_u_dev (n_links * D doubles, link-major) are
+ * device memory owned by the caller, written in the caller's link order by
+ * a kernel enqueued on the handle's stream (no host transfer; the caller
+ * orders its own use after that stream).  dg and ds are host arrays as in
+ * lbm_grad(); when both are NULL the call does not synchronise.  Any
+ * pointer may be NULL. */
+int lbm_grad_device(lbm_t *h, void *dq_dev, void *dwall_u_dev, double *dg, double *ds);
+
 /* Adjoint state lambda(t0) = dJ/df(x, t0) at the start of the last run,
  * lam[i*N + n] (0 at solid nodes).  Synchronises. */
 int lbm_get_adjoint(lbm_t *h, double *lam);

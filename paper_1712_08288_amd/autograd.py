@@ -57,11 +57,20 @@ class LBMObjective(torch.autograd.Function):
     def backward(ctx, grad_out):
         sv = ctx.problem.solver
         sv.adjoint()
-        gr = sv.grad()
+        (dev_q, _, _), (dev_u, _, _) = ctx.meta[0], ctx.meta[1]
+        if dev_q.type == "cuda" and dev_u.type == "cuda":
+            # per-link gradients stay on the device (no host round trip)
+            nf, nl = sv.counts()
+            dq = torch.empty(nl, dtype=torch.float64, device=dev_q)
+            du = torch.empty((nl, sv.D), dtype=torch.float64, device=dev_u)
+            small = sv.grad_device(dq, du)
+            gr = dict(q=dq, wall_u=du, g=torch.as_tensor(small["g"]), s=torch.as_tensor(small["s"]))
+        else:
+            gr = {k: torch.as_tensor(v) for k, v in sv.grad().items()}
         scale = float(grad_out)
         outs = []
         for key, (dev, dt, shape) in zip(("q", "wall_u", "g", "s"), ctx.meta):
-            outs.append(torch.as_tensor(gr[key] * scale, dtype=dt).reshape(shape).to(dev))
+            outs.append((gr[key] * scale).to(dtype=dt).reshape(shape).to(dev))
         return outs[0], outs[1], outs[2], outs[3], None
 
 

@@ -63,6 +63,7 @@ _objective = _sig("lbm_objective", _i, [_p, _p])
 _run_ckpt = _sig("lbm_run_checkpointed", _i, [_p, _i64, _i64])
 _adjoint = _sig("lbm_adjoint", _i, [_p])
 _grad = _sig("lbm_grad", _i, [_p, _p, _p, _p, _p])
+_grad_dev = _sig("lbm_grad_device", _i, [_p, _p, _p, _p, _p])
 _set_rate_grad = _sig("lbm_set_rate_gradient", _i, [_p, _i])
 _get_adj = _sig("lbm_get_adjoint", _i, [_p, _p])
 _set_stream = _sig("lbm_set_stream", _i, [_p, _p])
@@ -81,7 +82,7 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_get_distribution", "lbm_reduce", "lbm_force",
             "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
             "lbm_set_objective", "lbm_objective", "lbm_run_checkpointed",
-            "lbm_adjoint", "lbm_adjoint_step", "lbm_adjoint_remaining", "lbm_set_rate_gradient", "lbm_grad", "lbm_get_adjoint", "lbm_set_stream",
+            "lbm_adjoint", "lbm_adjoint_step", "lbm_adjoint_remaining", "lbm_set_rate_gradient", "lbm_grad", "lbm_grad_device", "lbm_get_adjoint", "lbm_set_stream",
             "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
             "lbm_last_step_ms", "lbm_stream_copy", "lbm_last_error",
             "lbm_destroy"]
@@ -339,6 +340,23 @@ class Solver:
         ds = np.zeros(self.Q)
         self._chk(_grad(self._h, _ptr(dq), _ptr(du), _ptr(dg), _ptr(ds)), "grad")
         return dict(q=dq, wall_u=du, g=dg, s=ds)
+
+    def grad_device(self, dq=None, wall_u=None):
+        """Per-link gradients written into caller-owned device tensors
+        (float64, contiguous: dq (L,), wall_u (L, D), caller link order) by
+        a kernel on the handle's stream; dJ/dg and dJ/ds come back on the
+        host."""
+        nf, nl = self.counts()
+        for t, shape in ((dq, (nl,)), (wall_u, (nl, self.D))):
+            if t is not None and (tuple(t.shape) != shape or not t.is_contiguous()
+                                  or str(t.dtype) != "torch.float64" or not t.is_cuda):
+                raise ValueError("grad_device: expected a contiguous float64 device tensor of shape %s" % (shape,))
+        dg = np.zeros(self.D)
+        ds = np.zeros(self.Q)
+        self._chk(_grad_dev(self._h, dq.data_ptr() if dq is not None else None,
+                            wall_u.data_ptr() if wall_u is not None else None,
+                            _ptr(dg), _ptr(ds)), "grad_device")
+        return dict(g=dg, s=ds)
 
     def get_adjoint(self):
         lam = np.empty((self.Q, self.N))

@@ -695,6 +695,22 @@ hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in
     });
 }
 
+__global__ void __launch_bounds__(BX)
+k_links_to_caller(const double* __restrict__ in, double* __restrict__ out,
+                  const int32_t* __restrict__ perm, uint32_t n_links, int width) {
+    const uint32_t k = blockIdx.x * BX + threadIdx.x;
+    if (k >= n_links) return;
+    const size_t p = (size_t)(uint32_t)perm[k];
+    for (int a = 0; a < width; ++a) out[p * width + a] = in[(size_t)k * width + a];
+}
+
+hipError_t launch_links_to_caller(Engine& e, const double* in, double* out, int width) {
+    if (!e.n_links) return hipSuccess;
+    hipLaunchKernelGGL(k_links_to_caller, dim3((unsigned)((e.n_links + BX - 1) / BX)), dim3(BX),
+                       0, e.stream, in, out, e.d_perm, (uint32_t)e.n_links, width);
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out) {
     const unsigned nb = (unsigned)((e.N + BX - 1) / BX);
     return adj_dispatch(e, [&](auto lat, auto prec, auto) -> hipError_t {

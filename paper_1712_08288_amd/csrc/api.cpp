@@ -700,6 +700,11 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     if ((rc = upload(h, e.d_wact, wact.data(), wact.size()))) return rc;
     if ((rc = upload(h, e.d_lkdir, d8.data(), d8.size()))) return rc;
     if ((rc = upload(h, e.d_lknode, n32.data(), n32.size()))) return rc;
+    {
+        std::vector<int32_t> p32(n_links);
+        for (int64_t k = 0; k < n_links; ++k) p32[k] = (int32_t)e.perm[k];
+        if ((rc = upload(h, e.d_perm, p32.data(), p32.size()))) return rc;
+    }
     if ((rc = upload(h, e.d_lktag, e.tag_h.data(), e.tag_h.size()))) return rc;
     if ((rc = upload_coefficients(h))) return rc;
     for (auto& b : e.buf) {
@@ -1096,6 +1101,17 @@ int lbm_grad(lbm_t* h, double* dq, double* dwall_u, double* dg, double* ds) {
     return LBM_OK;
 }
 
+int lbm_grad_device(lbm_t* h, void* dq_dev, void* dwall_u_dev, double* dg, double* ds) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.have_grad) return fail(h, LBM_ESTATE, "run lbm_adjoint first");
+    if (dq_dev) HIPCHK(h, lbe::launch_links_to_caller(e, e.d_gq, (double*)dq_dev, 1));
+    if (dwall_u_dev)
+        HIPCHK(h, lbe::launch_links_to_caller(e, e.d_gphi, (double*)dwall_u_dev, e.D));
+    if (!dg && !ds) return LBM_OK;
+    return lbm_grad(h, nullptr, nullptr, dg, ds);
+}
+
 int lbm_get_adjoint(lbm_t* h, double* lam) {
     if (!h || !lam) return LBM_EINVAL;
     Engine& e = h->e;
@@ -1176,6 +1192,7 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_wact);
     free_dev(e.d_lkdir);
     free_dev(e.d_lknode);
+    free_dev(e.d_perm);
     free_dev(e.d_lktag);
     free_dev(e.d_lkcoef);
     free_dev(e.d_lkderiv);

@@ -60,6 +60,7 @@ struct Engine {
     int64_t n_wact = 0;                 // {id, kind | links << 2, first link, 0}
     uint8_t* d_lkdir = nullptr;
     int32_t* d_lknode = nullptr;
+    int32_t* d_perm = nullptr;          // sorted link k -> caller index
     int32_t* d_lktag = nullptr;
     LinkCoef* d_lkcoef = nullptr;
     LinkDeriv* d_lkderiv = nullptr;
@@ -163,6 +164,9 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& n
                                const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
+// per-link values (width doubles each) from the sorted order into the
+// caller's order, device to device
+hipError_t launch_links_to_caller(Engine& e, const double* in, double* out, int width);
 // Eq. (211) links: move c1 * (adjoint of f_i(x_f, t+1)) onto the adjoint of
 // f_ibar(x_f, t+1) and add the gamma-derivative of that term, using the
 // forward state at t+1 in `next`.

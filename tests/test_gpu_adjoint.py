@@ -187,7 +187,10 @@ def test_fp32_adjoint_is_close_to_fp64():
     sv32.close()
 
 
-def test_autograd_function_matches_adjoint():
+@pytest.mark.parametrize("dev", ["cpu", "cuda"])
+def test_autograd_function_matches_adjoint(dev):
+    """Leaves on the host take the host gradient path; leaves on the device
+    get the per-link gradients written on the device (lbm_grad_device)."""
     import torch
     from paper_1712_08288_amd import binding
     from paper_1712_08288_amd.autograd import Problem, objective
@@ -196,20 +199,43 @@ def test_autograd_function_matches_adjoint():
     sv = binding.solver_for(geom, s, l_rule=kw["l_rule"])
     prob = Problem(sv, steps=steps, every=4, objective="force_x", tag=1,
                    window=(obj.t0, obj.t1))
-    q = torch.tensor(geom.q, requires_grad=True)
-    wu = torch.tensor(geom.wall_u, requires_grad=True)
-    g = torch.zeros(2, dtype=torch.float64, requires_grad=True)
-    tau = torch.tensor(1.0 / s[7], dtype=torch.float64, requires_grad=True)
-    ss = torch.cat([torch.tensor(s[:7]), (1.0 / tau).reshape(1), (1.0 / tau).reshape(1)])
+    q = torch.tensor(geom.q, device=dev, requires_grad=True)
+    wu = torch.tensor(geom.wall_u, device=dev, requires_grad=True)
+    g = torch.zeros(2, dtype=torch.float64, device=dev, requires_grad=True)
+    tau = torch.tensor(1.0 / s[7], dtype=torch.float64, device=dev, requires_grad=True)
+    ss = torch.cat([torch.tensor(s[:7], device=dev), (1.0 / tau).reshape(1), (1.0 / tau).reshape(1)])
     J = objective(q, wu, g, ss, prob)
     J.backward()
     sv2, J2, gr = _gpu_grad(geom, s, kw, obj, steps, 4, np.zeros((9, geom.n_nodes)))
     assert float(J) == J2
-    assert np.array_equal(q.grad.numpy(), gr["q"])
+    assert q.grad.device.type == dev and wu.grad.device.type == dev
+    assert np.array_equal(q.grad.cpu().numpy(), gr["q"])
+    assert np.array_equal(wu.grad.cpu().numpy(), gr["wall_u"])
     dtau = -(gr["s"][7] + gr["s"][8]) / float(tau) ** 2
     assert np.isclose(float(tau.grad), dtau, rtol=1e-12)
     sv.close()
     sv2.close()
+
+
+def test_device_gradients_equal_host_gradients():
+    """lbm_grad_device puts the per-link gradients in the caller's order on
+    the device, bit for bit what lbm_grad returns on the host."""
+    import torch
+    name, mk_geom, mk_s, kw, obj, steps = [c for c in CASES if c[0] == "d3q19_meanux_channel_many_links"][0]
+    geom, s = mk_geom(), mk_s()
+    df0 = states.random_deviation(19, geom.n_nodes, seed=5, amp=1e-3)
+    sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, 3, df0)
+    nl = geom.n_links
+    dq = torch.full((nl,), float("nan"), dtype=torch.float64, device="cuda")
+    du = torch.full((nl, 3), float("nan"), dtype=torch.float64, device="cuda")
+    small = sv.grad_device(dq, du)
+    assert np.array_equal(dq.cpu().numpy(), gr["q"])
+    assert np.array_equal(du.cpu().numpy(), gr["wall_u"])
+    assert np.array_equal(small["g"], gr["g"]) and np.array_equal(small["s"], gr["s"])
+    assert np.abs(gr["wall_u"]).max() > 0 and np.abs(gr["q"]).max() > 0
+    only = sv.grad_device(dq=dq)       # host outputs still filled, wall_u skipped
+    assert np.array_equal(only["g"], gr["g"])
+    sv.close()
 
 
 @pytest.mark.parametrize("case", [CASES[0], CASES[4]], ids=[CASES[0][0], CASES[4][0]])
