@@ -94,6 +94,19 @@ def copy_ceiling(binding, torch, nbytes=1 << 31, reps=20, all_modes=False):
     return out
 
 
+def pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
+    """Rate of the step's own access pattern without its arithmetic (every
+    plane read at the pull source, written at the node; D3Q19 FP32), raw
+    bytes moved per second."""
+    n = int(np.prod(shape))
+    a = torch.empty(19 * n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    ms = binding.pull_pattern_copy("D3Q19", "fp32", b, a, shape, reps=reps)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 19 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(geom, w, slab=48, steps=20, threads=None):
     """Oracle on the z-slab 0 <= z < slab of the same workload (window mode:
     reads across the slab faces see NaN and are not used; slab=None runs the
@@ -527,6 +540,9 @@ def main():
     sv32.close()
 
     ceiling = copy_ceiling(binding, torch)
+    pattern = pattern_ceiling(binding, torch)
+    traffic = (MEASURED_TRAFFIC["bytes"]
+               if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"] else None)
     bytes32 = algorithmic_bytes(19, 4, N, NF, NL)
     bytes64 = algorithmic_bytes(19, 8, N, NF, NL)
     achieved = bytes32 / (kms32 * 1e-3) / 1e9
@@ -558,12 +574,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (MEASURED_TRAFFIC["bytes"]
-                        if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"]
-                        else None),
+            "traffic": traffic,
             "kernel": "k_step<D3Q19,float,pressure>",
             "copy_ceiling_GBps": ceiling["best_GBps"],
             "frac_of_copy_ceiling": round(achieved / ceiling["best_GBps"], 4),
+            # the same access pattern without the arithmetic, measured here;
+            # compared with the kernel's measured HBM bytes per second
+            "pattern_ceiling_GBps": round(pattern, 1),
+            "traffic_GBps": (round(traffic / (kms32 * 1e-3) / 1e9, 1) if traffic else None),
+            "frac_of_pattern_ceiling": round((traffic or bytes32) / (kms32 * 1e-3) / 1e9 / pattern, 4),
             "kernel_ms": round(kms32, 4),
             "repeats_kernel_ms": reps, "repeats_median_ms": float(np.median(reps)),
             "algorithmic_bytes": int(bytes32),

@@ -298,6 +298,21 @@ int lbm_last_step_ms(lbm_t *h, double *ms_per_step);
 int lbm_stream_copy(void *dst_dev, const void *src_dev, int64_t bytes,
                     int32_t mode, int32_t reps, double *ms_per_copy);
 
+/* The step kernel's access pattern without its arithmetic, as a ceiling for
+ * it: Q planes of nx*ny*nz elements (stride nx*ny*nz, x fastest, FP64 or FP32
+ * per `precision`) are read at the periodic pull source of each direction
+ * (x - e_i wrapped in every axis, the step's own addressing) and written at
+ * the node with non-temporal stores, one node per thread in 256-thread
+ * blocks.  Runs `reps` times after one warm-up on a private stream and
+ * reports the mean time per pass from HIP events (a pass moves
+ * 2 * Q * nx*ny*nz * element bytes).  src_dev and dst_dev are caller-owned
+ * device buffers of at least Q * nx*ny*nz elements that must not overlap.
+ * Errors: EINVAL (bad sizes or lattice; D2Q9 needs nz = 1; one plane must
+ * stay below 4 GiB), EDEVICE. */
+int lbm_pull_pattern_copy(int lattice, int precision, void *dst_dev, const void *src_dev,
+                          int64_t nx, int64_t ny, int64_t nz, int32_t reps,
+                          double *ms_per_copy);
+
 const char *lbm_last_error(const lbm_t *h);
 int lbm_destroy(lbm_t *h);
 

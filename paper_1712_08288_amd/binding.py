@@ -72,6 +72,7 @@ _counts = _sig("lbm_counts", _i, [_p, _p, _p])
 _set_timing = _sig("lbm_set_timing", _i, [_p, _i])
 _last_ms = _sig("lbm_last_step_ms", _i, [_p, _p])
 _stream_copy = _sig("lbm_stream_copy", _i, [_p, _p, _i64, _i32, _i32, _p])
+_pull_pattern = _sig("lbm_pull_pattern_copy", _i, [_i, _i, _p, _p, _i64, _i64, _i64, _i32, _p])
 _last_err = _sig("lbm_last_error", C.c_char_p, [_p])
 _destroy = _sig("lbm_destroy", _i, [_p])
 
@@ -84,7 +85,7 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_set_objective", "lbm_objective", "lbm_run_checkpointed",
             "lbm_adjoint", "lbm_adjoint_step", "lbm_adjoint_remaining", "lbm_set_rate_gradient", "lbm_grad", "lbm_grad_device", "lbm_get_adjoint", "lbm_set_stream",
             "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
-            "lbm_last_step_ms", "lbm_stream_copy", "lbm_last_error",
+            "lbm_last_step_ms", "lbm_stream_copy", "lbm_pull_pattern_copy", "lbm_last_error",
             "lbm_destroy"]
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q15": 2}
@@ -162,6 +163,21 @@ def stream_copy(dst, src, nbytes, mode=0, reps=10):
     rc = _stream_copy(_p(d), _p(s), int(nbytes), int(mode), int(reps), _ptr(ms))
     if rc:
         raise LBMError(rc, "stream_copy")
+    return float(ms[0])
+
+
+def pull_pattern_copy(lattice, precision, dst, src, shape, reps=10):
+    """Time the step's pull pattern without arithmetic on a periodic
+    nx x ny x nz grid (dst/src: torch tensors or device pointers of at least
+    Q * nx*ny*nz elements).  Returns ms per pass."""
+    d = dst.data_ptr() if hasattr(dst, "data_ptr") else int(dst)
+    s = src.data_ptr() if hasattr(src, "data_ptr") else int(src)
+    nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+    ms = np.zeros(1)
+    rc = _pull_pattern(LATTICES[lattice], PRECISIONS[precision], _p(d), _p(s), int(nx), int(ny),
+                       int(nz), int(reps), _ptr(ms))
+    if rc:
+        raise LBMError(rc, "pull_pattern_copy")
     return float(ms[0])
 
 

@@ -1,12 +1,34 @@
-// Streaming copy used as the practical HBM ceiling that the step kernels are
-// compared against (read `bytes`, write `bytes`).
+// Streaming copies used as practical HBM ceilings that the step kernels are
+// compared against: flat copies (read `bytes`, write `bytes`), and the step's
+// own access pattern without its arithmetic (every plane read at the pull
+// source of its direction, written at the node).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 #include "../../include/lbm.h"
+#include "kernels.hpp"
 
 namespace lbe {
+
+// The pull pattern of a periodic node launch: the same addressing (Pull),
+// block shape and non-temporal stores as the step kernel, no collision.
+template <class L, class T>
+__global__ void __launch_bounds__(BX)
+k_pull_pattern(const T* __restrict__ src, T* __restrict__ dst, Grid g) {
+    const NodePos pos = node_of_thread(g);
+    if (!pos.in) return;
+    const Pull<XBC_PERIODIC> pl(g, pos);
+    T v[L::Q];
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        v[i] = ld(src + (size_t)i * g.S, pl.template src<L, i>());
+    });
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        st_nt(dst + (size_t)i * g.S, pos.n, v[i]);
+    });
+}
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -73,6 +95,61 @@ extern "C" int lbm_stream_copy(void* dst, const void* src, int64_t bytes, int32_
     (void)hipEventRecord(e1, s);
     int rc = LBM_OK;
     if (hipEventSynchronize(e1) != hipSuccess) rc = LBM_EDEVICE;
+    float ms = 0.f;
+    if (rc == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LBM_EDEVICE;
+    if (ms_per_copy) *ms_per_copy = ms / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
+extern "C" int lbm_pull_pattern_copy(int lattice, int precision, void* dst, const void* src,
+                                     int64_t nx, int64_t ny, int64_t nz, int32_t reps,
+                                     double* ms_per_copy) {
+    if (!dst || !src || nx < 1 || ny < 1 || nz < 1 || reps < 1) return LBM_EINVAL;
+    if (lattice < 0 || lattice > 2 || (precision != LBM_FP64 && precision != LBM_FP32))
+        return LBM_EINVAL;
+    if (lattice == LBM_D2Q9 && nz != 1) return LBM_EINVAL;
+    const int64_t N = nx * ny * nz;
+    const int64_t elem = precision == LBM_FP64 ? 8 : 4;
+    if (N >= (1LL << 31) || N * elem >= (1LL << 32)) return LBM_EINVAL;
+    lbe::Grid g;
+    g.nx = (uint32_t)nx;
+    g.ny = (uint32_t)ny;
+    g.nz = (uint32_t)nz;
+    g.N = (uint32_t)N;
+    g.S = (uint32_t)N;
+    g.nblocks = (uint32_t)((N + lbe::BX - 1) / lbe::BX);
+    g.chunk = 0u;
+    g.bpr = 0u;
+    hipStream_t s;
+    hipEvent_t e0, e1;
+    if (hipStreamCreate(&s) != hipSuccess) return LBM_EDEVICE;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return LBM_EDEVICE;
+    }
+    auto launch = [&]() {
+        auto go = [&](auto lat) {
+            using L = decltype(lat);
+            if (precision == LBM_FP64)
+                hipLaunchKernelGGL((lbe::k_pull_pattern<L, double>), dim3(g.nblocks), dim3(lbe::BX),
+                                   0, s, (const double*)src, (double*)dst, g);
+            else
+                hipLaunchKernelGGL((lbe::k_pull_pattern<L, float>), dim3(g.nblocks), dim3(lbe::BX),
+                                   0, s, (const float*)src, (float*)dst, g);
+        };
+        if (lattice == LBM_D2Q9) go(lbe::D2Q9{});
+        else if (lattice == LBM_D3Q15) go(lbe::D3Q15{});
+        else go(lbe::D3Q19{});
+    };
+    launch();   // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) launch();
+    (void)hipEventRecord(e1, s);
+    int rc = LBM_OK;
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) rc = LBM_EDEVICE;
     float ms = 0.f;
     if (rc == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LBM_EDEVICE;
     if (ms_per_copy) *ms_per_copy = ms / reps;
