@@ -183,6 +183,18 @@ def all_configs(binding, torch):
     from workloads import analytic, configs
     out = {}
 
+    def pattern_rate(lattice, shape, prec, Q):
+        """Raw bytes per second of the step's pull pattern without arithmetic
+        on this grid and precision (the kernel's own ceiling)."""
+        n = int(np.prod(shape))
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        a = torch.ones(Q * n, dtype=dt, device="cuda")
+        b = torch.empty_like(a)
+        ms = binding.pull_pattern_copy(lattice, prec, b, a, shape, reps=10)
+        del a, b
+        torch.cuda.empty_cache()
+        return 2 * Q * n * (4 if prec == "fp32" else 8) / (ms * 1e-3) / 1e9
+
     def fwd(w, geom, prec, steps, warm=10, **kw):
         sv = binding.solver_for(geom, w.s, g=w.g, precision=prec, dp=w.dp,
                                 l_rule=w.l_rule, **kw)
@@ -192,9 +204,12 @@ def all_configs(binding, torch):
         Q = 9 if geom.lattice == "D2Q9" else 19
         by = algorithmic_bytes(Q, 4 if prec == "fp32" else 8, geom.n_nodes,
                                geom.n_fluid, geom.n_links)
+        pat = pattern_rate(geom.lattice, geom.shape, prec, Q)
         return sv, {"ms_per_step": round(ms, 5), "wall_ms_per_step": round(wall, 5),
                     "mlups": round(geom.n_nodes / (ms * 1e-3) / 1e6, 1),
-                    "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                    "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "pattern_ceiling_GBps": round(pat, 1),
+                    "algorithmic_frac_of_pattern": round(by / (ms * 1e-3) / 1e9 / pat, 4)}
 
     _progress("C1")
     # C1: circular Couette, FP64, refinement under diffusive scaling
