@@ -99,3 +99,55 @@ def test_c5_crop_96x64x64_parity(precision):
                                    l_rule=w.l_rule)
     assert rel_l2(got, want, fl) < (1e-12 if precision == "fp64" else 3e-6)
     sv.close()
+
+
+def test_c3_adjoint_matches_central_differences_at_full_size():
+    """The benchmark workload's reverse sweep (256^3 D3Q19, FP64, checkpointed
+    as bench.py runs it) against central differences of J along directions
+    in g, in all link fractions q at once and in all wall velocities at once:
+    directional derivatives hold at any size, so this checks the adjoint
+    kernels on the real grid, wave mix and link count.  The q and wall
+    directions are the gradients themselves (a strong, well-conditioned
+    signal); a wrong gradient pattern changes the directional derivative the
+    differences measure, so it still fails."""
+    from paper_1712_08288_amd import binding
+    w = configs.c3_spheres()
+    geom = w.geometry()
+    g0 = np.array([2e-6, 0.0, 0.0])
+    steps, every = 12, 4
+    sv = binding.solver_for(geom, w.s, g=g0, precision="fp64", dp=w.dp, l_rule=w.l_rule)
+    print("workload", w.name, "fp64 adjoint", geom.shape, "links", geom.n_links, flush=True)
+
+    def J_at(q=None, wall_u=None, g=None):
+        sv.update_links(q if q is not None else geom.q,
+                        wall_u if wall_u is not None else geom.wall_u)
+        sv.set_parameters(w.s, g if g is not None else g0)
+        sv.init()
+        sv.set_objective("mean_ux", 0, 0, steps)
+        sv.step(steps)
+        return sv.objective()
+
+    sv.init()
+    sv.set_objective("mean_ux", 0, 0, steps)
+    sv.run_checkpointed(steps, every)
+    J = sv.objective()
+    sv.adjoint()
+    gr = sv.grad()
+    assert abs(J - J_at()) <= 1e-14 * abs(J)
+    h = 1e-7
+    fd = (J_at(g=g0 + [h, 0, 0]) - J_at(g=g0 - [h, 0, 0])) / (2 * h)
+    print("dJ/dg_x", fd, gr["g"][0], flush=True)
+    assert abs(fd - gr["g"][0]) <= 1e-6 * abs(gr["g"][0]), (fd, gr["g"][0])
+    hq = 1e-6
+    dq = gr["q"] / np.abs(gr["q"]).max()
+    dq[(geom.q + hq * dq > 1.0) | (geom.q - hq * dq <= 0.0)] = 0.0
+    fd = (J_at(q=geom.q + hq * dq) - J_at(q=geom.q - hq * dq)) / (2 * hq)
+    want = float(gr["q"] @ dq)
+    print("dJ/dq along dq", fd, want, flush=True)
+    assert abs(fd - want) <= 1e-6 * abs(want), (fd, want)
+    du = gr["wall_u"] / np.abs(gr["wall_u"]).max()
+    fd = (J_at(wall_u=geom.wall_u + hq * du) - J_at(wall_u=geom.wall_u - hq * du)) / (2 * hq)
+    want = float((gr["wall_u"] * du).sum())
+    print("dJ/dwall_u along du", fd, want, flush=True)
+    assert abs(fd - want) <= 1e-6 * abs(want), (fd, want)
+    sv.close()
