@@ -151,3 +151,21 @@ def test_c3_adjoint_matches_central_differences_at_full_size():
     print("dJ/dwall_u along du", fd, want, flush=True)
     assert abs(fd - want) <= 1e-6 * abs(want), (fd, want)
     sv.close()
+    # the FP32 path bench.py times, against these FP64 gradients
+    sv32 = binding.solver_for(geom, w.s, g=g0, precision="fp32", dp=w.dp, l_rule=w.l_rule)
+    sv32.set_rate_gradient(False)
+    sv32.init()
+    sv32.set_objective("mean_ux", 0, 0, steps)
+    sv32.run_checkpointed(steps, every)
+    J32 = sv32.objective()
+    sv32.adjoint()
+    g32 = sv32.grad()
+    print("fp32 vs fp64: J", abs(J32 - J) / abs(J), "dJ/dg",
+          np.abs(g32["g"] - gr["g"]).max() / np.abs(gr["g"]).max(), flush=True)
+    assert abs(J32 - J) <= 1e-4 * abs(J)
+    for key in ("q", "wall_u", "g"):
+        scale = np.abs(gr[key]).max()
+        err = np.abs(g32[key] - gr[key]).max() / scale
+        print("fp32 vs fp64", key, err, flush=True)
+        assert err <= 1e-3, key
+    sv32.close()
