@@ -107,6 +107,20 @@ def pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
     return 2 * 19 * n * 4 / (ms * 1e-3) / 1e9
 
 
+def adjoint_pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
+    """Rate of the adjoint step's access pattern without its arithmetic (the
+    forward state pulled, the adjoint gathered from x + e_i, the result
+    written; D3Q19 FP32), raw bytes moved per second."""
+    n = int(np.prod(shape))
+    a = torch.empty(19 * n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a).fill_(2.0)
+    c = torch.empty_like(a)
+    ms = binding.adjoint_pattern_copy("D3Q19", "fp32", c, a, b, shape, reps=reps)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 3 * 19 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(geom, w, slab=48, steps=20, threads=None):
     """Oracle on the z-slab 0 <= z < slab of the same workload (window mode:
     reads across the slab faces see NaN and are not used; slab=None runs the
@@ -556,6 +570,7 @@ def main():
 
     ceiling = copy_ceiling(binding, torch)
     pattern = pattern_ceiling(binding, torch)
+    adj_pattern = adjoint_pattern_ceiling(binding, torch)
     traffic = (MEASURED_TRAFFIC["bytes"]
                if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"] else None)
     bytes32 = algorithmic_bytes(19, 4, N, NF, NL)
@@ -617,6 +632,9 @@ def main():
             "ms_per_step_reverse": round(ms_adj, 4),
             "fwd_adjoint_mlups": round(N / ((ms_fwd_ckpt + ms_adj) * 1e-3) / 1e6, 1),
             "adjoint_over_forward_cost": round((ms_fwd_ckpt + ms_adj) / ms32, 3),
+            # the adjoint's access pattern without arithmetic, raw bytes
+            # per second (the adjoint kernels' own ceiling)
+            "pattern_ceiling_GBps": round(adj_pattern, 1),
             "every_step_kept": {
                 "ms_per_step_forward": round(ms_fwd_all, 4),
                 "ms_per_step_reverse": round(ms_adj_all, 4),

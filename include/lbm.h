@@ -313,6 +313,16 @@ int lbm_pull_pattern_copy(int lattice, int precision, void *dst_dev, const void 
                           int64_t nx, int64_t ny, int64_t nz, int32_t reps,
                           double *ms_per_copy);
 
+/* The adjoint step's access pattern without its arithmetic, as above with
+ * a second source: plane i of f_src is read at the pull source x - e_i, plane
+ * i of lam_src at x + e_i (the node that pulls from x), and their sum is
+ * written at x (a pass moves 3 * Q * nx*ny*nz * element bytes).  The three
+ * buffers are caller-owned device memory of at least Q * nx*ny*nz elements;
+ * dst_dev must not overlap either source.  Errors as above. */
+int lbm_adjoint_pattern_copy(int lattice, int precision, void *dst_dev, const void *f_src_dev,
+                             const void *lam_src_dev, int64_t nx, int64_t ny, int64_t nz,
+                             int32_t reps, double *ms_per_copy);
+
 const char *lbm_last_error(const lbm_t *h);
 int lbm_destroy(lbm_t *h);
 

@@ -73,6 +73,7 @@ _set_timing = _sig("lbm_set_timing", _i, [_p, _i])
 _last_ms = _sig("lbm_last_step_ms", _i, [_p, _p])
 _stream_copy = _sig("lbm_stream_copy", _i, [_p, _p, _i64, _i32, _i32, _p])
 _pull_pattern = _sig("lbm_pull_pattern_copy", _i, [_i, _i, _p, _p, _i64, _i64, _i64, _i32, _p])
+_adj_pattern = _sig("lbm_adjoint_pattern_copy", _i, [_i, _i, _p, _p, _p, _i64, _i64, _i64, _i32, _p])
 _last_err = _sig("lbm_last_error", C.c_char_p, [_p])
 _destroy = _sig("lbm_destroy", _i, [_p])
 
@@ -85,7 +86,7 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_set_objective", "lbm_objective", "lbm_run_checkpointed",
             "lbm_adjoint", "lbm_adjoint_step", "lbm_adjoint_remaining", "lbm_set_rate_gradient", "lbm_grad", "lbm_grad_device", "lbm_get_adjoint", "lbm_set_stream",
             "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
-            "lbm_last_step_ms", "lbm_stream_copy", "lbm_pull_pattern_copy", "lbm_last_error",
+            "lbm_last_step_ms", "lbm_stream_copy", "lbm_pull_pattern_copy", "lbm_adjoint_pattern_copy", "lbm_last_error",
             "lbm_destroy"]
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q15": 2}
@@ -178,6 +179,20 @@ def pull_pattern_copy(lattice, precision, dst, src, shape, reps=10):
                        int(nz), int(reps), _ptr(ms))
     if rc:
         raise LBMError(rc, "pull_pattern_copy")
+    return float(ms[0])
+
+
+def adjoint_pattern_copy(lattice, precision, dst, f_src, lam_src, shape, reps=10):
+    """Time the adjoint step's access pattern without arithmetic (f read at
+    x - e_i, lambda at x + e_i, their sum written at x).  Returns ms per
+    pass."""
+    ptr = [t.data_ptr() if hasattr(t, "data_ptr") else int(t) for t in (dst, f_src, lam_src)]
+    nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+    ms = np.zeros(1)
+    rc = _adj_pattern(LATTICES[lattice], PRECISIONS[precision], _p(ptr[0]), _p(ptr[1]), _p(ptr[2]),
+                      int(nx), int(ny), int(nz), int(reps), _ptr(ms))
+    if rc:
+        raise LBMError(rc, "adjoint_pattern_copy")
     return float(ms[0])
 
 

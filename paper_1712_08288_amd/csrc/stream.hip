@@ -60,6 +60,32 @@ k_copy_flat(const v4f* __restrict__ src, v4f* __restrict__ dst, uint64_t n) {
     else dst[i] = src[i];
 }
 
+// The adjoint step's access pattern without its arithmetic: the forward
+// state read at the pull source of each direction, the adjoint read at the
+// node that pulls from this one (x + e_i), the result written at the node.
+template <class L, class T>
+__global__ void __launch_bounds__(BX)
+k_adjoint_pattern(const T* __restrict__ fsrc, const T* __restrict__ lsrc, T* __restrict__ dst,
+                  Grid g) {
+    const NodePos pos = node_of_thread(g);
+    if (!pos.in) return;
+    const Pull<XBC_PERIODIC> pl(g, pos);
+    T f[L::Q], lg[L::Q];
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        f[i] = ld(fsrc + (size_t)i * g.S, pl.template src<L, i>());
+    });
+    // x + e_i is the pull source of the opposite direction
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        lg[i] = ld(lsrc + (size_t)i * g.S, pl.template src<L, TAB<L>.opp[i]>());
+    });
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        st_nt(dst + (size_t)i * g.S, pos.n, f[i] + lg[i]);
+    });
+}
+
 }  // namespace lbe
 
 extern "C" int lbm_stream_copy(void* dst, const void* src, int64_t bytes, int32_t mode,
@@ -104,9 +130,10 @@ extern "C" int lbm_stream_copy(void* dst, const void* src, int64_t bytes, int32_
     return rc;
 }
 
-extern "C" int lbm_pull_pattern_copy(int lattice, int precision, void* dst, const void* src,
-                                     int64_t nx, int64_t ny, int64_t nz, int32_t reps,
-                                     double* ms_per_copy) {
+namespace {
+
+int pattern_copy(int lattice, int precision, void* dst, const void* src, const void* src2,
+                 int64_t nx, int64_t ny, int64_t nz, int32_t reps, double* ms_per_copy) {
     if (!dst || !src || nx < 1 || ny < 1 || nz < 1 || reps < 1) return LBM_EINVAL;
     if (lattice < 0 || lattice > 2 || (precision != LBM_FP64 && precision != LBM_FP32))
         return LBM_EINVAL;
@@ -133,12 +160,18 @@ extern "C" int lbm_pull_pattern_copy(int lattice, int precision, void* dst, cons
     auto launch = [&]() {
         auto go = [&](auto lat) {
             using L = decltype(lat);
-            if (precision == LBM_FP64)
-                hipLaunchKernelGGL((lbe::k_pull_pattern<L, double>), dim3(g.nblocks), dim3(lbe::BX),
-                                   0, s, (const double*)src, (double*)dst, g);
-            else
-                hipLaunchKernelGGL((lbe::k_pull_pattern<L, float>), dim3(g.nblocks), dim3(lbe::BX),
-                                   0, s, (const float*)src, (float*)dst, g);
+            auto typed = [&](auto zero) {
+                using T = decltype(zero);
+                if (src2)
+                    hipLaunchKernelGGL((lbe::k_adjoint_pattern<L, T>), dim3(g.nblocks),
+                                       dim3(lbe::BX), 0, s, (const T*)src, (const T*)src2,
+                                       (T*)dst, g);
+                else
+                    hipLaunchKernelGGL((lbe::k_pull_pattern<L, T>), dim3(g.nblocks),
+                                       dim3(lbe::BX), 0, s, (const T*)src, (T*)dst, g);
+            };
+            if (precision == LBM_FP64) typed(0.0);
+            else typed(0.0f);
         };
         if (lattice == LBM_D2Q9) go(lbe::D2Q9{});
         else if (lattice == LBM_D3Q15) go(lbe::D3Q15{});
@@ -157,4 +190,19 @@ extern "C" int lbm_pull_pattern_copy(int lattice, int precision, void* dst, cons
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(s);
     return rc;
+}
+
+}  // namespace
+
+extern "C" int lbm_pull_pattern_copy(int lattice, int precision, void* dst, const void* src,
+                                     int64_t nx, int64_t ny, int64_t nz, int32_t reps,
+                                     double* ms_per_copy) {
+    return pattern_copy(lattice, precision, dst, src, nullptr, nx, ny, nz, reps, ms_per_copy);
+}
+
+extern "C" int lbm_adjoint_pattern_copy(int lattice, int precision, void* dst, const void* f_src,
+                                        const void* lam_src, int64_t nx, int64_t ny, int64_t nz,
+                                        int32_t reps, double* ms_per_copy) {
+    if (!lam_src) return LBM_EINVAL;
+    return pattern_copy(lattice, precision, dst, f_src, lam_src, nx, ny, nz, reps, ms_per_copy);
 }

@@ -41,6 +41,33 @@ def test_pull_pattern_copy_is_the_periodic_pull(lattice, shape, precision):
         assert np.array_equal(got[i], want), i
 
 
+@pytest.mark.parametrize("lattice,shape,precision", [
+    ("D3Q19", (11, 6, 5), "fp32"), ("D2Q9", (7, 9, 1), "fp64")])
+def test_adjoint_pattern_copy_reads_pull_and_push_sources(lattice, shape, precision):
+    import torch
+    from paper_1712_08288_amd import binding
+    e, _, _ = binding.lattice_info(lattice)
+    Q = e.shape[0]
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    rng = np.random.default_rng(8)
+    f_h = rng.standard_normal((Q, n))
+    l_h = rng.standard_normal((Q, n))
+    f = torch.tensor(f_h, dtype=dt, device="cuda").contiguous()
+    lam = torch.tensor(l_h, dtype=dt, device="cuda").contiguous()
+    dst = torch.full_like(f, float("nan"))
+    assert binding.adjoint_pattern_copy(lattice, precision, dst, f, lam, shape, reps=2) > 0
+    got = dst.cpu()
+    f3 = f.cpu().reshape(Q, nz, ny, nx)
+    l3 = lam.cpu().reshape(Q, nz, ny, nx)
+    for i in range(Q):
+        ex = int(e[i, 0]); ey = int(e[i, 1]); ez = int(e[i, 2]) if e.shape[1] == 3 else 0
+        pulled = torch.roll(f3[i], shifts=(ez, ey, ex), dims=(0, 1, 2))
+        pushed = torch.roll(l3[i], shifts=(-ez, -ey, -ex), dims=(0, 1, 2))
+        assert torch.equal(got[i], (pulled + pushed).reshape(n)), i
+
+
 def test_pull_pattern_copy_rejects_bad_sizes():
     import torch
     from paper_1712_08288_amd import binding
