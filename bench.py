@@ -464,7 +464,7 @@ def main():
                     help="run one of the paper's Section 3 sweeps on the GPU instead")
     ap.add_argument("--all", action="store_true",
                     help="also measure every workload (C1-C5) into 'per_config'")
-    ap.add_argument("--only", choices=["fwd32", "fwd64", "adjoint32", "copy"],
+    ap.add_argument("--only", choices=["fwd32", "fwd64", "adjoint32", "copy", "pattern"],
                     help="profiling runs: time only this part and print its line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -486,6 +486,11 @@ def main():
     if args.only == "copy":
         # reference copies of known size: HBM ceiling and counter scaling
         print(json.dumps(copy_ceiling(binding, torch, reps=args.steps, all_modes=True)))
+        return
+    if args.only == "pattern":
+        # the step's and the adjoint's access patterns without arithmetic
+        print(json.dumps({"pull_pattern_GBps": round(pattern_ceiling(binding, torch, reps=args.steps), 1),
+                          "adjoint_pattern_GBps": round(adjoint_pattern_ceiling(binding, torch, reps=args.steps), 1)}))
         return
 
     w = configs.c3_spheres(args.n)
