@@ -13,7 +13,8 @@
 // and J_ij = d f^eq_i / d f_j = w_i [1 + (3 e_i + 9 (e_i.u) e_i - 3 u).e_j]
 // (derivative of Eq. (42)), so that (J^T v)_j = a + b.e_j with
 // a = sum_i w_i v_i and b = sum_i w_i v_i (3 e_i + 9 (e_i.u) e_i - 3 u).
-// Gradients accumulated on the way, in double:
+// Gradients accumulated on the way, in double (the per-link ones in a
+// kernel over the links, the others in per-block sums of the node kernel):
 //   dJ/dgamma_k += a_k (dc1 f_ibar + dc2 g_i + dc3 g_ibar + dwall),
 //   dJ/dphi_k   += a_k c4 3 w_i rho0 e_i,
 //   dJ/dg       += sum_i mu_i 3 w_i rho0 e_i,
@@ -218,12 +219,13 @@ __device__ __forceinline__ NodePos node_of_wave(const Grid& g, const WaveList& w
 }
 
 // One launch covers the non-idle waves in memory order.  Plain and mixed
-// waves take separate paths from the start.  Mixed waves handle their cut links cooperatively (see LinkStage): the
-// link lanes read the link data and a_k = lambda_i(y, t+1) (plus the drag
-// term) with coalesced loads and hand c2 a_k, c3 a_k (+ drag), c0 a_k and
-// c1 a_k to the node's lane through LDS; the node's lane hands back
-// f_ibar(y, t), which the link lanes stage for the link-gradient kernel
-// together with a_k and the forward step's stored f'_i(y, t), f'_ibar(y, t).
+// waves take separate paths from the start.  Mixed waves handle their cut
+// links cooperatively (see LinkStage): the link lanes read the link data
+// and a_k = lambda_i(y, t+1) (plus the drag term) with coalesced loads and
+// hand c2 a_k, c3 a_k (+ drag), c0 a_k and c1 a_k to the node's lane
+// through LDS; the node's lane hands back f_ibar(y, t), which the link
+// lanes stage for the link-gradient kernel together with a_k and the
+// forward step's stored f'_i(y, t), f'_ibar(y, t).
 template <class L, class T, int XB, bool WANT_DS, bool ROWS>
 __global__ void __launch_bounds__(BX)
 k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict__ nxt,
