@@ -80,6 +80,9 @@ CASES = [
     ("d3q19_meanux_channel_many_links", _moving_channel,
      lambda: configs.d3q19_rates(0.8), dict(g=(1e-5, 0, 2e-6), l_rule="gamma2", b=0.95),
      Objective("mean_ux", t0=1, t1=7), 7),
+    ("d3q19_meanux_no_links", lambda: G.build("D3Q19", (24, 10, 6)),
+     lambda: configs.d3q19_rates(0.75), dict(g=(3e-5, -1e-5, 2e-5)),
+     Objective("mean_ux", t0=0, t1=6), 6),
     ("d3q15_drag_periodic_two_node", lambda: G.random_spheres(18, 15, 13, 2, 2.4, 3.6, seed=11,
                                                               lattice="D3Q15"),
      lambda: configs.d3q15_paper_rates(1.1), dict(g=(3e-5, 0, 0), l_rule="1.5gamma", b=0.95,
@@ -107,10 +110,15 @@ def test_adjoint_matches_oracle_reverse(case):
     fl = geom.solid == 0
     for key in ("q", "wall_u", "g"):
         a, b = gr[key], r[key]
+        assert a.shape == b.shape, key
+        if b.size == 0:      # no cut links
+            continue
         scale = max(np.abs(b).max(), 1e-300)
         assert np.abs(a - b).max() <= 1e-10 * scale, (key, np.abs(a - b).max(), scale)
+    # dJ/ds is exactly zero when no wall breaks the momentum balance (the
+    # case without links): an absolute floor far below any real gradient
     ds_scale = np.abs(r["s"]).max()
-    assert np.abs(gr["s"] - r["s"]).max() <= 1e-10 * ds_scale
+    assert np.abs(gr["s"] - r["s"]).max() <= 1e-10 * ds_scale + 1e-18
     lam_scale = np.abs(r["lam0"][:, fl]).max()
     assert np.abs(gr["lam0"][:, fl] - r["lam0"][:, fl]).max() <= 1e-10 * lam_scale
     sv.close()
