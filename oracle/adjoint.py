@@ -14,6 +14,9 @@ Its reverse, for lambda(t+1) = dJ/df(., t+1):
 * the collision's Jacobian, per node, is I - M^{-1} S M (I - J_eq) with
   J_eq the derivative of Eq. (42) (formed densely here), applied transposed.
 
+Objectives: the drag (momentum-exchange force), the mean velocity and the
+pressure drop between two cross-sections.
+
 Gradients: of the coefficients of Eq. (213) through gamma (l follows the
 rule), of the wall velocity phi (of phi(x_b, 0) when the wall data decay as
 phi(0) * wall_decay**t), of the body force g and of the relaxation rates s.  Pinned by complex-step differentiation of the forward oracle
@@ -30,13 +33,31 @@ from .lbm import Oracle
 class Objective:
     """J = sum over steps t in [t0, t1) of j(t) / (t1 - t0), with
     kind "force_x": x momentum-exchange force on `tag` during step t -> t+1,
-    kind "mean_ux": mean u_x over fluid nodes of f(t)."""
+    kind "mean_ux": mean u_x over fluid nodes of f(t),
+    kind "pressure_drop": p_in - p_out of f(t), where p = c_s^2 rho (the
+    pressure of the incompressible model, c_s^2 = 1/3 in lattice units) and
+    p_in, p_out are its means over the fluid nodes of the planes x = x_in and
+    x = x_out (planes = (x_in, x_out); negative values count from nx)."""
 
-    def __init__(self, kind, tag=0, t0=0, t1=1):
+    def __init__(self, kind, tag=0, t0=0, t1=1, planes=(0, -1)):
         self.kind, self.tag, self.t0, self.t1 = kind, tag, t0, t1
+        self.planes = planes
 
     def weight(self, t):
         return 1.0 / (self.t1 - self.t0) if self.t0 <= t < self.t1 else 0.0
+
+    def plane_weights(self, o):
+        """Per-node weights a(x) with p_in - p_out = c_s^2 sum_x a(x) rho(x):
+        1/n_in on the fluid nodes of x_in, -1/n_out on those of x_out."""
+        nx = o.shape[0]
+        x = o.nodes % nx
+        a = np.zeros(o.N)
+        for xp, sign in zip(self.planes, (1.0, -1.0)):
+            sel = (x == xp % nx) & o.fluid
+            if not sel.any():
+                raise ValueError("plane x = %d has no fluid node" % (xp % nx))
+            a[sel] += sign / sel.sum()
+        return a
 
     def value(self, o, t, f, fp, fn):
         w = self.weight(t)
@@ -45,6 +66,10 @@ class Objective:
         if self.kind == "force_x":
             nt = max(int(o.lk_tag.max()) + 1 if len(o.lk_tag) else 0, self.tag + 1)
             return w * o.force(fp, fn, n_tags=nt)[self.tag, 0]
+        if self.kind == "pressure_drop":
+            a = self.plane_weights(o)
+            rho = o.density_deviation(f)
+            return w * (a[o.fluid] * rho[o.fluid]).sum() / 3.0
         u = o.velocity(f)
         return w * u[0, o.fluid].sum() / o.fluid.sum()
 
@@ -147,6 +172,8 @@ def reverse(o, states, obj, rule=None):
         lam = _collision_jacobian_T(o, fz, muf) + direct
         if wt and obj.kind == "mean_ux":
             lam += (wt * o.e[:, 0] / (o.rho0 * n_f))[:, None]
+        if wt and obj.kind == "pressure_drop":
+            lam += (wt / 3.0) * obj.plane_weights(o)[None, :]
         lam[:, ~fluid] = 0.0
     return dict(lam0=lam, q=gq, wall_u=gphi, g=gg, s=gs)
 

@@ -128,3 +128,66 @@ def test_decaying_wall_data_gradient():
     obj = Objective("force_x", tag=1, t0=1, t1=7)
     _check(geom, configs.d2q9_rates(0.7),
            dict(g=(1e-4, 0, 0), l_rule="gamma2", wall_decay=0.93), obj, 7, n_q=10)
+
+
+# ----------------------------------------------------------------------------
+# pressure drop between two cross-sections
+
+
+def test_pressure_drop_value_is_the_plane_density_difference():
+    """J at t = 0 of f = f^eq(rho, u): c_s^2 times the difference of the
+    prescribed rho averaged over the fluid nodes of the two planes."""
+    geom = G.random_spheres(12, 9, 8, 2, 2.0, 3.0, seed=11, x_bc="pressure")
+    rng = np.random.default_rng(3)
+    rho = 1.0 + rng.uniform(-1e-2, 1e-2, geom.n_nodes)
+    u = rng.uniform(-1e-2, 1e-2, (geom.n_nodes, 3))
+    x = np.arange(geom.n_nodes) % 12
+    fl = geom.solid == 0
+    for planes in [(0, -1), (3, 8), (7, 2)]:
+        o = Oracle(geom, configs.d3q19_rates(0.7), dp=1e-3)
+        obj = Objective("pressure_drop", t0=0, t1=1, planes=planes)
+        J, _ = forward(o, o.init_equilibrium(rho=rho, u=u), 1, obj)
+        a, b = planes[0] % 12, planes[1] % 12
+        assert (fl & (x == a)).sum() < (x == a).sum() or (fl & (x == b)).sum() < (x == b).sum()
+        want = (rho[fl & (x == a)].mean() - rho[fl & (x == b)].mean()) / 3.0
+        assert abs(J - want) <= 1e-15, (planes, J, want)
+
+
+def test_pressure_drop_of_the_seam_driven_channel_is_linear():
+    """Steady channel flow driven by a seam jump drho: the pressure falls
+    linearly by c_s^2 drho over one period, so between planes a < b the drop
+    is c_s^2 drho (b - a) / nx."""
+    nx, ny_mesh, drho = 8, 10, 2e-4
+    geom = G.build("D2Q9", (nx, ny_mesh + 1, 1),
+                   planes=[G.PlaneWall(1, -1, 0, 0.5), G.PlaneWall(1, +1, ny_mesh, ny_mesh - 0.5)],
+                   x_bc="pressure")
+    o = Oracle(geom, configs.d2q9_rates(0.8), dp=drho, l_rule="min")
+    f = o.run(o.init_equilibrium(), 4000)
+    for a, b in [(0, nx - 1), (2, 5), (1, 7)]:
+        obj = Objective("pressure_drop", t0=0, t1=1, planes=(a, b))
+        J = obj.value(o, 0, f, None, None)
+        want = drho * (b - a) / nx / 3.0
+        assert abs(J - want) < 1e-9 * want, (a, b, J, want)
+
+
+def test_pressure_drop_gradient_d3q19_seam():
+    geom = G.random_spheres(10, 8, 7, 1, 1.8, 2.4, seed=4, x_bc="pressure")
+    obj = Objective("pressure_drop", t0=1, t1=6, planes=(2, 7))
+    _check(geom, configs.d3q19_rates(0.65), dict(g=(2e-5, 0, 1e-5), dp=1e-3, l_rule="gamma2"),
+           obj, 6, n_q=8)
+
+
+def test_pressure_drop_gradient_outflow_channel():
+    geom = G.channel_cylinder(24, 13, 2.7, (9.3, 6.4), 0.04)
+    obj = Objective("pressure_drop", t0=0, t1=7, planes=(3, -1))
+    _check(geom, configs.d2q9_rates(0.6), dict(l_rule="gamma2+gamma"), obj, 7, n_q=10)
+
+
+def test_pressure_drop_gradient_two_node_periodic():
+    geom = G.random_cylinders(22, 17, 2, 2.4, 3.6, seed=6)
+    wu = np.zeros_like(geom.wall_u)
+    wu[:, 0] = 0.02
+    geom = geom.with_wall_u(wu)
+    obj = Objective("pressure_drop", t0=2, t1=7, planes=(1, 12))
+    _check(geom, configs.d2q9_rates(0.7), dict(g=(1e-4, 2e-5, 0), l_rule="gamma", two_node=True),
+           obj, 7, n_q=12)
