@@ -85,8 +85,12 @@ enum { LBM_X_PERIODIC = 0, LBM_X_PRESSURE = 1, LBM_X_OUTFLOW = 2 };
  * FORCE_X: x component of the momentum-exchange force on the links with the
  *   given tag during step t -> t+1,
  *   sum_links (e_ibar)_x (f'_ibar(x_f,t) + f_i(x_f,t+1));
- * MEAN_UX: mean of u_x(x,t) over the fluid nodes. */
-enum { LBM_OBJ_NONE = 0, LBM_OBJ_FORCE_X = 1, LBM_OBJ_MEAN_UX = 2 };
+ * MEAN_UX: mean of u_x(x,t) over the fluid nodes;
+ * PRESSURE_DROP: p_in(t) - p_out(t), p = c_s^2 rho = rho / 3 the pressure of
+ *   the incompressible model (Eq. (42) and the pressure of Section 3.2),
+ *   p_in and p_out its means over the fluid nodes of the cross-sections
+ *   x = x_in and x = x_out (lbm_set_objective_planes; default 0 and nx-1). */
+enum { LBM_OBJ_NONE = 0, LBM_OBJ_FORCE_X = 1, LBM_OBJ_MEAN_UX = 2, LBM_OBJ_PRESSURE_DROP = 3 };
 
 /* Create a solver.  s: Q relaxation rates in the row order of the lattice's
  * moment matrix (rows for conserved moments -- density and momentum -- are
@@ -203,6 +207,17 @@ int lbm_set_state(lbm_t *h, const void *src_dev, int64_t time);
  * whose steps fall in [t_begin, t_end). */
 int lbm_set_objective(lbm_t *h, int kind, int32_t tag, int64_t t_begin,
                       int64_t t_end);
+
+/* Cross-sections x = x_in and x = x_out (0 <= x < nx) of the PRESSURE_DROP
+ * objective; read by the next lbm_set_objective(), which fails with EINVAL
+ * when either plane has no fluid node.  Errors: EINVAL. */
+int lbm_set_objective_planes(lbm_t *h, int64_t x_in, int64_t x_out);
+
+/* Pressure drop at the current time t, from f(x,t): *dp = p_in - p_out with
+ * p = rho / 3 averaged over the fluid nodes of the planes x = x_in and
+ * x = x_out, summed in double.  Errors: EINVAL (plane outside [0, nx) or
+ * without fluid), ESTATE, ENONFINITE.  Synchronises. */
+int lbm_pressure_drop(lbm_t *h, int64_t x_in, int64_t x_out, double *dp);
 
 /* Value of the objective accumulated so far.  Synchronises. */
 int lbm_objective(lbm_t *h, double *J);

@@ -24,9 +24,10 @@ class Problem:
     solver: object                      # binding.Solver with its geometry set
     steps: int
     every: int
-    objective: str = "force_x"          # "force_x" or "mean_ux"
+    objective: str = "force_x"          # "force_x", "mean_ux" or "pressure_drop"
     tag: int = 0
     window: tuple = (0, 1)              # [t_begin, t_end)
+    planes: Optional[tuple] = None      # (x_in, x_out) of "pressure_drop"
     init: Optional[Callable] = None     # init(solver); default: rest state
     last_J: float = field(default=float("nan"))
 
@@ -45,7 +46,7 @@ class LBMObjective(torch.autograd.Function):
             sv.init()
         else:
             problem.init(sv)
-        sv.set_objective(problem.objective, problem.tag, *problem.window)
+        sv.set_objective(problem.objective, problem.tag, *problem.window, planes=problem.planes)
         sv.run_checkpointed(problem.steps, problem.every)
         J = sv.objective()
         problem.last_J = J

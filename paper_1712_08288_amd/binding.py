@@ -60,6 +60,8 @@ _get_state = _sig("lbm_get_state", _i, [_p, _p])
 _set_state = _sig("lbm_set_state", _i, [_p, _p, _i64])
 _set_obj = _sig("lbm_set_objective", _i, [_p, _i, _i32, _i64, _i64])
 _objective = _sig("lbm_objective", _i, [_p, _p])
+_set_obj_planes = _sig("lbm_set_objective_planes", _i, [_p, _i64, _i64])
+_pressure_drop = _sig("lbm_pressure_drop", _i, [_p, _i64, _i64, _p])
 _run_ckpt = _sig("lbm_run_checkpointed", _i, [_p, _i64, _i64])
 _adjoint = _sig("lbm_adjoint", _i, [_p])
 _grad = _sig("lbm_grad", _i, [_p, _p, _p, _p, _p])
@@ -83,7 +85,8 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_init_deviation", "lbm_step", "lbm_time", "lbm_moments",
             "lbm_get_distribution", "lbm_reduce", "lbm_force",
             "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
-            "lbm_set_objective", "lbm_objective", "lbm_run_checkpointed",
+            "lbm_set_objective", "lbm_set_objective_planes", "lbm_pressure_drop",
+            "lbm_objective", "lbm_run_checkpointed",
             "lbm_adjoint", "lbm_adjoint_step", "lbm_adjoint_remaining", "lbm_set_rate_gradient", "lbm_grad", "lbm_grad_device", "lbm_get_adjoint", "lbm_set_stream",
             "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
             "lbm_last_step_ms", "lbm_stream_copy", "lbm_pull_pattern_copy", "lbm_adjoint_pattern_copy", "lbm_last_error",
@@ -94,7 +97,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1}
 RULES = {"gamma": 0, "1.5gamma": 1, "2gamma": 2, "gamma2": 3,
          "gamma2+gamma": 4, "zero": 5, "min": 6}
 X_BC = {"periodic": 0, "pressure": 1, "outflow": 2}
-OBJECTIVES = {"none": 0, "force_x": 1, "mean_ux": 2}
+OBJECTIVES = {"none": 0, "force_x": 1, "mean_ux": 2, "pressure_drop": 3}
 ERRORS = {-1: "EINVAL", -2: "EGEOM", -3: "ESTATE", -4: "ENOMEM",
           -5: "EDEVICE", -6: "ENONFINITE"}
 
@@ -338,9 +341,24 @@ class Solver:
         self._chk(_set_stream(self._h, _p(ptr) if ptr else None), "set_stream")
 
     # -- objective and adjoint
-    def set_objective(self, kind, tag=0, t_begin=0, t_end=1):
+    def set_objective(self, kind, tag=0, t_begin=0, t_end=1, planes=None):
+        """planes = (x_in, x_out) for "pressure_drop" (negative values count
+        from nx; default (0, nx - 1))."""
+        if planes is not None:
+            nx = self.shape[0]
+            self._chk(_set_obj_planes(self._h, int(planes[0]) % nx, int(planes[1]) % nx),
+                      "set_objective_planes")
         self._chk(_set_obj(self._h, OBJECTIVES[kind], int(tag), int(t_begin),
                            int(t_end)), "set_objective")
+
+    def pressure_drop(self, x_in=0, x_out=-1):
+        """p_in - p_out (p = rho / 3, plane means over fluid nodes) at the
+        current time."""
+        nx = self.shape[0]
+        dp = np.zeros(1)
+        self._chk(_pressure_drop(self._h, int(x_in) % nx, int(x_out) % nx, _ptr(dp)),
+                  "pressure_drop")
+        return float(dp[0])
 
     def objective(self):
         J = np.zeros(1)

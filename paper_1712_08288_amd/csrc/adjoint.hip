@@ -66,6 +66,10 @@ struct AdjArgs {
     double w_force;      // weight of this step's drag term (0 outside window)
     double w_ux;         // weight of d(mean u_x)/df_j = e_jx * w_ux
     int want_ds;
+    // pressure drop: dJ/df_j(x) = a_in [x = x_in] - a_out [x = x_out] for
+    // every j at fluid nodes (a_* include the step's weight and c_s^2)
+    uint32_t x_in, x_out;
+    double a_in, a_out;
 };
 
 // Per-link values one adjoint step hands to the link-gradient kernel: the
@@ -432,6 +436,9 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
             b[1] -= T(3) * u[1] * as;
             b[2] -= T(3) * u[2] * as;
             const T wux = (T)a.w_ux;
+            // pressure drop: the same term for every population of the node
+            if (a.obj_kind == 3)
+                as += (T)((pos.ix == a.x_in ? a.a_in : 0.0) - (pos.ix == a.x_out ? a.a_out : 0.0));
             auto finish = [&](auto J, T v) {
                 constexpr int jd = decltype(J)::value;
                 T out = mu[jd] - v + as;
@@ -644,6 +651,10 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& n
     a.w_force = obj.kind == 1 ? obj.weight : 0.0;
     a.w_ux = obj.kind == 2 ? obj.weight * obj.inv_nfluid / e.rho0 : 0.0;
     a.want_ds = e.want_ds ? 1 : 0;
+    a.x_in = obj.x_in;
+    a.x_out = obj.x_out;
+    a.a_in = obj.kind == 3 ? obj.weight * obj.a_in / 3.0 : 0.0;
+    a.a_out = obj.kind == 3 ? obj.weight * obj.a_out / 3.0 : 0.0;
     return adj_dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);
         using T = decltype(prec);
@@ -684,6 +695,8 @@ hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in
     a.w_force = obj.kind == 1 ? obj.weight : 0.0;
     a.w_ux = 0.0;
     a.want_ds = 0;
+    a.x_in = a.x_out = 0u;
+    a.a_in = a.a_out = 0.0;
     const unsigned nb = (unsigned)((e.n_links + BX - 1) / BX);
     return adj_dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);

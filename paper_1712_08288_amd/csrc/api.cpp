@@ -311,9 +311,21 @@ int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumul
     lbe::StepObjective so;
     const bool in_window = accumulate && e.obj_kind != LBM_OBJ_NONE &&
                            e.t >= e.obj_t0 && e.t < e.obj_t1;
+    const double window = (double)(e.obj_t1 - e.obj_t0);
     if (in_window && e.obj_kind == LBM_OBJ_MEAN_UX) {
-        so.acc_ux = e.d_obj_acc;
-        so.w_ux = 1.0 / ((double)(e.obj_t1 - e.obj_t0) * (double)e.n_fluid);
+        so.acc = e.d_obj_acc;
+        so.kind = LBM_OBJ_MEAN_UX;
+        so.w = 1.0 / (window * (double)e.n_fluid);
+    }
+    if (in_window && e.obj_kind == LBM_OBJ_PRESSURE_DROP) {
+        // p = c_s^2 rho with c_s^2 = 1/3
+        so.acc = e.d_obj_acc;
+        so.kind = LBM_OBJ_PRESSURE_DROP;
+        so.w = 1.0 / (3.0 * window);
+        so.x_in = (uint32_t)e.obj_x_in;
+        so.x_out = (uint32_t)e.obj_x_out;
+        so.a_in = e.obj_a_in;
+        so.a_out = e.obj_a_out;
     }
     HIPCHK(h, lbe::launch_step(e, in, out, so));
     if (in_window && e.obj_kind == LBM_OBJ_FORCE_X)
@@ -417,6 +429,10 @@ int adjoint_steps(lbm_t* h, int64_t n) {
         const bool in_w = e.obj_kind != LBM_OBJ_NONE && t >= e.obj_t0 && t < e.obj_t1;
         ao.weight = in_w ? 1.0 / (double)(e.obj_t1 - e.obj_t0) : 0.0;
         ao.inv_nfluid = e.n_fluid ? 1.0 / (double)e.n_fluid : 0.0;
+        ao.x_in = (uint32_t)e.obj_x_in;
+        ao.x_out = (uint32_t)e.obj_x_out;
+        ao.a_in = e.obj_a_in;
+        ao.a_out = e.obj_a_out;
         if (!in_w) ao.kind = LBM_OBJ_NONE;
         hipError_t st = hipSuccess;
         e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
@@ -591,12 +607,14 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         mask[node[k]] |= bit;
     }
     int64_t n_fluid = 0;
+    std::vector<int64_t> fluid_per_x(e.nx, 0);
     for (int64_t z = 0; z < e.nz; ++z)
         for (int64_t y = 0; y < e.ny; ++y)
             for (int64_t x = 0; x < e.nx; ++x) {
                 const int64_t n = x + e.nx * (y + e.ny * z);
                 if (solid[n]) continue;
                 ++n_fluid;
+                ++fluid_per_x[x];
                 if (e.xbc == LBM_X_OUTFLOW && x == 0)
                     return fail(h, LBM_EGEOM, "outflow x boundary needs a solid column x = 0");
                 for (int i = 1; i < Q; ++i) {
@@ -612,6 +630,8 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     e.perm = perm;
     e.n_links = n_links;
     e.n_fluid = n_fluid;
+    e.fluid_per_x = fluid_per_x;
+    e.obj_kind = LBM_OBJ_NONE;   // an objective refers to the previous geometry
     e.lk_node_h.resize(n_links);
     e.lk_dir_h.resize(n_links);
     e.q_h.resize(n_links);
@@ -960,13 +980,22 @@ int lbm_set_state(lbm_t* h, const void* src, int64_t time) {
 int lbm_set_objective(lbm_t* h, int kind, int32_t tag, int64_t t_begin, int64_t t_end) {
     if (!h) return LBM_EINVAL;
     Engine& e = h->e;
-    if (kind < LBM_OBJ_NONE || kind > LBM_OBJ_MEAN_UX)
+    if (kind < LBM_OBJ_NONE || kind > LBM_OBJ_PRESSURE_DROP)
         return fail(h, LBM_EINVAL, "unknown objective");
     if (kind != LBM_OBJ_NONE && !(t_end > t_begin && t_begin >= 0))
         return fail(h, LBM_EINVAL, "objective window must satisfy 0 <= t_begin < t_end");
     if (!e.has_geometry) return fail(h, LBM_ESTATE, "set the geometry first");
     if (kind == LBM_OBJ_FORCE_X && (tag < 0 || tag >= e.n_tags))
         return fail(h, LBM_EINVAL, "objective tag has no links");
+    if (kind == LBM_OBJ_PRESSURE_DROP) {
+        const int64_t xo = e.obj_x_out < 0 ? e.nx - 1 : e.obj_x_out;
+        const int64_t ni = e.fluid_per_x[e.obj_x_in], no = e.fluid_per_x[xo];
+        if (ni == 0 || no == 0)
+            return fail(h, LBM_EINVAL, "a pressure-drop plane has no fluid node");
+        e.obj_x_out = xo;
+        e.obj_a_in = 1.0 / (double)ni;
+        e.obj_a_out = 1.0 / (double)no;
+    }
     e.obj_kind = kind;
     e.obj_tag = tag;
     e.obj_t0 = t_begin;
@@ -984,6 +1013,39 @@ int lbm_set_objective(lbm_t* h, int kind, int32_t tag, int64_t t_begin, int64_t 
         if (rc) return rc;
     }
     return sync(h);
+}
+
+int lbm_set_objective_planes(lbm_t* h, int64_t x_in, int64_t x_out) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (x_in < 0 || x_in >= e.nx || x_out < 0 || x_out >= e.nx)
+        return fail(h, LBM_EINVAL, "pressure-drop planes must lie in [0, nx)");
+    e.obj_x_in = x_in;
+    e.obj_x_out = x_out;
+    return LBM_OK;
+}
+
+int lbm_pressure_drop(lbm_t* h, int64_t x_in, int64_t x_out, double* dp) {
+    if (!h || !dp) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.initialized) return fail(h, LBM_ESTATE, "not initialised");
+    if (x_in < 0 || x_in >= e.nx || x_out < 0 || x_out >= e.nx)
+        return fail(h, LBM_EINVAL, "pressure-drop planes must lie in [0, nx)");
+    const int64_t ni = e.fluid_per_x[x_in], no = e.fluid_per_x[x_out];
+    if (ni == 0 || no == 0) return fail(h, LBM_EINVAL, "a pressure-drop plane has no fluid node");
+    const int64_t nb = (2 * e.ny * e.nz + lbe::kBlock - 1) / lbe::kBlock;
+    int rc = ensure_scratch(h, nb + 1);
+    if (rc) return rc;
+    int64_t rows = 0;
+    HIPCHK(h, lbe::launch_plane_density(e, e.buf[e.cur], (uint32_t)x_in, (uint32_t)x_out,
+                                        1.0 / (double)ni, 1.0 / (double)no, e.d_scratch, &rows));
+    HIPCHK(h, lbe::launch_sum_blocks(e, e.d_scratch, rows, 1, e.d_scratch + nb));
+    double out = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&out, e.d_scratch + nb, 8, hipMemcpyDeviceToHost, e.stream));
+    if ((rc = sync(h))) return rc;
+    *dp = out / 3.0;   // p = c_s^2 rho
+    if (!std::isfinite(*dp)) return fail(h, LBM_ENONFINITE, "pressure drop is not finite");
+    return LBM_OK;
 }
 
 int lbm_objective(lbm_t* h, double* J) {

@@ -83,6 +83,9 @@ struct Engine {
     int obj_kind = 0;
     int obj_tag = 0;
     int64_t obj_t0 = 0, obj_t1 = 0;
+    int64_t obj_x_in = 0, obj_x_out = -1;   // pressure-drop planes (-1: nx - 1)
+    double obj_a_in = 0.0, obj_a_out = 0.0; // 1 / (fluid nodes of each plane)
+    std::vector<int64_t> fluid_per_x;       // fluid nodes of each plane x = const
     double* d_obj_acc = nullptr;        // per-block partial sums
     int64_t obj_acc_len = 0;
 
@@ -120,9 +123,15 @@ struct Engine {
 };
 
 // ---- launchers (forward.hip) -------------------------------------------------
+// Objective terms a step accumulates (per-block sums in double, one thread
+// per node): MEAN_UX adds w u_x(x, t); PRESSURE_DROP adds
+// w (a_in [x = x_in] - a_out [x = x_out]) (rho(x, t) - rho0).
 struct StepObjective {
-    double* acc_ux = nullptr;    // per-block accumulator for MEAN_UX, or null
-    double w_ux = 0.0;           // weight (1/(window * n_fluid))
+    double* acc = nullptr;       // per-block accumulator, or null (no objective term)
+    double w = 0.0;              // weight of this step's term
+    int kind = 0;                // LBM_OBJ_MEAN_UX or LBM_OBJ_PRESSURE_DROP
+    uint32_t x_in = 0, x_out = 0;
+    double a_in = 0.0, a_out = 0.0;
 };
 
 hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
@@ -136,6 +145,11 @@ hipError_t launch_observe(Engine& e, const Snapshot& in, double* rho, double* u,
 // per-block partial sums of (drho, rho0 u) over fluid nodes: (nblocks, 1 + D)
 hipError_t launch_mass(Engine& e, const Snapshot& in, double* partials,
                        int64_t* nblocks);
+// per-block partial sums of a_p (rho - rho0) over the fluid nodes of the
+// planes x = x_in (a_in) and x = x_out (a_out); one thread per node of the
+// two planes
+hipError_t launch_plane_density(Engine& e, const Snapshot& in, uint32_t x_in, uint32_t x_out,
+                                double a_in, double a_out, double* partials, int64_t* nblocks);
 // per-block partial momentum-exchange force: (nblocks, n_tags, D)
 hipError_t launch_force(Engine& e, const Snapshot& post, double* partials,
                         int64_t* nblocks);
@@ -157,6 +171,8 @@ struct AdjointObjective {
     int tag = 0;
     double weight = 0.0;         // 0 when step t is outside the window
     double inv_nfluid = 0.0;
+    uint32_t x_in = 0, x_out = 0;        // pressure-drop planes
+    double a_in = 0.0, a_out = 0.0;      // 1 / (fluid nodes of each plane)
 };
 // One reverse step: lambda(t) from lambda(t+1) with the forward states at t
 // (`fwd`) and t+1 (`next`), accumulating the gradients.

@@ -69,6 +69,16 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
     }
 }
 
+// The objective term of one fluid node (see StepObjective): u_x for the mean
+// velocity, the plane weight times the density deviation for the pressure
+// drop.
+__device__ __forceinline__ double objective_term(const StepObjective& ob, uint32_t ix,
+                                                 double drho, double ux) {
+    if (ob.kind == 3)
+        return ((ix == ob.x_in ? ob.a_in : 0.0) - (ix == ob.x_out ? ob.a_out : 0.0)) * drho;
+    return ux;
+}
+
 // Waves are classified on the host (one scalar load per wave): a wave whose
 // 64 nodes are all fluid and free of cut links issues its pulls at once and
 // collides; a wave without fluid exits.  A mixed wave reads every plane as
@@ -81,7 +91,7 @@ template <class L, class T, int XB, bool ROWS>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
        T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
-       Grid g, Params<L, T> p, double* __restrict__ acc_ux, double w_ux) {
+       Grid g, Params<L, T> p, StepObjective ob) {
     __shared__ LinkStage<T> stage[BX / 64];
     const NodePos pos = node_of_thread<ROWS>(g);
     uint32_t lb = blockIdx.x;
@@ -89,13 +99,13 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
     const uint32_t kind = wave_kind(wv);
-    double ux_local = 0.0;
+    double obj_local = 0.0;
     if (kind == WAVE_PLAIN) {
         T f[L::Q];
         pull<L, T, XB, false, kStepTables<T>>(A, waA, g, pos, p, NodeLinks{0u, 0u}, f);
         Macro<L, T> mac;
         collide<L, T, false, kStepTables<T>>(f, p, mac);
-        ux_local = (double)mac.u[0];
+        if (ob.acc) obj_local = objective_term(ob, pos.ix, (double)mac.rho, (double)mac.u[0]);
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             st_nt(B + (size_t)i * g.S, pos.n, f[i]);
@@ -126,7 +136,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         Macro<L, T> mac;
         collide<L, T, false, kStepTables<T>>(f, p, mac);
         if (live) {
-            if (!sol) ux_local = (double)mac.u[0];
+            if (!sol && ob.acc) obj_local = objective_term(ob, pos.ix, (double)mac.rho, (double)mac.u[0]);
             const T nan = (T)__builtin_nan("");
             unroll<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
@@ -136,9 +146,9 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         wave_link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0, p.wall_scale, wbase, nlw, lane,
                              stage[wid]);
     }
-    if (acc_ux) {   // uniform over the launch
-        const double s = block_sum(ux_local);
-        if (threadIdx.x == 0 && lb < g.nblocks) acc_ux[lb] += w_ux * s;
+    if (ob.acc) {   // uniform over the launch
+        const double s = block_sum(obj_local);
+        if (threadIdx.x == 0 && lb < g.nblocks) ob.acc[lb] += ob.w * s;
     }
 }
 
@@ -267,6 +277,39 @@ k_mass(const T* __restrict__ A, const T* __restrict__ wa, NodeMeta nm,
         const double s = block_sum(vals[c]);
         if (threadIdx.x == 0 && b < g.nblocks) partials[(size_t)b * (1 + L::D) + c] = s;
     }
+}
+
+// per-block sums of a_p (rho - rho0) over the fluid nodes of the planes
+// x = x_in and x = x_out: thread t covers node (x_p, r) of plane p = t / R,
+// r = t % R, R = ny nz
+template <class L, class T, int XB>
+__global__ void __launch_bounds__(BX)
+k_plane_density(const T* __restrict__ A, const T* __restrict__ wa, NodeMeta nm, Grid g,
+                Params<L, T> p, uint32_t x_in, uint32_t x_out, double a_in, double a_out,
+                double* __restrict__ partials) {
+    const uint32_t R = g.ny * g.nz;
+    const uint32_t t = blockIdx.x * BX + threadIdx.x;
+    double v = 0.0;
+    if (t < 2u * R) {
+        const uint32_t plane = t / R, r = t - plane * R;
+        NodePos pos;
+        pos.ix = plane ? x_out : x_in;
+        pos.iz = r / g.ny;
+        pos.iy = r - pos.iz * g.ny;
+        pos.n = pos.ix + g.nx * r;
+        pos.in = true;
+        const uint32_t info = nm.info[pos.n];
+        if (!is_solid(info)) {
+            const NodeLinks nl = node_links(nm, g, info, pos.n);
+            T f[L::Q];
+            pull<L, T, XB, true>(A, wa, g, pos, p, nl, f);
+            double r0 = 0.0;
+            unroll<L::Q>([&](auto I) { r0 += (double)f[decltype(I)::value]; });
+            v = (plane ? -a_out : a_in) * r0;
+        }
+    }
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 // momentum exchange of the last step on each link; `post` holds f'(t-1) at
@@ -454,7 +497,7 @@ hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
         hipLaunchKernelGGL(kern, dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
                            (T*)out.wa, meta(e), e.d_lkcoef, g,
-                           make_params<L, T>(e), obj.acc_ux, obj.w_ux);
+                           make_params<L, T>(e), obj);
         return hipGetLastError();
     });
 }
@@ -498,6 +541,22 @@ hipError_t launch_mass(Engine& e, const Snapshot& in, double* partials,
         hipLaunchKernelGGL((k_mass<L, T, XB>), dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (const T*)in.wa, meta(e), g,
                            make_params<L, T>(e), partials);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_plane_density(Engine& e, const Snapshot& in, uint32_t x_in, uint32_t x_out,
+                                double a_in, double a_out, double* partials, int64_t* nblocks) {
+    const Grid g = make_grid(e);
+    const int64_t nb = (2 * e.ny * e.nz + BX - 1) / BX;
+    *nblocks = nb;
+    return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_plane_density<L, T, XB>), dim3((unsigned)nb), dim3(BX), 0, e.stream,
+                           (const T*)in.f, (const T*)in.wa, meta(e), g, make_params<L, T>(e),
+                           x_in, x_out, a_in, a_out, partials);
         return hipGetLastError();
     });
 }

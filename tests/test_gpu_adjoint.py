@@ -36,7 +36,7 @@ def _gpu_grad(geom, s, kw, obj, steps, every, df0, precision="fp64"):
     if kw.get("wall_decay", 1.0) != 1.0:
         sv.set_wall_decay(kw["wall_decay"])
     sv.init_deviation(df0)
-    sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1)
+    sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1, planes=obj.planes)
     sv.run_checkpointed(steps, every)
     J = sv.objective()
     sv.adjoint()
@@ -88,6 +88,19 @@ CASES = [
      lambda: configs.d3q15_paper_rates(1.1), dict(g=(3e-5, 0, 0), l_rule="1.5gamma", b=0.95,
                                                    two_node=True),
      Objective("force_x", tag=1, t0=2, t1=9), 9),
+    ("d3q19_pdrop_seam", lambda: G.random_spheres(22, 14, 12, 2, 2.2, 3.4, seed=4, x_bc="pressure"),
+     lambda: configs.d3q19_rates(0.7), dict(dp=1e-3, l_rule="min"),
+     Objective("pressure_drop", t0=1, t1=9, planes=(0, -1)), 9),
+    ("d3q19_pdrop_seam_rows", lambda: G.random_spheres(64, 9, 8, 2, 2.2, 3.4, seed=14, x_bc="pressure"),
+     lambda: configs.d3q19_rates(0.65), dict(g=(1e-5, 0, 0), dp=1e-3, l_rule="gamma2"),
+     Objective("pressure_drop", t0=0, t1=7, planes=(5, 40)), 7),
+    ("d3q19_meanux_rows256_seam", lambda: G.random_spheres(256, 8, 8, 6, 1.6, 2.9, seed=19,
+                                                           x_bc="pressure"),
+     lambda: configs.d3q19_rates(0.7), dict(dp=1e-3, g=(1e-5, 0, 2e-6), l_rule="gamma2"),
+     Objective("mean_ux", t0=2, t1=20), 20),
+    ("d2q9_pdrop_outflow", lambda: G.channel_cylinder(48, 25, 4.2, (16.3, 12.4), 0.04),
+     lambda: configs.d2q9_rates(0.6), dict(l_rule="gamma2+gamma"),
+     Objective("pressure_drop", t0=2, t1=10, planes=(3, -1)), 10),
 ]
 
 
@@ -181,8 +194,54 @@ def test_adjoint_against_central_differences():
     sv.close()
 
 
-def test_fp32_adjoint_is_close_to_fp64():
-    name, mk_geom, mk_s, kw, obj, steps = CASES[2]
+def test_pressure_drop_gradient_against_central_differences():
+    """C3-like case (D3Q19 sphere packing, pressure seam drho = 1e-3,
+    tau = 0.7): dJ/dgamma of the largest links, dJ/dg and dJ/dtau of the
+    pressure drop between the first and last cross-section."""
+    geom = G.random_spheres(32, 20, 18, 3, 3.0, 4.5, seed=3, x_bc="pressure")
+    s = configs.d3q19_rates(0.7)
+    obj = Objective("pressure_drop", t0=4, t1=16, planes=(0, -1))
+    steps = 16
+    df0 = np.zeros((19, geom.n_nodes))
+    kw = dict(dp=1e-3, l_rule="gamma2", g=(1e-5, 0, 0))
+    sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, 4, df0)
+    assert abs(J) > 0
+    h = 1e-6
+    g0 = np.array([1e-5, 0.0, 0.0])
+
+    def J_at(q=None, g=None, ss=None):
+        sv.update_links(q if q is not None else geom.q, geom.wall_u)
+        sv.set_parameters(ss if ss is not None else s, g if g is not None else g0)
+        sv.init_deviation(df0)
+        sv.set_objective(obj.kind, 0, obj.t0, obj.t1, planes=obj.planes)
+        sv.step(steps)
+        return sv.objective()
+
+    for k in np.argsort(-np.abs(gr["q"]))[:4]:
+        qp, qm = geom.q.copy(), geom.q.copy()
+        qp[k] += h if geom.q[k] + h <= 1 else 0
+        qm[k] -= h
+        fd = (J_at(q=qp) - J_at(q=qm)) / (qp[k] - qm[k])
+        assert abs(fd - gr["q"][k]) <= 1e-6 * abs(gr["q"][k]), (k, fd, gr["q"][k])
+    gp, gm = g0.copy(), g0.copy()
+    gp[0] += h
+    gm[0] -= h
+    fd = (J_at(g=gp) - J_at(g=gm)) / (2 * h)
+    assert abs(fd - gr["g"][0]) <= 1e-6 * abs(gr["g"][0]), (fd, gr["g"][0])
+    visc = [9, 11, 13, 14, 15]
+    sp, sm = s.copy(), s.copy()
+    sp[visc] += h
+    sm[visc] -= h
+    fd = (J_at(ss=sp) - J_at(ss=sm)) / (2 * h)
+    dsn = gr["s"][visc].sum()
+    assert abs(fd - dsn) <= 1e-6 * abs(dsn), (fd, dsn)
+    sv.close()
+
+
+@pytest.mark.parametrize("case", [CASES[2], [c for c in CASES if c[0] == "d3q19_meanux_rows256_seam"][0]],
+                         ids=["d3q19_meanux_seam", "d3q19_meanux_rows256_seam"])
+def test_fp32_adjoint_is_close_to_fp64(case):
+    name, mk_geom, mk_s, kw, obj, steps = case
     geom, s = mk_geom(), mk_s()
     df0 = states.random_deviation(19, geom.n_nodes, seed=3, amp=2e-3)
     sv64, J64, g64 = _gpu_grad(geom, s, kw, obj, steps, 4, df0, "fp64")

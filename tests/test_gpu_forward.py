@@ -49,6 +49,12 @@ def cases():
     yield "d3q15_seam_spheres", G.random_spheres(40, 24, 20, 3, 3.0, 5.5, seed=7, x_bc="pressure",
                                                  lattice="D3Q15"), \
         configs.d3q15_paper_rates(0.9), dict(dp=1e-3, l_rule="2gamma"), 12
+    # nx = 256: the row-aligned variant of the step (block-uniform rows), the
+    # one the 256^3 benchmark runs
+    yield "d3q19_rows256_seam", G.random_spheres(256, 8, 8, 6, 1.6, 2.9, seed=19, x_bc="pressure"), \
+        configs.d3q19_rates(0.7), dict(dp=1e-3, g=(1e-5, 0, 2e-6), l_rule="min"), 24
+    yield "d2q9_rows256_periodic", G.random_cylinders(256, 24, 4, 3.0, 6.0, seed=21), \
+        configs.d2q9_rates(0.6), dict(g=(1e-5, 0, 0), l_rule="gamma2"), 24
 
 
 CASES = list(cases())
@@ -123,6 +129,22 @@ def test_couette_c1_full_run():
     e_o = analytic.relative_l2(u_o, ua, fl)
     assert abs(e_g - e_o) < 1e-10 * e_o
     assert e_g < 2e-3
+    sv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pressure_drop_reduction_matches_oracle(precision):
+    """lbm_pressure_drop (FP64 plane sums) against the oracle's objective
+    value on the same state; planes crossing spheres and the seam."""
+    from oracle.adjoint import Objective
+    geom = G.random_spheres(40, 24, 20, 3, 3.0, 5.5, seed=7, x_bc="pressure")
+    got, want, fl, sv, o, f = pair(geom, configs.d3q19_rates(0.7), 12, precision=precision,
+                                   dp=1e-3, l_rule="min")
+    for planes in [(0, 39), (3, 17), (25, 6)]:
+        dp_o = Objective("pressure_drop", planes=planes).value(o, 0, f, None, None)
+        dp_g = sv.pressure_drop(*planes)
+        tol = 1e-12 if precision == "fp64" else 1e-5
+        assert abs(dp_g - dp_o) <= tol * abs(dp_o), (planes, dp_g, dp_o)
     sv.close()
 
 
