@@ -189,6 +189,17 @@ int lbm_get_distribution(lbm_t *h, double *df);
  * finite.  Synchronises. */
 int lbm_reduce(lbm_t *h, double *mass, double *mom);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * totals of lbm_reduce(), same outputs and errors, computed without any
+ * allocation.  The per-block partial sums go to a fixed device array of
+ * 2^19 doubles (4 MiB) that the library holds on each device until the
+ * process ends; EINVAL when the domain needs more partial sums than that
+ * (above 33,554,176 nodes for D3Q19/D3Q15, 44,738,816 for D2Q9).  Every
+ * call on one device uses the same array: calls that overlap on one device
+ * (separate threads or streams) race.  Synchronises. */
+int lbm_reduce_noalloc(lbm_t *h, double *mass, double *mom);
+
 /* Momentum-exchange force of the most recent step t-1 -> t on each tag:
  * force[tag*D + a] = sum over the tag's links of
  * (e_ibar)_a (f'_ibar(x_f,t-1) + f_i(x_f,t)), absolute (not deviation)

@@ -54,6 +54,7 @@ _time = _sig("lbm_time", _i64, [_p])
 _moments = _sig("lbm_moments", _i, [_p, _p, _p])
 _get_dist = _sig("lbm_get_distribution", _i, [_p, _p])
 _reduce = _sig("lbm_reduce", _i, [_p, _p, _p])
+_reduce_noalloc = _sig("lbm_reduce_noalloc", _i, [_p, _p, _p])
 _force = _sig("lbm_force", _i, [_p, _i32, _p])
 _state_bytes = _sig("lbm_state_bytes", _i64, [_p])
 _get_state = _sig("lbm_get_state", _i, [_p, _p])
@@ -83,7 +84,7 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_set_x_boundary",
             "lbm_set_geometry", "lbm_update_links", "lbm_set_parameters", "lbm_init",
             "lbm_init_deviation", "lbm_step", "lbm_time", "lbm_moments",
-            "lbm_get_distribution", "lbm_reduce", "lbm_force",
+            "lbm_get_distribution", "lbm_reduce", "lbm_reduce_noalloc", "lbm_force",
             "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
             "lbm_set_objective", "lbm_set_objective_planes", "lbm_pressure_drop",
             "lbm_objective", "lbm_run_checkpointed",
@@ -317,6 +318,13 @@ class Solver:
         m = np.zeros(1)
         mom = np.zeros(self.D)
         self._chk(_reduce(self._h, _ptr(m), _ptr(mom)), "reduce")
+        return float(m[0]), mom
+
+    def reduce_noalloc(self):
+        """reduce() through the allocation-free entry point."""
+        m = np.zeros(1)
+        mom = np.zeros(self.D)
+        self._chk(_reduce_noalloc(self._h, _ptr(m), _ptr(mom)), "reduce_noalloc")
         return float(m[0]), mom
 
     def force(self, n_tags):

@@ -506,6 +506,10 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
     for (int k = 0; k < Q; ++k) e.s[k] = s[k];
     e.rho0 = rho0;
     for (int a = 0; a < 3; ++a) e.g[a] = (g && a < D) ? g[a] : 0.0;
+    if (hipGetDevice(&e.device) != hipSuccess) {
+        delete h;
+        return LBM_EDEVICE;
+    }
     if (hipStreamCreate(&e.own_stream) != hipSuccess) {
         delete h;
         return LBM_EDEVICE;
@@ -916,6 +920,39 @@ int lbm_reduce(lbm_t* h, double* mass, double* mom) {
     double out[4] = {0, 0, 0, 0};
     HIPCHK(h, hipMemcpyAsync(out, d_out, cols * 8, hipMemcpyDeviceToHost, e.stream));
     if ((rc = sync(h))) return rc;
+    const double m = (double)e.n_fluid * e.rho0 + out[0];
+    if (mass) *mass = m;
+    if (mom)
+        for (int a = 0; a < e.D; ++a) mom[a] = out[1 + a];
+    bool finite = std::isfinite(m);
+    for (int a = 0; a < e.D; ++a) finite = finite && std::isfinite(out[1 + a]);
+    if (!finite) return fail(h, LBM_ENONFINITE, "mass or momentum is not finite");
+    return LBM_OK;
+}
+
+int lbm_reduce_noalloc(lbm_t* h, double* mass, double* mom) {
+    if (!h) return LBM_EINVAL;
+    Engine& e = h->e;
+    if (!e.initialized) return fail(h, LBM_ESTATE, "not initialised");
+    const int64_t nb = lbe::step_blocks(e);
+    const int cols = 1 + e.D;
+    if (nb * cols + cols > lbe::kNoAllocScratchDoubles)
+        return fail(h, LBM_EINVAL,
+                    "domain too large for the fixed reduction scratch: " +
+                        std::to_string(nb * cols + cols) + " partial sums needed, at most " +
+                        std::to_string(lbe::kNoAllocScratchDoubles) + " (" +
+                        std::to_string((lbe::kNoAllocScratchDoubles / cols - 1) * lbe::kBlock) +
+                        " nodes)");
+    double* scr = nullptr;
+    HIPCHK(h, lbe::noalloc_scratch(e.device, &scr));
+    int64_t rows = 0;
+    HIPCHK(h, lbe::launch_mass(e, e.buf[e.cur], scr, &rows));
+    double* d_out = scr + nb * cols;
+    HIPCHK(h, lbe::launch_sum_blocks(e, scr, rows, cols, d_out));
+    double out[4] = {0, 0, 0, 0};
+    HIPCHK(h, hipMemcpyAsync(out, d_out, cols * 8, hipMemcpyDeviceToHost, e.stream));
+    int rc = sync(h);
+    if (rc) return rc;
     const double m = (double)e.n_fluid * e.rho0 + out[0];
     if (mass) *mass = m;
     if (mom)

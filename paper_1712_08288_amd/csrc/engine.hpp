@@ -11,6 +11,9 @@ namespace lbe {
 
 constexpr int kBlock = 256;             // threads per block of node launches
 constexpr int kWave = 64;
+// doubles of the fixed per-device scratch of the allocation-free entry points
+// (4 MiB)
+constexpr int64_t kNoAllocScratchDoubles = 1 << 19;
 
 struct LinkCoef {        // per cut link, double: Eq. (213) coefficients
     double c1, c2, c3;   // on f_ibar(x_f,t), f'_i(x_f,t), f'_ibar(x_f,t)
@@ -29,6 +32,7 @@ struct Snapshot {
 struct Engine {
     // configuration
     int lattice = 0, precision = 0, Q = 0, D = 0;
+    int device = 0;          // HIP device current at lbm_create
     int64_t nx = 0, ny = 0, nz = 0, N = 0;
     int64_t S = 0;           // stride (values) between direction planes, >= N
     bool xcd_remap = false;  // deal contiguous row slabs to each XCD (measured slower)
@@ -159,6 +163,9 @@ hipError_t launch_force_objective(Engine& e, const Snapshot& post, double* acc,
 // out[c] = sum_b partials[b*cols + c], deterministic
 hipError_t launch_sum_blocks(Engine& e, const double* partials, int64_t rows,
                              int64_t cols, double* out);
+// device address of the fixed scratch (kNoAllocScratchDoubles doubles) on
+// `device`, looked up once per device; shared by every caller on that device
+hipError_t noalloc_scratch(int device, double** out);
 int64_t step_blocks(const Engine& e);       // logical blocks of a node launch
 int64_t adjoint_blocks(const Engine& e);    // blocks of the two adjoint launches together
 int64_t link_blocks(const Engine& e);       // blocks of a link launch

@@ -7,6 +7,8 @@
 //                Eq. (213) during the previous step (the "write-ahead" slot).
 // Pulling f_i(x, t) = A_i(x - e_i) (+ seam term), or wa[k] on a cut link,
 // gives the pre-collision state of Eq. (21) at time t.
+#include <mutex>
+
 #include "engine.hpp"
 #include "kernels.hpp"
 
@@ -602,6 +604,40 @@ hipError_t launch_sum_blocks(Engine& e, const double* partials, int64_t rows,
     hipLaunchKernelGGL(k_sum_blocks, dim3((unsigned)cols), dim3(BX), 0, e.stream,
                        partials, (uint32_t)rows, (uint32_t)cols, out);
     return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Fixed device scratch for the entry points that allocate nothing: one array
+// per device, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (on the host it only names the symbol); it uses the
+// device address that hipGetSymbolAddress returns, looked up once per device
+// with that device current.
+
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t st = hipGetDevice(&cur);
+        if (st != hipSuccess) return st;
+        if (cur != device && (st = hipSetDevice(device)) != hipSuccess) return st;
+        void* p = nullptr;
+        st = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (st != hipSuccess) return st;
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 }  // namespace lbe
