@@ -72,7 +72,8 @@ def test_distribution_matches_oracle(case, precision):
     assert err < TOL[precision], err
     rho_g, u_g = sv.moments()
     rho_o, u_o = o.macroscopic(f)
-    assert rel_l2(u_g.T, u_o.T, fl) < TOL[precision] * 10
+    # FP64: the velocity is a linear map of f, so the same bound holds
+    assert rel_l2(u_g.T, u_o.T, fl) < TOL[precision] * (1 if precision == "fp64" else 10)
     sv.close()
 
 
@@ -92,7 +93,7 @@ def test_two_node_scheme_matches_oracle(case, precision):
         f_prev = o.run(f_prev, steps - 1)
         fn, fp = o.step(f_prev)
         nt = geom.n_tags
-        assert np.allclose(sv.force(nt), o.force(fp, fn, n_tags=nt), rtol=1e-10, atol=1e-13)
+        assert np.allclose(sv.force(nt), o.force(fp, fn, n_tags=nt), rtol=1e-12, atol=1e-14)
     sv.close()
 
 
@@ -102,7 +103,7 @@ def test_outflow_channel_matches_oracle(precision):
     geom = G.channel_cylinder(60, 31, 5.2, (20.4, 15.3), 0.03)
     got, want, fl, sv, o, f = pair(geom, configs.d2q9_rates(0.56), 40,
                                    precision=precision, init="rest", l_rule="min")
-    assert rel_l2(got, want, fl) < TOL[precision] * 10
+    assert rel_l2(got, want, fl) < TOL[precision] * (1 if precision == "fp64" else 10)
     sv.close()
 
 
@@ -157,14 +158,14 @@ def test_reductions_and_force_match_oracle():
     got, want, fl, sv, o, f = pair(geom, s, 9, g=(1e-5, 0, 0), l_rule="gamma2")
     mass, mom = sv.reduce()
     assert abs(mass - o.mass(f)) < 1e-12 * mass
-    assert np.allclose(mom, o.momentum(f), rtol=1e-11, atol=1e-15)
+    assert np.allclose(mom, o.momentum(f), rtol=1e-12, atol=1e-15)
     # force of the last step: rerun the oracle's last step with observation
     f_prev = o.init_deviation(states.random_deviation(9, geom.n_nodes, seed=1))
     f_prev = o.run(f_prev, 8)
     fn, fp = o.step(f_prev)
     want_force = o.force(fp, fn, n_tags=2)
     got_force = sv.force(2)
-    assert np.allclose(got_force, want_force, rtol=1e-11, atol=1e-14)
+    assert np.allclose(got_force, want_force, rtol=1e-12, atol=1e-14)
     sv.close()
 
 
@@ -345,7 +346,7 @@ def test_decaying_wall_data_matches_oracle(precision):
     sv.step(69)
     f = o.run(f, 130)
     fl = geom.solid == 0
-    assert rel_l2(sv.distribution(), o.as_deviation(f), fl) < TOL[precision] * 3
+    assert rel_l2(sv.distribution(), o.as_deviation(f), fl) < TOL[precision] * (1 if precision == "fp64" else 3)
     sv.close()
 
 
