@@ -312,43 +312,6 @@ int lbm_counts(const lbm_t *h, int64_t *n_fluid, int64_t *n_links);
 int lbm_set_timing(lbm_t *h, int on);
 int lbm_last_step_ms(lbm_t *h, double *ms_per_step);
 
-/* Measurement helper, not part of the method: copy `bytes` (a multiple of
- * 16) from src_dev to dst_dev `reps` times after one warm-up copy, on a
- * private stream, and report the mean time per copy from HIP events.  Used
- * as the practical HBM ceiling (read + write of `bytes`) that the step
- * kernels are compared against.  mode 0: grid-stride loop with four
- * independent 16-byte loads per thread and non-temporal stores; 1: one
- * 16-byte element per thread, non-temporal stores; 2: as 1 with ordinary
- * stores.  Both buffers are device memory owned by the caller and must not
- * overlap.  Errors: EINVAL, EDEVICE. */
-int lbm_stream_copy(void *dst_dev, const void *src_dev, int64_t bytes,
-                    int32_t mode, int32_t reps, double *ms_per_copy);
-
-/* The step kernel's access pattern without its arithmetic, as a ceiling for
- * it: Q planes of nx*ny*nz elements (stride nx*ny*nz, x fastest, FP64 or FP32
- * per `precision`) are read at the periodic pull source of each direction
- * (x - e_i wrapped in every axis, the step's own addressing) and written at
- * the node with non-temporal stores, one node per thread in 256-thread
- * blocks.  Runs `reps` times after one warm-up on a private stream and
- * reports the mean time per pass from HIP events (a pass moves
- * 2 * Q * nx*ny*nz * element bytes).  src_dev and dst_dev are caller-owned
- * device buffers of at least Q * nx*ny*nz elements that must not overlap.
- * Errors: EINVAL (bad sizes or lattice; D2Q9 needs nz = 1; one plane must
- * stay below 4 GiB), EDEVICE. */
-int lbm_pull_pattern_copy(int lattice, int precision, void *dst_dev, const void *src_dev,
-                          int64_t nx, int64_t ny, int64_t nz, int32_t reps,
-                          double *ms_per_copy);
-
-/* The adjoint step's access pattern without its arithmetic, as above with
- * a second source: plane i of f_src is read at the pull source x - e_i, plane
- * i of lam_src at x + e_i (the node that pulls from x), and their sum is
- * written at x (a pass moves 3 * Q * nx*ny*nz * element bytes).  The three
- * buffers are caller-owned device memory of at least Q * nx*ny*nz elements;
- * dst_dev must not overlap either source.  Errors as above. */
-int lbm_adjoint_pattern_copy(int lattice, int precision, void *dst_dev, const void *f_src_dev,
-                             const void *lam_src_dev, int64_t nx, int64_t ny, int64_t nz,
-                             int32_t reps, double *ms_per_copy);
-
 const char *lbm_last_error(const lbm_t *h);
 int lbm_destroy(lbm_t *h);
 

@@ -77,6 +77,7 @@ _last_ms = _sig("lbm_last_step_ms", _i, [_p, _p])
 _stream_copy = _sig("lbm_stream_copy", _i, [_p, _p, _i64, _i32, _i32, _p])
 _pull_pattern = _sig("lbm_pull_pattern_copy", _i, [_i, _i, _p, _p, _i64, _i64, _i64, _i32, _p])
 _adj_pattern = _sig("lbm_adjoint_pattern_copy", _i, [_i, _i, _p, _p, _p, _i64, _i64, _i64, _i32, _p])
+_aa_pattern = _sig("lbm_aa_pattern_copy", _i, [_i, _i, _p, _i64, _i64, _i64, _i32, _p, _p])
 _last_err = _sig("lbm_last_error", C.c_char_p, [_p])
 _destroy = _sig("lbm_destroy", _i, [_p])
 
@@ -90,8 +91,10 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_objective", "lbm_run_checkpointed",
             "lbm_adjoint", "lbm_adjoint_step", "lbm_adjoint_remaining", "lbm_set_rate_gradient", "lbm_grad", "lbm_grad_device", "lbm_get_adjoint", "lbm_set_stream",
             "lbm_lattice_info", "lbm_counts", "lbm_set_timing",
-            "lbm_last_step_ms", "lbm_stream_copy", "lbm_pull_pattern_copy", "lbm_adjoint_pattern_copy", "lbm_last_error",
-            "lbm_destroy"]
+            "lbm_last_step_ms", "lbm_last_error", "lbm_destroy"]
+# measurement probes (include/lbm_probe.h)
+EXPORTED_PROBES = ["lbm_stream_copy", "lbm_pull_pattern_copy", "lbm_adjoint_pattern_copy",
+                   "lbm_aa_pattern_copy"]
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q15": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
@@ -198,6 +201,20 @@ def adjoint_pattern_copy(lattice, precision, dst, f_src, lam_src, shape, reps=10
     if rc:
         raise LBMError(rc, "adjoint_pattern_copy")
     return float(ms[0])
+
+
+def aa_pattern_copy(lattice, precision, buf, shape, reps=10):
+    """Time the in-place two-pass (AA) access pattern on one buffer of at
+    least Q * nx*ny*nz elements (torch tensor or device pointer).  Returns
+    (ms per even pass, ms per odd pass)."""
+    b = buf.data_ptr() if hasattr(buf, "data_ptr") else int(buf)
+    nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+    ms = np.zeros(2)
+    rc = _aa_pattern(LATTICES[lattice], PRECISIONS[precision], _p(b), int(nx), int(ny), int(nz),
+                     int(reps), ms[:1].ctypes.data_as(_p), ms[1:].ctypes.data_as(_p))
+    if rc:
+        raise LBMError(rc, "aa_pattern_copy")
+    return float(ms[0]), float(ms[1])
 
 
 class Solver:

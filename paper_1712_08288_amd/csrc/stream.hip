@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/lbm.h"
+#include "../../include/lbm_probe.h"
 #include "kernels.hpp"
 
 namespace lbe {
@@ -83,6 +84,32 @@ k_adjoint_pattern(const T* __restrict__ fsrc, const T* __restrict__ lsrc, T* __r
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         st_nt(dst + (size_t)i * g.S, pos.n, f[i] + lg[i]);
+    });
+}
+
+// The in-place "AA" access pattern, one buffer, no arithmetic.  Even pass:
+// node x reads every plane at x and writes plane i's value into plane ibar at
+// x (node-local).  Odd pass: node x reads plane ibar at x - e_i and writes
+// plane i at x + e_i.  In the odd pass the location (j, y) is read and
+// written by the same node, y - e_j, so the pass is race-free in place.
+template <class L, class T, bool ODD>
+__global__ void __launch_bounds__(BX)
+k_aa_pattern(T* buf, Grid g) {
+    const NodePos pos = node_of_thread(g);
+    if (!pos.in) return;
+    const Pull<XBC_PERIODIC> pl(g, pos);
+    T v[L::Q];
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ib = TAB<L>.opp[i];
+        if constexpr (ODD) v[i] = ld(buf + (size_t)ib * g.S, pl.template src<L, i>());
+        else v[i] = ld(buf + (size_t)i * g.S, pos.n);
+    });
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ib = TAB<L>.opp[i];
+        if constexpr (ODD) st_nt(buf + (size_t)i * g.S, pl.template src<L, ib>(), v[i]);
+        else st_nt(buf + (size_t)ib * g.S, pos.n, v[i]);
     });
 }
 
@@ -205,4 +232,77 @@ extern "C" int lbm_adjoint_pattern_copy(int lattice, int precision, void* dst, c
                                         int32_t reps, double* ms_per_copy) {
     if (!lam_src) return LBM_EINVAL;
     return pattern_copy(lattice, precision, dst, f_src, lam_src, nx, ny, nz, reps, ms_per_copy);
+}
+
+extern "C" int lbm_aa_pattern_copy(int lattice, int precision, void* buf, int64_t nx, int64_t ny,
+                                   int64_t nz, int32_t reps, double* ms_even, double* ms_odd) {
+    if (!buf || nx < 1 || ny < 1 || nz < 1 || reps < 1) return LBM_EINVAL;
+    if (lattice < 0 || lattice > 2 || (precision != LBM_FP64 && precision != LBM_FP32))
+        return LBM_EINVAL;
+    if (lattice == LBM_D2Q9 && nz != 1) return LBM_EINVAL;
+    const int64_t N = nx * ny * nz;
+    const int64_t elem = precision == LBM_FP64 ? 8 : 4;
+    if (N >= (1LL << 31) || N * elem >= (1LL << 32)) return LBM_EINVAL;
+    lbe::Grid g;
+    g.nx = (uint32_t)nx;
+    g.ny = (uint32_t)ny;
+    g.nz = (uint32_t)nz;
+    g.N = (uint32_t)N;
+    g.S = (uint32_t)N;
+    g.nblocks = (uint32_t)((N + lbe::BX - 1) / lbe::BX);
+    g.chunk = 0u;
+    g.bpr = 0u;
+    hipStream_t s;
+    hipEvent_t ev[3];
+    if (hipStreamCreate(&s) != hipSuccess) return LBM_EDEVICE;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipStreamDestroy(s);
+            return LBM_EDEVICE;
+        }
+    auto launch = [&](bool odd) {
+        auto go = [&](auto lat) {
+            using L = decltype(lat);
+            auto typed = [&](auto zero) {
+                using T = decltype(zero);
+                if (odd)
+                    hipLaunchKernelGGL((lbe::k_aa_pattern<L, T, true>), dim3(g.nblocks),
+                                       dim3(lbe::BX), 0, s, (T*)buf, g);
+                else
+                    hipLaunchKernelGGL((lbe::k_aa_pattern<L, T, false>), dim3(g.nblocks),
+                                       dim3(lbe::BX), 0, s, (T*)buf, g);
+            };
+            if (precision == LBM_FP64) typed(0.0);
+            else typed(0.0f);
+        };
+        if (lattice == LBM_D2Q9) go(lbe::D2Q9{});
+        else if (lattice == LBM_D3Q15) go(lbe::D3Q15{});
+        else go(lbe::D3Q19{});
+    };
+    launch(false);   // warm-up pair
+    launch(true);
+    double t_even = 0.0, t_odd = 0.0;
+    int rc = LBM_OK;
+    for (int r = 0; r < reps && rc == LBM_OK; ++r) {
+        (void)hipEventRecord(ev[0], s);
+        launch(false);
+        (void)hipEventRecord(ev[1], s);
+        launch(true);
+        (void)hipEventRecord(ev[2], s);
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(ev[2]) != hipSuccess) {
+            rc = LBM_EDEVICE;
+            break;
+        }
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[1], ev[2]) != hipSuccess)
+            rc = LBM_EDEVICE;
+        t_even += a;
+        t_odd += b;
+    }
+    if (ms_even) *ms_even = t_even / reps;
+    if (ms_odd) *ms_odd = t_odd / reps;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(s);
+    return rc;
 }

@@ -11,10 +11,11 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
+PROBE_HEADER = os.path.join(ROOT, "include", "lbm_probe.h")
 
 
-def _declared():
-    text = open(HEADER).read()
+def _declared(path=HEADER):
+    text = open(path).read()
     return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
 
 
@@ -27,10 +28,12 @@ def binding():
 def test_library_exports_every_declared_symbol(binding):
     lib = ctypes.CDLL(binding.LIB_PATH)
     names = _declared()
-    assert len(names) >= 25
-    for n in names:
+    probes = _declared(PROBE_HEADER)
+    assert len(names) >= 25 and len(probes) >= 4
+    for n in names + probes:
         assert hasattr(lib, n), n
     assert sorted(binding.EXPORTED) == names
+    assert sorted(binding.EXPORTED_PROBES) == probes
 
 
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q15", "D3Q19"])
