@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblbm.so")
-SOURCES = ["api.cpp", "forward.hip", "adjoint.hip", "stream.hip"]
+SOURCES = ["api.cpp", "geometry.cpp", "forward.hip", "adjoint.hip", "stream.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -13,6 +13,7 @@
 
 #include "../../include/lbm.h"
 #include "engine.hpp"
+#include "geometry.hpp"
 #include "lattice.hpp"
 
 using lbe::Engine;
@@ -169,21 +170,6 @@ int upload(lbm_t* h, T*& dst, const T* src, size_t n) {
 int sync(lbm_t* h) {
     HIPCHK(h, hipStreamSynchronize(h->e.stream));
     return LBM_OK;
-}
-
-// pull source of direction i at node (x, y, z), or -1 when it lies outside
-int64_t pull_source(const Engine& e, int64_t x, int64_t y, int64_t z, int i) {
-    int64_t sx = x - lat_e(e.lattice, i, 0);
-    const int64_t sy = ((y - lat_e(e.lattice, i, 1)) % e.ny + e.ny) % e.ny;
-    const int64_t dz = e.D == 3 ? lat_e(e.lattice, i, 2) : 0;
-    const int64_t sz = ((z - dz) % e.nz + e.nz) % e.nz;
-    if (e.xbc == LBM_X_OUTFLOW) {
-        if (sx >= e.nx) sx = e.nx - 1;
-        if (sx < 0) sx = 0;
-    } else {
-        sx = (sx % e.nx + e.nx) % e.nx;
-    }
-    return sx + e.nx * (sy + e.ny * sz);
 }
 
 // Coefficients of Eq. (213) for every (sorted) link, and their gamma
@@ -577,138 +563,49 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
                      const double* wall_u, const int32_t* tag) {
     if (!h) return LBM_EINVAL;
     Engine& e = h->e;
-    if (!solid) return fail(h, LBM_EINVAL, "solid mask is NULL");
-    if (n_links < 0 || n_links >= (1LL << 26))
-        return fail(h, LBM_EINVAL, "number of links out of range [0, 2^26)");
-    if (n_links > 0 && (!node || !dir || !q))
-        return fail(h, LBM_EINVAL, "link arrays are NULL");
-    const int64_t N = e.N;
-    const int Q = e.Q, D = e.D;
-    for (int64_t n = 0; n < N; ++n)
-        if (solid[n] > 1) return fail(h, LBM_EINVAL, "solid mask values must be 0 or 1");
-    for (int64_t k = 0; k < n_links; ++k) {
-        if (node[k] < 0 || node[k] >= N) return fail(h, LBM_EINVAL, "link node out of range");
-        if (dir[k] < 1 || dir[k] >= Q) return fail(h, LBM_EINVAL, "link direction out of range");
-        if (!(q[k] > 0.0 && q[k] <= 1.0)) return fail(h, LBM_EINVAL, "q must lie in (0, 1]");
-        if (solid[node[k]]) return fail(h, LBM_EGEOM, "link at a solid node");
-        if (tag && tag[k] < 0) return fail(h, LBM_EINVAL, "negative tag");
-        if (wall_u)
-            for (int a = 0; a < D; ++a)
-                if (!std::isfinite(wall_u[k * D + a]))
-                    return fail(h, LBM_EINVAL, "wall velocity not finite");
-    }
-    // sort by (node, dir)
-    std::vector<int64_t> perm(n_links);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
-        return node[a] != node[b] ? node[a] < node[b] : dir[a] < dir[b];
-    });
-    // per-node link mask, duplicates, consistency with the mask
-    std::vector<uint32_t> mask(N, 0u);
-    for (int64_t k = 0; k < n_links; ++k) {
-        const uint32_t bit = 1u << dir[k];
-        if (mask[node[k]] & bit) return fail(h, LBM_EGEOM, "duplicate cut link");
-        mask[node[k]] |= bit;
-    }
-    int64_t n_fluid = 0;
-    std::vector<int64_t> fluid_per_x(e.nx, 0);
-    for (int64_t z = 0; z < e.nz; ++z)
-        for (int64_t y = 0; y < e.ny; ++y)
-            for (int64_t x = 0; x < e.nx; ++x) {
-                const int64_t n = x + e.nx * (y + e.ny * z);
-                if (solid[n]) continue;
-                ++n_fluid;
-                ++fluid_per_x[x];
-                if (e.xbc == LBM_X_OUTFLOW && x == 0)
-                    return fail(h, LBM_EGEOM, "outflow x boundary needs a solid column x = 0");
-                for (int i = 1; i < Q; ++i) {
-                    const bool need = solid[pull_source(e, x, y, z, i)] != 0;
-                    const bool have = (mask[n] >> i) & 1u;
-                    if (need != have)
-                        return fail(h, LBM_EGEOM,
-                                    need ? "fluid node pulls from a solid node without a cut link"
-                                         : "cut link whose pull source is fluid");
-                }
-            }
-    // host copies in sorted order
-    e.perm = perm;
+    // validation, link sort and the node / wave tables (host, geometry.cpp)
+    int E[19][3];
+    for (int i = 0; i < e.Q; ++i)
+        for (int a = 0; a < 3; ++a) E[i][a] = a < e.D ? lat_e(e.lattice, i, a) : 0;
+    lbe::GeomDomain dom;
+    dom.Q = e.Q;
+    dom.D = e.D;
+    dom.e = E;
+    dom.nx = e.nx;
+    dom.ny = e.ny;
+    dom.nz = e.nz;
+    dom.outflow = e.xbc == LBM_X_OUTFLOW;
+    dom.block = lbe::kBlock;
+    dom.wave = lbe::kWave;
+    lbe::GeomLinks links;
+    links.n = n_links;
+    links.node = node;
+    links.dir = dir;
+    links.q = q;
+    links.wall_u = wall_u;
+    links.tag = tag;
+    lbe::GeomTables tab;
+    std::string why;
+    const int vrc = lbe::build_geometry(dom, solid, links, tab, why);
+    if (vrc) return fail(h, vrc, why);
+    static_assert(sizeof(lbe::WaveWord) == sizeof(uint2) && sizeof(lbe::WaveEntry) == sizeof(uint4),
+                  "host wave tables must match the device vector types");
+    e.perm = tab.perm;
     e.n_links = n_links;
-    e.n_fluid = n_fluid;
-    e.fluid_per_x = fluid_per_x;
+    e.n_fluid = tab.n_fluid;
+    e.fluid_per_x = tab.fluid_per_x;
     e.obj_kind = LBM_OBJ_NONE;   // an objective refers to the previous geometry
-    e.lk_node_h.resize(n_links);
-    e.lk_dir_h.resize(n_links);
-    e.q_h.resize(n_links);
-    e.wall_u_h.assign((size_t)n_links * D, 0.0);
-    e.tag_h.resize(n_links);
-    int max_tag = -1;
-    for (int64_t k = 0; k < n_links; ++k) {
-        const int64_t p = perm[k];
-        e.lk_node_h[k] = node[p];
-        e.lk_dir_h[k] = dir[p];
-        e.q_h[k] = q[p];
-        if (wall_u)
-            for (int a = 0; a < D; ++a) e.wall_u_h[k * D + a] = wall_u[p * D + a];
-        e.tag_h[k] = tag ? tag[p] : 0;
-        max_tag = std::max(max_tag, e.tag_h[k]);
-    }
-    e.n_tags = max_tag + 1;
-    e.ibar_is_link.assign(n_links, 0);
-    for (int64_t k = 0; k < n_links; ++k) {
-        const int i = e.lk_dir_h[k];
-        int ib = 0;
-        for (int j = 0; j < Q; ++j) {
-            bool opp = true;
-            for (int a = 0; a < D; ++a) opp = opp && lat_e(e.lattice, j, a) == -lat_e(e.lattice, i, a);
-            if (opp) ib = j;
-        }
-        e.ibar_is_link[k] = (mask[e.lk_node_h[k]] >> ib) & 1u;
-    }
-    // per node: bit 31 solid, else the link-direction mask and, in bits
-    // 19..30, the number of links at earlier nodes of its wave; per 64-node
-    // wave of a node launch (64 consecutive node indices): its kind -- idle
-    // (no fluid), plain (64 fluid nodes without links) or mixed -- with its
-    // link count, and the index of its first link (links are sorted by node)
-    std::vector<uint32_t> info(N);
-    std::vector<uint2> wave;
-    {
-        const int64_t nwave = (N + lbe::kBlock - 1) / lbe::kBlock * (lbe::kBlock / lbe::kWave);
-        wave.assign(nwave, make_uint2(2u, 0u));
-        int64_t k = 0;
-        for (int64_t w = 0; w < nwave; ++w) {
-            const int64_t n0 = w * lbe::kWave;
-            const int64_t nin = std::max<int64_t>(0, std::min<int64_t>(lbe::kWave, N - n0));
-            bool any_fluid = false, all_plain = nin == lbe::kWave;
-            const int64_t k0 = k;
-            for (int64_t n = n0; n < n0 + nin; ++n) {
-                if (solid[n]) {
-                    info[n] = 0x80000000u;
-                    all_plain = false;
-                    continue;
-                }
-                any_fluid = true;
-                all_plain = all_plain && mask[n] == 0u;
-                info[n] = mask[n] | ((uint32_t)(k - k0) << 19);
-                k += __builtin_popcount(mask[n]);
-            }
-            const uint32_t kind = !any_fluid ? 2u : (all_plain ? 1u : 0u);
-            uint32_t dead = 0u;   // eighths of 8 lanes without a fluid node
-            for (int qd = 0; qd < 8; ++qd) {
-                bool fluid = false;
-                for (int64_t n = n0 + 8 * qd; n < std::min<int64_t>(n0 + 8 * qd + 8, N); ++n)
-                    fluid = fluid || !solid[n];
-                if (!fluid) dead |= 1u << qd;
-            }
-            if (kind != 0u) dead = 0u;
-            wave[w] = make_uint2(kind | ((uint32_t)(k - k0) << 2) | (dead << 16), (uint32_t)k0);
-        }
-        if (k != n_links) return fail(h, LBM_EGEOM, "link count mismatch");
-    }
-    // the adjoint's wave list: the non-idle waves with their table entries
-    std::vector<uint4> wact;
-    for (size_t w = 0; w < wave.size(); ++w)
-        if ((wave[w].x & 3u) != 2u) wact.push_back(make_uint4((uint32_t)w, wave[w].x, wave[w].y, 0u));
-    e.n_wact = (int64_t)wact.size();
+    e.lk_node_h = tab.node;
+    e.lk_dir_h = tab.dir;
+    e.q_h = tab.q;
+    e.wall_u_h = tab.wall_u;
+    e.tag_h = tab.tag;
+    e.n_tags = tab.n_tags;
+    e.ibar_is_link = tab.ibar_is_link;
+    const std::vector<uint32_t>& info = tab.info;
+    const auto* wave = reinterpret_cast<const uint2*>(tab.wave.data());
+    const auto* wact = reinterpret_cast<const uint4*>(tab.wact.data());
+    e.n_wact = (int64_t)tab.wact.size();
     std::vector<uint8_t> d8(n_links);
     std::vector<int32_t> n32(n_links);
     for (int64_t k = 0; k < n_links; ++k) {
@@ -720,8 +617,8 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
     free_run(e);
     int rc;
     if ((rc = upload(h, e.d_info, info.data(), info.size()))) return rc;
-    if ((rc = upload(h, e.d_wave, wave.data(), wave.size()))) return rc;
-    if ((rc = upload(h, e.d_wact, wact.data(), wact.size()))) return rc;
+    if ((rc = upload(h, e.d_wave, wave, tab.wave.size()))) return rc;
+    if ((rc = upload(h, e.d_wact, wact, tab.wact.size()))) return rc;
     if ((rc = upload(h, e.d_lkdir, d8.data(), d8.size()))) return rc;
     if ((rc = upload(h, e.d_lknode, n32.data(), n32.size()))) return rc;
     {
