@@ -4,14 +4,18 @@ pressure-driven x, tau = 0.7), on one MI355X.
 
 Timed, each with inputs resident in HBM:
   * FP32 forward step (deviation storage): `value` = MLUPS over all N nodes,
-    `ms_per_step`, and the roofline of the step kernel from HIP events on the
-    library's stream (algorithmic bytes / average launch time);
+    `ms_per_step` (median of windows of K steps), and the roofline of the
+    step kernel from HIP events on the library's stream (algorithmic bytes
+    of the scope table / median launch time);
   * FP64 forward step: MLUPS and the FP32/FP64 speedup;
-  * FP32 forward + adjoint: a checkpointed run of A steps followed by the
-    reverse sweep (segment replay + adjoint steps + gradient sums), as MLUPS
-    of differentiated time steps and the adjoint/forward cost ratio;
-  * the velocity difference between the FP32 and FP64 runs (same steps);
-  * the CPU oracle (numpy, float64) on a bounded slab of the same workload.
+  * the velocity difference between FP32 and FP64 after the workload's
+    configured 500 steps;
+  * FP32 and FP64 forward + adjoint: a checkpointed run of A steps followed
+    by the reverse sweep (segment replay + adjoint steps + gradient sums), as
+    MLUPS of differentiated time steps and the reverse/forward cost ratio;
+  * the forward step of the other workloads (per_config);
+  * the CPU oracle (numpy, float64) on a bounded slab of the same workload,
+    on one thread and with all BLAS threads, with the CPU model.
 Prints one JSON line.
 """
 
@@ -46,27 +50,44 @@ def kernel_sources_hash():
 
 
 def algorithmic_bytes(Q, s, n_nodes, n_fluid, n_links):
-    """Bytes one forward step must move: each fluid node reads and writes Q
-    values, every node's 4-byte node word is read, and each cut link reads
-    its direction byte, four double coefficients and one link slot and
-    writes one link slot."""
+    """Bytes one forward step must move by the per-unit count of the scope
+    table: each fluid node reads and writes Q values (2 Q s), each cut link
+    moves 48 bytes of link data, and each node one byte of its type."""
+    return 2 * Q * s * n_fluid + 48 * n_links + n_nodes
+
+
+def kernel_bytes(Q, s, n_nodes, n_fluid, n_links):
+    """The same with what this step kernel actually has to move: a 4-byte
+    node word per node, and per cut link its direction byte, four double
+    coefficients, one link-slot read and one link-slot write."""
     return 2 * Q * s * n_fluid + 4 * n_nodes + n_links * (1 + 32 + 2 * s)
 
 
-def time_forward(binding, geom, w, precision, steps, warmup):
+def timed_windows(sv, steps, windows):
+    """`windows` timed windows of exactly `steps` steps, each between
+    synchronisations: wall ms per step and the step kernel's HIP-event ms
+    per step (library stream) of every window."""
     import torch
-    sv = binding.solver_for(geom, w.s, precision=precision, dp=w.dp, l_rule=w.l_rule)
+    walls, kers = [], []
+    for _ in range(windows):
+        sv.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv.step(steps)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3 / steps)
+        kers.append(sv.last_step_ms())
+        sv.set_timing(False)
+    return walls, kers
+
+
+def time_forward(binding, geom, w, precision, steps, warmup, windows=5):
+    """W untimed steps, then `windows` windows of K steps; medians."""
+    sv = binding.solver_for(geom, w.s, g=w.g, precision=precision, dp=w.dp, l_rule=w.l_rule)
     sv.init()
     sv.step(warmup)
-    torch.cuda.synchronize()
-    sv.set_timing(True)
-    t0 = time.perf_counter()
-    sv.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kernel_ms = sv.last_step_ms()
-    sv.set_timing(False)
-    return sv, (t1 - t0) * 1e3 / steps, kernel_ms
+    walls, kers = timed_windows(sv, steps, windows)
+    return sv, float(np.median(walls)), float(np.median(kers)), walls, kers
 
 
 def copy_ceiling(binding, torch, nbytes=1 << 31, reps=20, all_modes=False):
@@ -124,7 +145,9 @@ def adjoint_pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
 def cpu_baseline(geom, w, slab=48, steps=20, threads=None):
     """Oracle on the z-slab 0 <= z < slab of the same workload (window mode:
     reads across the slab faces see NaN and are not used; slab=None runs the
-    whole domain).  threads limits the BLAS threads (None: all)."""
+    whole domain).  threads limits the BLAS threads (None: all).  The
+    oracle's elementwise numpy work runs on one thread whatever the limit;
+    only its dense moment products use the BLAS threads."""
     from oracle.lbm import Oracle
     import contextlib
     try:
@@ -191,23 +214,64 @@ def _progress(what):
     print("[bench] " + what, file=sys.stderr, flush=True)
 
 
+def pattern_rate(binding, torch, lattice, shape, prec, Q):
+    """Raw bytes per second of the step's pull pattern without arithmetic on
+    this grid and precision (the kernel's own ceiling)."""
+    n = int(np.prod(shape))
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    a = torch.ones(Q * n, dtype=dt, device="cuda")
+    b = torch.empty_like(a)
+    ms = binding.pull_pattern_copy(lattice, prec, b, a, shape, reps=10)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * Q * n * (4 if prec == "fp32" else 8) / (ms * 1e-3) / 1e9
+
+
+def per_config_forward(binding, torch, windows=3):
+    """The forward step of every workload in its benchmark precisions, from
+    rest: MLUPS over all nodes, the HBM fraction by the scope table's
+    algorithmic bytes, and the fraction of the step's own access pattern on
+    the same grid (periodic, no arithmetic).  Medians over `windows` timed
+    windows.  The 256^3 sphere packing is the headline line itself."""
+    from workloads import configs
+    plan = [("c1_couette_64", configs.c1_couette(64), ("fp64",), 640),
+            ("c2_cylinders_2048", configs.c2_cylinders(), ("fp64", "fp32"), 200),
+            ("c4_cylinder_1024x512", configs.c4_cylinder(), ("fp64", "fp32"), 200),
+            ("c5_porous_384x256x256", configs.c5_porous(), ("fp32",), 100)]
+    out = {}
+    for name, w, precs, steps in plan:
+        geom = w.geometry()
+        Q = 9 if geom.lattice == "D2Q9" else 19
+        res = {"n_nodes": geom.n_nodes, "n_fluid": geom.n_fluid, "n_links": geom.n_links}
+        for prec in precs:
+            s = 4 if prec == "fp32" else 8
+            sv = binding.solver_for(geom, w.s, g=w.g, precision=prec, dp=w.dp, l_rule=w.l_rule)
+            sv.init()
+            sv.step(20)
+            walls, kers = timed_windows(sv, steps, windows)
+            sv.close()
+            ms, kms = float(np.median(walls)), float(np.median(kers))
+            by = algorithmic_bytes(Q, s, geom.n_nodes, geom.n_fluid, geom.n_links)
+            pat = pattern_rate(binding, torch, geom.lattice, geom.shape, prec, Q)
+            res[prec] = {"ms_per_step": round(ms, 5), "kernel_ms": round(kms, 5),
+                         "mlups": round(geom.n_nodes / (ms * 1e-3) / 1e6, 1),
+                         "hbm_frac": round(by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "pattern_ceiling_GBps": round(pat, 1),
+                         "frac_of_pattern": round(by / (kms * 1e-3) / 1e9 / pat, 4)}
+        if name.startswith("c1"):
+            res["note"] = "0.6 MB working set, graph replay: launch-bound, not an HBM measurement"
+        if name.startswith("c4"):
+            res["note"] = "19-38 MB working set: runs partly from the 256 MB last-level cache"
+        out[name] = res
+        del geom
+    return out
+
+
 def all_configs(binding, torch):
     """Every benchmark workload: MLUPS and HBM fraction per precision,
     accuracy figures, and the checkpointed adjoints of C4 and C5."""
     from workloads import analytic, configs
     out = {}
-
-    def pattern_rate(lattice, shape, prec, Q):
-        """Raw bytes per second of the step's pull pattern without arithmetic
-        on this grid and precision (the kernel's own ceiling)."""
-        n = int(np.prod(shape))
-        dt = torch.float32 if prec == "fp32" else torch.float64
-        a = torch.ones(Q * n, dtype=dt, device="cuda")
-        b = torch.empty_like(a)
-        ms = binding.pull_pattern_copy(lattice, prec, b, a, shape, reps=10)
-        del a, b
-        torch.cuda.empty_cache()
-        return 2 * Q * n * (4 if prec == "fp32" else 8) / (ms * 1e-3) / 1e9
 
     def fwd(w, geom, prec, steps, warm=10, **kw):
         sv = binding.solver_for(geom, w.s, g=w.g, precision=prec, dp=w.dp,
@@ -218,7 +282,7 @@ def all_configs(binding, torch):
         Q = 9 if geom.lattice == "D2Q9" else 19
         by = algorithmic_bytes(Q, 4 if prec == "fp32" else 8, geom.n_nodes,
                                geom.n_fluid, geom.n_links)
-        pat = pattern_rate(geom.lattice, geom.shape, prec, Q)
+        pat = pattern_rate(binding, torch, geom.lattice, geom.shape, prec, Q)
         return sv, {"ms_per_step": round(ms, 5), "wall_ms_per_step": round(wall, 5),
                     "mlups": round(geom.n_nodes / (ms * 1e-3) / 1e6, 1),
                     "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -453,17 +517,22 @@ def run_study(name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--adjoint-steps", type=int, default=64)
     ap.add_argument("--every", type=int, default=8)
     ap.add_argument("--n", type=int, default=256, help="lattice edge (256 = the benchmark)")
+    ap.add_argument("--windows", type=int, default=5,
+                    help="timed windows of --steps steps (the median is reported)")
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the forward step of the other workloads")
     ap.add_argument("--study", choices=["poiseuille", "taylor_green", "hagen_poiseuille",
                                         "hagen_poiseuille_d3q19", "b", "b_bgk", "collisions"],
                     help="run one of the paper's Section 3 sweeps on the GPU instead")
     ap.add_argument("--all", action="store_true",
-                    help="also measure every workload (C1-C5) into 'per_config'")
+                    help="also measure every workload (C1-C5) in detail into 'all_configs'")
     ap.add_argument("--only", choices=["fwd32", "fwd64", "adjoint32", "copy", "pattern"],
                     help="profiling runs: time only this part and print its line")
     args = ap.parse_args()
@@ -498,7 +567,7 @@ def main():
     N, NF, NL = geom.n_nodes, geom.n_fluid, geom.n_links
     if args.only in ("fwd32", "fwd64"):
         prec = args.only.replace("fwd", "fp")
-        sv, ms, kms = time_forward(binding, geom, w, prec, args.steps, args.warmup)
+        sv, ms, kms, _, _ = time_forward(binding, geom, w, prec, args.steps, args.warmup, windows=1)
         s = 4 if prec == "fp32" else 8
         by = algorithmic_bytes(19, s, N, NF, NL)
         print(json.dumps({"only": args.only, "ms_per_step": ms, "kernel_ms": kms,
@@ -519,60 +588,65 @@ def main():
         sv.close()
         return
 
-    # FP32 forward (headline)
-    sv32, ms32, kms32 = time_forward(binding, geom, w, "fp32", args.steps, args.warmup)
+    W, K, R = args.warmup, args.steps, args.windows
+    _progress("FP32 and FP64 forward: %d warm-up steps, %d windows of %d steps" % (W, R, K))
+    # FP32 forward (headline): median over R windows of exactly K steps
+    sv32, ms32, kms32, walls32, kers32 = time_forward(binding, geom, w, "fp32", K, W, R)
     # FP64 forward
-    sv64, ms64, kms64 = time_forward(binding, geom, w, "fp64", args.steps, args.warmup)
-    # same number of steps on both: velocity difference FP32 vs FP64
+    sv64, ms64, kms64, walls64, kers64 = time_forward(binding, geom, w, "fp64", K, W, R)
+    # FP32 against FP64 after the workload's configured steps (both from rest)
+    t_cmp = max(w.steps, sv32.time)
+    sv32.step(t_cmp - sv32.time)
+    sv64.step(t_cmp - sv64.time)
     _, u32 = sv32.moments()
     _, u64 = sv64.moments()
     fl = geom.solid == 0
     du = float(np.sqrt(((u32 - u64)[fl] ** 2).sum() / (u64[fl] ** 2).sum()))
-    sv64.close()
-    # spread of the FP32 step time: five more timed runs of 100 steps
-    reps = []
-    for _ in range(5):
-        sv32.set_timing(True)
-        sv32.step(100)
-        reps.append(round(sv32.last_step_ms(), 4))
-        sv32.set_timing(False)
+    del u32, u64
 
-    # FP32 forward + adjoint (checkpointed run, then the reverse sweep)
+    # forward + adjoint (checkpointed run, then the reverse sweep), both
+    # precisions; mean u_x over the window, gradients in g and every q
     A = args.adjoint_steps
-    sv32.set_rate_gradient(False)      # the benchmark objective needs dJ/dg and dJ/dq
-    state0 = torch.empty(sv32.state_bytes(), dtype=torch.uint8, device="cuda")
-    sv32.get_state(state0)
-    t_start = sv32.time
 
-    nl32 = sv32.counts()[1]
-    dq_dev = torch.empty(nl32, dtype=torch.float64, device="cuda")
-    du_dev = torch.empty((nl32, 3), dtype=torch.float64, device="cuda")
-
-    def fwd_rev(every):
+    def fwd_rev(sv, every):
         """One untimed forward + reverse cycle allocates the checkpoints, the
         replay pool and the adjoint arrays (kept); the second is timed.  The
         per-link gradients end in device tensors, as the autograd path
         returns them."""
+        sv.set_rate_gradient(False)
+        state0 = torch.empty(sv.state_bytes(), dtype=torch.uint8, device="cuda")
+        sv.get_state(state0)
+        t_start = sv.time
+        nl = sv.counts()[1]
+        dq_dev = torch.empty(nl, dtype=torch.float64, device="cuda")
+        du_dev = torch.empty((nl, 3), dtype=torch.float64, device="cuda")
         for _ in range(2):
-            sv32.set_state(state0, t_start)
-            sv32.set_objective("mean_ux", 0, t_start, t_start + A)
+            sv.set_state(state0, t_start)
+            sv.set_objective("mean_ux", 0, t_start, t_start + A)
             torch.cuda.synchronize()
             a = time.perf_counter()
-            sv32.run_checkpointed(A, every)
+            sv.run_checkpointed(A, every)
             torch.cuda.synchronize()
             b = time.perf_counter()
-            sv32.adjoint()
-            gr = sv32.grad_device(dq_dev, du_dev)
+            sv.adjoint()
+            gr = sv.grad_device(dq_dev, du_dev)
             torch.cuda.synchronize()
             c = time.perf_counter()
-        return sv32.objective(), gr, (b - a) * 1e3 / A, (c - b) * 1e3 / A
+        sv.set_state(state0, t_start)
+        return sv.objective(), gr, (b - a) * 1e3 / A, (c - b) * 1e3 / A
 
-    J, g, ms_fwd_ckpt, ms_adj = fwd_rev(args.every)
+    _progress("FP64 forward + adjoint")
+    J64, g64, ms64_fwd_ckpt, ms64_adj = fwd_rev(sv64, args.every)
+    sv64.close()
+    _progress("FP32 forward + adjoint")
+    J32, g32, ms_fwd_ckpt, ms_adj = fwd_rev(sv32, args.every)
     # every step kept (no replay): A states of state_bytes, 81 GB at 256^3
     # FP32 with A = 64, well inside one MI355X
-    _, _, ms_fwd_all, ms_adj_all = fwd_rev(1)
+    _, _, ms_fwd_all, ms_adj_all = fwd_rev(sv32, 1)
     sv32.close()
+    torch.cuda.empty_cache()
 
+    _progress("ceilings")
     ceiling = copy_ceiling(binding, torch)
     pattern = pattern_ceiling(binding, torch)
     adj_pattern = adjoint_pattern_ceiling(binding, torch)
@@ -580,7 +654,9 @@ def main():
                if kernel_sources_hash() == MEASURED_TRAFFIC["sources_sha256_16"] else None)
     bytes32 = algorithmic_bytes(19, 4, N, NF, NL)
     bytes64 = algorithmic_bytes(19, 8, N, NF, NL)
+    kbytes32 = kernel_bytes(19, 4, N, NF, NL)
     achieved = bytes32 / (kms32 * 1e-3) / 1e9
+    frac = achieved / HBM_PEAK_GBS
     mlups32 = N / (ms32 * 1e-3) / 1e6
     mlups64 = N / (ms64 * 1e-3) / 1e6
     out = {
@@ -588,14 +664,16 @@ def main():
         "value": round(mlups32, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": K,
+        "warmup": W,
         "ms_per_step": round(ms32, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
+        "timing": "median over %d windows of exactly %d steps, each between device "
+                  "synchronisations, after %d untimed steps" % (R, K, W),
         "config": {
             "workload": "D3Q19 MRT %d^3, 120 random spheres r~U[10,20] seed 3, "
                         "pressure-driven x drho=1e-3, tau=0.7, l=max(0,2q-1), "
@@ -608,49 +686,79 @@ def main():
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(frac, 4),
             "traffic": traffic,
+            "traffic_source": ("rocprofv3 FETCH_SIZE + WRITE_SIZE per launch of this kernel "
+                               "source (hash %s), scaled by a copy of known size; "
+                               "profiles/k_step_d3q19_fp32_spheres256.md; null when the "
+                               "kernel source changed since" % MEASURED_TRAFFIC["sources_sha256_16"]),
             "kernel": "k_step<D3Q19,float,pressure>",
+            "kernel_ms": round(kms32, 4),
+            "windows_kernel_ms": [round(v, 4) for v in kers32],
+            "algorithmic_bytes": int(bytes32),
+            "algorithmic_bytes_rule": "2*Q*s*N_fluid + 48*N_links + N_nodes",
+            "kernel_count_bytes": int(kbytes32),
+            "kernel_count_frac": round(kbytes32 / (kms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "target_frac": 0.70,
+            "target_met": bool(frac >= 0.70),
             "copy_ceiling_GBps": ceiling["best_GBps"],
             "frac_of_copy_ceiling": round(achieved / ceiling["best_GBps"], 4),
             # the same access pattern without the arithmetic, measured here;
             # compared with the kernel's measured HBM bytes per second
             "pattern_ceiling_GBps": round(pattern, 1),
             "traffic_GBps": (round(traffic / (kms32 * 1e-3) / 1e9, 1) if traffic else None),
-            "frac_of_pattern_ceiling": round((traffic or bytes32) / (kms32 * 1e-3) / 1e9 / pattern, 4),
-            "kernel_ms": round(kms32, 4),
-            "repeats_kernel_ms": reps, "repeats_median_ms": float(np.median(reps)),
-            "algorithmic_bytes": int(bytes32),
+            "frac_of_pattern_ceiling": round((traffic or kbytes32) / (kms32 * 1e-3) / 1e9 / pattern, 4),
         },
+        "windows_ms_per_step": [round(v, 4) for v in walls32],
         "fp64": {
             "mlups": round(mlups64, 1), "ms_per_step": round(ms64, 4),
             "kernel_ms": round(kms64, 4),
             "hbm_frac": round(bytes64 / (kms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "fp32_over_fp64_speedup": round(ms64 / ms32, 3),
-            "u_rel_l2_fp32_vs_fp64": du,
         },
+        "fp32_vs_fp64": {"steps": int(t_cmp), "u_rel_l2": du},
         "adjoint": {
             "steps": A, "checkpoint_every": args.every,
-            "objective": "mean u_x over the window", "J": J,
-            "dJ_dg": [float(v) for v in g["g"]],
-            "ms_per_step_checkpointed_forward": round(ms_fwd_ckpt, 4),
-            "ms_per_step_reverse": round(ms_adj, 4),
-            "fwd_adjoint_mlups": round(N / ((ms_fwd_ckpt + ms_adj) * 1e-3) / 1e6, 1),
-            "adjoint_over_forward_cost": round((ms_fwd_ckpt + ms_adj) / ms32, 3),
+            "objective": "mean u_x over the window; gradients in g and every gamma",
+            "fp32": {
+                "J": J32, "dJ_dg": [float(v) for v in g32["g"]],
+                "ms_per_step_checkpointed_forward": round(ms_fwd_ckpt, 4),
+                "ms_per_step_reverse": round(ms_adj, 4),
+                "fwd_adjoint_mlups": round(N / ((ms_fwd_ckpt + ms_adj) * 1e-3) / 1e6, 1),
+                "reverse_over_forward": round(ms_adj / ms32, 3),
+                "forward_plus_reverse_over_forward": round((ms_fwd_ckpt + ms_adj) / ms32, 3),
+                "every_step_kept": {
+                    "ms_per_step_forward": round(ms_fwd_all, 4),
+                    "ms_per_step_reverse": round(ms_adj_all, 4),
+                    "reverse_over_forward": round(ms_adj_all / ms32, 3)},
+            },
+            "fp64": {
+                "J": J64, "dJ_dg": [float(v) for v in g64["g"]],
+                "ms_per_step_checkpointed_forward": round(ms64_fwd_ckpt, 4),
+                "ms_per_step_reverse": round(ms64_adj, 4),
+                "fwd_adjoint_mlups": round(N / ((ms64_fwd_ckpt + ms64_adj) * 1e-3) / 1e6, 1),
+                "reverse_over_forward": round(ms64_adj / ms64, 3),
+                "forward_plus_reverse_over_forward": round((ms64_fwd_ckpt + ms64_adj) / ms64, 3),
+            },
+            "fp32_vs_fp64": {"J_rel": abs(J32 - J64) / abs(J64),
+                             "dJ_dg_rel": _rel(g32["g"], g64["g"])},
             # the adjoint's access pattern without arithmetic, raw bytes
             # per second (the adjoint kernels' own ceiling)
             "pattern_ceiling_GBps": round(adj_pattern, 1),
-            "every_step_kept": {
-                "ms_per_step_forward": round(ms_fwd_all, 4),
-                "ms_per_step_reverse": round(ms_adj_all, 4),
-                "adjoint_over_forward_cost": round((ms_fwd_all + ms_adj_all) / ms32, 3)},
         },
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(geom, w)
-    if args.all:
+    if not args.no_configs:
         del geom
-        out["per_config"] = all_configs(binding, torch)
+        _progress("forward step of every workload")
+        out["per_config"] = per_config_forward(binding, torch)
+    if not args.no_cpu:
+        _progress("CPU oracle")
+        geom = w.geometry()
+        one = cpu_baseline(geom, w, steps=args.cpu_steps, threads=1)
+        many = cpu_baseline(geom, w, steps=args.cpu_steps)
+        out["cpu_baseline"] = dict(one, all_cores=many, **host_info())
+    if args.all:
+        out["all_configs"] = all_configs(binding, torch)
     print(json.dumps(out), flush=True)
 
 
