@@ -142,6 +142,37 @@ def adjoint_pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
     return 3 * 19 * n * 4 / (ms * 1e-3) / 1e9
 
 
+def pattern_study(binding, torch, shape=(256, 256, 256), reps=20):
+    """Raw GB/s of D3Q19 access patterns without arithmetic, FP32 and FP64:
+    the step's pull (planes of N nodes), the same pull with node blocks of
+    B nodes holding their Q planes, the in-place two-pass (AA) pattern, the
+    adjoint's pattern, and a flat copy of the same bytes."""
+    n = int(np.prod(shape))
+    out = {"shape": list(shape)}
+    for prec, dt, s in (("fp32", torch.float32, 4), ("fp64", torch.float64, 8)):
+        a = torch.ones(19 * n, dtype=dt, device="cuda")
+        b = torch.empty_like(a)
+        raw = 2 * 19 * n * s
+        r = {}
+        ms = binding.stream_copy(b, a, 19 * n * s, mode=0, reps=reps)
+        r["copy"] = round(raw / (ms * 1e-3) / 1e9, 1)
+        r["pull_planes"] = round(raw / (binding.pull_pattern_copy("D3Q19", prec, b, a, shape, reps=reps) * 1e-3) / 1e9, 1)
+        for B in (64, 256, 1024, 4096, 16384):
+            ms = binding.blocked_pull_pattern_copy("D3Q19", prec, B, b, a, shape, reps=reps)
+            r["pull_blocks_%d" % B] = round(raw / (ms * 1e-3) / 1e9, 1)
+        e_ms, o_ms = binding.aa_pattern_copy("D3Q19", prec, a, shape, reps=reps)
+        r["aa_even"] = round(raw / (e_ms * 1e-3) / 1e9, 1)
+        r["aa_odd"] = round(raw / (o_ms * 1e-3) / 1e9, 1)
+        r["aa_two_pass"] = round(2 * raw / ((e_ms + o_ms) * 1e-3) / 1e9, 1)
+        c = torch.empty_like(a)
+        ms = binding.adjoint_pattern_copy("D3Q19", prec, c, a, b, shape, reps=reps)
+        r["adjoint_pattern"] = round(3 * 19 * n * s / (ms * 1e-3) / 1e9, 1)
+        del a, b, c
+        torch.cuda.empty_cache()
+        out[prec] = r
+    return out
+
+
 def cpu_baseline(geom, w, slab=48, steps=20, threads=None):
     """Oracle on the z-slab 0 <= z < slab of the same workload (window mode:
     reads across the slab faces see NaN and are not used; slab=None runs the
@@ -557,9 +588,9 @@ def main():
         print(json.dumps(copy_ceiling(binding, torch, reps=args.steps, all_modes=True)))
         return
     if args.only == "pattern":
-        # the step's and the adjoint's access patterns without arithmetic
-        print(json.dumps({"pull_pattern_GBps": round(pattern_ceiling(binding, torch, reps=args.steps), 1),
-                          "adjoint_pattern_GBps": round(adjoint_pattern_ceiling(binding, torch, reps=args.steps), 1)}))
+        # the step's and the adjoint's access patterns without arithmetic,
+        # and the alternatives to the step's layout and addressing
+        print(json.dumps(pattern_study(binding, torch, reps=args.steps)))
         return
 
     w = configs.c3_spheres(args.n)

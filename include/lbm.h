@@ -149,6 +149,26 @@ int lbm_set_geometry(lbm_t *h, const uint8_t *solid, int64_t n_links,
  * Either pointer may be NULL to keep the current values. */
 int lbm_update_links(lbm_t *h, const double *q, const double *wall_u);
 
+/* Collision operators of Remark (1) (the boundary scheme does not depend on
+ * the collision): every row of the moment matrix is even or odd under
+ * e -> -e, so the two-relaxation-time operator (TRT) -- relaxing the halves
+ * (f_i + f_ibar)/2 at s_plus and (f_i - f_ibar)/2 at s_minus -- is exactly the
+ * MRT operator with rate s_plus on the even rows and s_minus on the odd ones;
+ * BGK is s_minus = s_plus.  For TRT, s_plus = s_nu and s_minus follows from
+ * (1/s_plus - 1/2)(1/s_minus - 1/2) = magic (magic > 0; 3/16 is the common
+ * choice).  The conserved rows get s_nu too (their non-equilibrium part is
+ * zero, so any value is equivalent). */
+enum { LBM_COLLISION_BGK = 1, LBM_COLLISION_TRT = 2 };
+
+/* The Q rates of such an operator, in the lattice's moment-row order, into
+ * s_out (no GPU needed).  s_nu in (0, 2); magic is ignored for BGK.
+ * Errors: EINVAL. */
+int lbm_collision_rates(int lattice, int kind, double s_nu, double magic, double *s_out);
+
+/* Set the rates of a handle to those of lbm_collision_rates() (as
+ * lbm_set_parameters() would).  Errors: EINVAL. */
+int lbm_set_collision(lbm_t *h, int kind, double s_nu, double magic);
+
 /* Replace the relaxation rates (Q values, same rules as lbm_create) or the
  * body force (D values); either pointer may be NULL.  Takes effect at the
  * next step; the state is kept.  Errors: EINVAL. */
@@ -240,8 +260,10 @@ int lbm_objective(lbm_t *h, double *J);
  * buffers with the current state, without a copy, and the snapshot buffers
  * are kept for the next run with the same snapshot count.  Memory: ceil(n /
  * every) snapshots, plus `every` replay states and two adjoint arrays
- * allocated by lbm_adjoint(), all of lbm_state_bytes().  The objective
- * accumulates as in lbm_step.  Errors: ESTATE, EINVAL, ENOMEM. */
+ * allocated by lbm_adjoint(), all of lbm_state_bytes(); with the rate
+ * gradients off and the single-node scheme, also ceil(n / every) + `every`
+ * velocity fields of D values per node (see lbm_set_rate_gradient).  The
+ * objective accumulates as in lbm_step.  Errors: ESTATE, EINVAL, ENOMEM. */
 int lbm_run_checkpointed(lbm_t *h, int64_t n, int64_t every);
 
 /* Reverse sweep over the last lbm_run_checkpointed() run: for each segment
@@ -272,7 +294,12 @@ int64_t lbm_adjoint_remaining(const lbm_t *h);
 
 /* Choose whether lbm_adjoint() accumulates dJ/ds for the relaxation rates
  * (a block reduction of Q extra sums per step; default on).  When off,
- * lbm_grad() reports zeros for ds. */
+ * lbm_grad() reports zeros for ds, and with the single-node scheme the
+ * reverse sweep reads the velocity u of each forward state instead of the
+ * state itself (the equilibrium's Jacobian depends on u alone): the
+ * checkpointed run then records u of each segment's last state and the
+ * replay the others (D values per node each; the gradients are the same).
+ * Takes effect at the next lbm_run_checkpointed() and sweep. */
 int lbm_set_rate_gradient(lbm_t *h, int on);
 
 /* Gradients of J from the last lbm_adjoint(), in double: dq[k] = dJ/dgamma_k

@@ -52,6 +52,17 @@ int lbm_adjoint_pattern_copy(int lattice, int precision, void *dst_dev, const vo
                              const void *lam_src_dev, int64_t nx, int64_t ny, int64_t nz,
                              int32_t reps, double *ms_per_copy);
 
+/* The step's pull pattern (as lbm_pull_pattern_copy) in a blocked layout:
+ * consecutive blocks of `block` nodes (a power of two from 64 to 2^20 that
+ * divides nx*ny*nz), each holding its Q planes one after the other -- the
+ * element (i, n) at (n / block) * Q * block + i * block + n % block.  Used to
+ * measure whether a layout other than whole planes moves the pattern faster.
+ * Buffers as lbm_pull_pattern_copy; the whole array must stay below 4 GiB.
+ * Errors as lbm_pull_pattern_copy. */
+int lbm_blocked_pull_pattern_copy(int lattice, int precision, int32_t block, void *dst_dev,
+                                  const void *src_dev, int64_t nx, int64_t ny, int64_t nz,
+                                  int32_t reps, double *ms_per_copy);
+
 /* The in-place two-pass ("AA") access pattern on one buffer of Q planes of
  * nx*ny*nz elements (stride nx*ny*nz, periodic in every axis), one node per
  * thread in 256-thread blocks, non-temporal stores.  Even pass: node x reads

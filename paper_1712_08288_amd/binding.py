@@ -47,6 +47,8 @@ _adj_remaining = _sig("lbm_adjoint_remaining", C.c_int64, [_p])
 _set_geometry = _sig("lbm_set_geometry", _i, [_p, _p, _i64, _p, _p, _p, _p, _p])
 _update_links = _sig("lbm_update_links", _i, [_p, _p, _p])
 _set_params = _sig("lbm_set_parameters", _i, [_p, _p, _p])
+_coll_rates = _sig("lbm_collision_rates", _i, [_i, _i, _d, _d, _p])
+_set_collision = _sig("lbm_set_collision", _i, [_p, _i, _d, _d])
 _init = _sig("lbm_init", _i, [_p, _p, _p])
 _init_dev = _sig("lbm_init_deviation", _i, [_p, _p])
 _step = _sig("lbm_step", _i, [_p, _i64])
@@ -78,12 +80,15 @@ _stream_copy = _sig("lbm_stream_copy", _i, [_p, _p, _i64, _i32, _i32, _p])
 _pull_pattern = _sig("lbm_pull_pattern_copy", _i, [_i, _i, _p, _p, _i64, _i64, _i64, _i32, _p])
 _adj_pattern = _sig("lbm_adjoint_pattern_copy", _i, [_i, _i, _p, _p, _p, _i64, _i64, _i64, _i32, _p])
 _aa_pattern = _sig("lbm_aa_pattern_copy", _i, [_i, _i, _p, _i64, _i64, _i64, _i32, _p, _p])
+_blocked_pattern = _sig("lbm_blocked_pull_pattern_copy", _i,
+                        [_i, _i, _i32, _p, _p, _i64, _i64, _i64, _i32, _p])
 _last_err = _sig("lbm_last_error", C.c_char_p, [_p])
 _destroy = _sig("lbm_destroy", _i, [_p])
 
 EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_decay",
             "lbm_set_x_boundary",
-            "lbm_set_geometry", "lbm_update_links", "lbm_set_parameters", "lbm_init",
+            "lbm_set_geometry", "lbm_update_links", "lbm_set_parameters",
+            "lbm_collision_rates", "lbm_set_collision", "lbm_init",
             "lbm_init_deviation", "lbm_step", "lbm_time", "lbm_moments",
             "lbm_get_distribution", "lbm_reduce", "lbm_reduce_noalloc", "lbm_force",
             "lbm_state_bytes", "lbm_get_state", "lbm_set_state",
@@ -94,7 +99,7 @@ EXPORTED = ["lbm_create", "lbm_set_scheme", "lbm_set_two_node", "lbm_set_wall_de
             "lbm_last_step_ms", "lbm_last_error", "lbm_destroy"]
 # measurement probes (include/lbm_probe.h)
 EXPORTED_PROBES = ["lbm_stream_copy", "lbm_pull_pattern_copy", "lbm_adjoint_pattern_copy",
-                   "lbm_aa_pattern_copy"]
+                   "lbm_aa_pattern_copy", "lbm_blocked_pull_pattern_copy"]
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1, "D3Q15": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1}
@@ -139,27 +144,18 @@ def lattice_info(lattice):
     return e.astype(np.int64), w, M
 
 
-def collision_rates(lattice, kind, s_nu, magic=3.0 / 16.0):
-    """Rates that turn the library's MRT collision into BGK or TRT (the
-    boundary scheme does not depend on the collision operator, Remark (1)).
+COLLISIONS = {"bgk": 1, "trt": 2}
 
-    Every moment row is even or odd under e -> -e, so relaxing the even rows
-    at s_plus = s_nu and the odd rows at s_minus is exactly the TRT operator
-    on the halves (f_i +- f_ibar)/2; s_minus follows from the "magic"
-    product (1/s_plus - 1/2)(1/s_minus - 1/2) = magic.  BGK is s_minus =
-    s_plus.  The conserved rows get s_nu as well (their non-equilibrium part
-    is zero, so any value is equivalent)."""
-    e, _, M = lattice_info(lattice)
-    Q = len(e)
-    opp = np.array([int(np.nonzero((e == -e[i]).all(1))[0][0]) for i in range(Q)])
-    even = np.all(M[:, opp] == M, axis=1)
-    if kind == "bgk":
-        s_minus = s_nu
-    elif kind == "trt":
-        s_minus = 1.0 / (0.5 + magic / (1.0 / s_nu - 0.5))
-    else:
-        raise ValueError("kind must be 'bgk' or 'trt'")
-    return np.where(even, float(s_nu), float(s_minus))
+
+def collision_rates(lattice, kind, s_nu, magic=3.0 / 16.0):
+    """MRT rates that realise the BGK or TRT operator (lbm_collision_rates;
+    Remark (1): the boundary scheme does not depend on the collision)."""
+    e, _, _ = lattice_info(lattice)
+    s = np.zeros(len(e))
+    rc = _coll_rates(LATTICES[lattice], COLLISIONS[kind], float(s_nu), float(magic), _ptr(s))
+    if rc:
+        raise LBMError(rc, "collision_rates")
+    return s
 
 
 def stream_copy(dst, src, nbytes, mode=0, reps=10):
@@ -200,6 +196,21 @@ def adjoint_pattern_copy(lattice, precision, dst, f_src, lam_src, shape, reps=10
                       int(nx), int(ny), int(nz), int(reps), _ptr(ms))
     if rc:
         raise LBMError(rc, "adjoint_pattern_copy")
+    return float(ms[0])
+
+
+def blocked_pull_pattern_copy(lattice, precision, block, dst, src, shape, reps=10):
+    """Time the pull pattern in a layout of node blocks of `block` nodes that
+    each hold their Q planes (dst/src: at least Q * nx*ny*nz elements).
+    Returns ms per pass."""
+    d = dst.data_ptr() if hasattr(dst, "data_ptr") else int(dst)
+    s = src.data_ptr() if hasattr(src, "data_ptr") else int(src)
+    nx, ny, nz = (tuple(shape) + (1, 1))[:3]
+    ms = np.zeros(1)
+    rc = _blocked_pattern(LATTICES[lattice], PRECISIONS[precision], int(block), _p(d), _p(s),
+                          int(nx), int(ny), int(nz), int(reps), _ptr(ms))
+    if rc:
+        raise LBMError(rc, "blocked_pull_pattern_copy")
     return float(ms[0])
 
 
@@ -297,6 +308,11 @@ class Solver:
         s = _f64(s, self.Q) if s is not None else None
         g = _f64(np.asarray(g, float)[: self.D], self.D) if g is not None else None
         self._chk(_set_params(self._h, _ptr(s), _ptr(g)), "set_parameters")
+
+    def set_collision(self, kind, s_nu, magic=3.0 / 16.0):
+        """BGK or TRT through the MRT rates (lbm_set_collision)."""
+        self._chk(_set_collision(self._h, COLLISIONS[kind], float(s_nu), float(magic)),
+                  "set_collision")
 
     def counts(self):
         nf, nl = _i64(), _i64()

@@ -122,7 +122,7 @@ __device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w, int& opp
 // contribution of its adjoint a_k to mu and to lambda(y, t), and f_ibar(y, t)
 // staged for the link-gradient kernel.  Used for links past the 64th of a
 // wave (the first 64 go through the wave's LDS slab).
-template <class L, class T, int i>
+template <class L, class T, int i, bool UM>
 __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict__ lam_in,
                                                 const T* __restrict__ nxt,
                                                 uint32_t n, uint32_t S,
@@ -143,7 +143,7 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
     mu[i] += (T)(c.c2 * ak);
     mu[ib] += (T)(c.c3 * ak);
     sg.ak[k] = ak;
-    sg.fib[k] = f[ib];
+    if constexpr (!UM) sg.fib[k] = f[ib];
     sg.fpi[k] = ld(nxt + (size_t)i * S, n);
     sg.fpib[k] = ld(nxt + (size_t)ib * S, n);
 }
@@ -171,12 +171,16 @@ __device__ __forceinline__ void own_link_bypass(uint32_t k, const T* __restrict_
 //   dJ/dgamma_k += a_k (dc1 f_ibar(y,t) + dc2 f'_i(y,t) + dc3 f'_ibar(y,t) + dwall),
 //   dJ/dphi_k   += a_k c4 3 w_i rho0 e_i,
 // from the values the adjoint kernel staged (coalesced, one thread per link).
-template <class L, class T>
+// UM (the adjoint ran on recorded velocities, without the forward state):
+// f_ibar(y, t) is read here from the forward state at t instead -- the pull
+// of direction ibar at y, or the link slot when (y, ibar) is a cut link too.
+template <class L, class T, int XB, bool UM>
 __global__ void __launch_bounds__(BX)
 k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
             const LinkDeriv* __restrict__ lkderiv, const double* __restrict__ lkc4,
             double* __restrict__ gq, double* __restrict__ gphi, uint32_t n_links,
-            Params<L, T> p) {
+            Params<L, T> p, const T* __restrict__ A, const T* __restrict__ wa,
+            const int32_t* __restrict__ lknode, NodeMeta nm, Grid g) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     if (k >= n_links) return;
     int e[3] = {0, 0, 0}, ib = 0;
@@ -184,7 +188,15 @@ k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
     dir_data<L>(lkdir[k], e, w, ib);
     const double ak = sg.ak[k];
     const LinkDeriv dc = lkderiv[k];
-    gq[k] += ak * (dc.d1 * (double)sg.fib[k] + dc.d2 * (double)sg.fpi[k] +
+    T fib;
+    if constexpr (UM) {
+        const uint32_t n = (uint32_t)lknode[k];
+        const NodeLinks nl = node_links(nm, g, nm.info[n], n);
+        fib = ((nl.mask >> ib) & 1u) ? wa[link_index(nl, ib)] : pull_one<L, T, XB>(A, g, p, n, ib);
+    } else {
+        fib = sg.fib[k];
+    }
+    gq[k] += ak * (dc.d1 * (double)fib + dc.d2 * (double)sg.fpi[k] +
                    dc.d3 * (double)sg.fpib[k] + p.wall_scale * dc.dwall);
     const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * p.wall_scale * ak;
 #pragma unroll
@@ -230,15 +242,21 @@ __device__ __forceinline__ NodePos node_of_wave(const Grid& g, const WaveList& w
 // through LDS; the node's lane hands back f_ibar(y, t), which the link
 // lanes stage for the link-gradient kernel together with a_k and the
 // forward step's stored f'_i(y, t), f'_ibar(y, t).
-template <class L, class T, int XB, bool WANT_DS, bool ROWS>
+// UM: the forward state enters the collision adjoint only through its
+// velocity (the equilibrium's Jacobian depends on u alone), so with the rate
+// gradients off the kernel reads u(y, t) recorded by the forward step (D
+// planes of U) instead of pulling the Q populations of f(y, t).
+template <class L, class T, int XB, bool WANT_DS, bool ROWS, bool UM>
 __global__ void __launch_bounds__(BX)
-k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict__ nxt,
+k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict__ wa,
+          const T* __restrict__ nxt,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
           NodeMeta nm, WaveList wl, const LinkCoef* __restrict__ lkcoef,
           const int32_t* __restrict__ lktag,
           const uint8_t* __restrict__ lkdir, const int32_t* __restrict__ lknode,
           LinkStaging<T> sg, double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
     constexpr int Q = L::Q, D = L::D, NP = NPAIR<L>;
+    static_assert(!(UM && WANT_DS), "the rate gradients need the forward populations");
     constexpr int NC = D + Q;                 // layout of the per-block sums
     constexpr int NR = WANT_DS ? NC : D;      // columns reduced here
     __shared__ LinkStage<T> stage[BX / 64];
@@ -278,14 +296,18 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
         // loads that do not depend on the node's metadata: the planes of the
         // forward pull and the adjoint gathers lambda_i(y + e_i, t+1) (entries
         // of solid or absent neighbours are read and then discarded)
-        T f[Q], lg[Q];
+        T f[Q], lg[Q], uv[3] = {T(0), T(0), T(0)};
         const Push<XB> ps(g, pos);
         // plain waves are 64 fluid nodes inside the grid; in mixed waves the
         // lanes of 64-byte plane segments without fluid nodes neither read nor
         // write
         const bool live = !MX || (pos.in && lane_in_live_segment<T>(wx, lane));
         if (live) {
-            pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
+            if constexpr (UM) {
+                for (int a = 0; a < D; ++a) uv[a] = ld(U + (size_t)a * g.S, pos.n);
+            } else {
+                pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
+            }
             unroll<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 lg[i] = ld(lam_in + (size_t)i * g.S, i == 0 ? pos.n : ps.template dst<L, i>());
@@ -303,12 +325,20 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
         // holds the link slots.
         auto node = [&](auto plain_c, const NodeLinks& nl) {
             constexpr bool PLAIN = decltype(plain_c)::value;
-            // forward state f(y, t) and its velocity
+            // forward state f(y, t) and its velocity (UM: the recorded one)
             T sp[NP], dp[NP];
-            pair_split<L, T>(f, sp, dp);
-            T rho, j[3];
-            conserved_of<L, T>(f[0], sp, dp, rho, j);
-            const T u[3] = {j[0] * p.inv_rho0, j[1] * p.inv_rho0, j[2] * p.inv_rho0};
+            T rho = 0, j[3] = {0, 0, 0}, u[3];
+            if constexpr (UM) {
+                u[0] = uv[0];
+                u[1] = uv[1];
+                u[2] = uv[2];
+            } else {
+                pair_split<L, T>(f, sp, dp);
+                conserved_of<L, T>(f[0], sp, dp, rho, j);
+                u[0] = j[0] * p.inv_rho0;
+                u[1] = j[1] * p.inv_rho0;
+                u[2] = j[2] * p.inv_rho0;
+            }
 
             // mu_i(y) = dJ/df'_i(y): lambda_i(y + e_i, t+1) where that node pulls
             T mu[Q];
@@ -344,10 +374,11 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
                                 if (k < 64u) {
                                     mu[i] += st.v[0][k];
                                     mu[ib] += st.v[1][k];
-                                    st.v[0][k] = f[ib];
+                                    if constexpr (!UM) st.v[0][k] = f[ib];
                                 } else {
-                                    own_link_direct<L, T, i>(wbase + k, lam_in, nxt, pos.n, g.S,
-                                                             lkcoef, lktag, sg, p, a, f, mu);
+                                    own_link_direct<L, T, i, UM>(wbase + k, lam_in, nxt, pos.n,
+                                                                 g.S, lkcoef, lktag, sg, p, a, f,
+                                                                 mu);
                                 }
                             }
                             k += bit;
@@ -490,10 +521,12 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
             const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
             const bool sol = is_solid(info);
             const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, 0u);
-            // forward state: the link slots of the recorded step
-            const T wa0 = lane < nlw ? wa[wbase + lane] : T(0);
-            wave_link_values<L, T>(wa, wbase, lane, wa0, nl, st, f);
-            if (p.c1d) complete_two_node<L, T>(p.c1d + wbase, nl, f);
+            if constexpr (!UM) {
+                // forward state: the link slots of the recorded step
+                const T wa0 = lane < nlw ? wa[wbase + lane] : T(0);
+                wave_link_values<L, T>(wa, wbase, lane, wa0, nl, st, f);
+                if (p.c1d) complete_two_node<L, T>(p.c1d + wbase, nl, f);
+            }
             // link lanes: the pieces of mu and lambda(y, t) that a_k feeds
             if (link_lane) {
                 double dfx = 0.0;
@@ -512,7 +545,8 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ wa, const T* __restrict
             if (!sol) node(std::false_type{}, nl);
             wave_lds_sync();
             // link lanes: stage f_ibar(y, t) handed back by the node's lane
-            if (link_lane) sg.fib[kl] = st.v[0][lane];
+            if constexpr (!UM)
+                if (link_lane) sg.fib[kl] = st.v[0][lane];
             // the solid lanes store NaN (nothing reads lambda at solid nodes) so
             // that the wave writes whole lines of lam_out: partial lines cost
             // HBM read-modify-write cycles
@@ -612,7 +646,6 @@ static Grid adj_grid(const Engine& e) {
     // the adjoint kernels index waves and links, not blocks of a node launch
     g.nblocks = (uint32_t)((e.N + BX - 1) / BX);
     g.bpr = 0u;
-    g.chunk = 0u;
     return g;
 }
 
@@ -641,7 +674,8 @@ int64_t adjoint_blocks(const Engine& e) {
 }
 
 hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& next,
-                               const void* lam_in, void* lam_out, const AdjointObjective& obj) {
+                               const void* u_rec, const void* lam_in, void* lam_out,
+                               const AdjointObjective& obj) {
     const Grid g = adj_grid(e);
     const uint32_t wpr = e.nx % 64 == 0 ? (uint32_t)(e.nx / 64) : 0u;
     const WaveList waves{e.d_wact, (uint32_t)e.n_wact, wpr};
@@ -659,8 +693,13 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& n
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        auto kern = a.want_ds ? (wpr ? k_adjoint<L, T, XB, true, true> : k_adjoint<L, T, XB, true, false>)
-                              : (wpr ? k_adjoint<L, T, XB, false, true> : k_adjoint<L, T, XB, false, false>);
+        const bool um = u_rec != nullptr && !a.want_ds;
+        auto kern = a.want_ds ? (wpr ? k_adjoint<L, T, XB, true, true, false>
+                                     : k_adjoint<L, T, XB, true, false, false>)
+                    : um      ? (wpr ? k_adjoint<L, T, XB, false, true, true>
+                                     : k_adjoint<L, T, XB, false, false, true>)
+                              : (wpr ? k_adjoint<L, T, XB, false, true, false>
+                                     : k_adjoint<L, T, XB, false, false, false>);
         const Params<L, T> prm = adj_params<L, T>(e);
         // staging: [a_k: L doubles][f_ibar][f'_i][f'_ibar: L values of T each]
         const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
@@ -671,16 +710,20 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& n
         sg.fpib = sg.fpi + L1;
         if (waves.count)
             hipLaunchKernelGGL(kern, dim3(wave_blocks(waves.count)), dim3(BX), 0, e.stream,
-                               (const T*)fwd.f, (const T*)fwd.wa, (const T*)next.f,
+                               (const T*)fwd.f, (const T*)u_rec, (const T*)fwd.wa,
+                               (const T*)next.f,
                                (const T*)lam_in, (T*)lam_out,
                                NodeMeta{e.d_info, e.d_wave}, waves, e.d_lkcoef,
                                e.d_lktag, e.d_lkdir, e.d_lknode, sg,
                                e.d_gglob, g, prm, a);
         // per-link gradients, from what the mixed waves staged
-        if (e.n_links)
-            hipLaunchKernelGGL((k_link_grad<L, T>), dim3((unsigned)((e.n_links + BX - 1) / BX)),
-                               dim3(BX), 0, e.stream, sg, e.d_lkdir, e.d_lkderiv, e.d_lkc4,
-                               e.d_gq, e.d_gphi, (uint32_t)e.n_links, prm);
+        if (e.n_links) {
+            auto lkern = um ? k_link_grad<L, T, XB, true> : k_link_grad<L, T, XB, false>;
+            hipLaunchKernelGGL(lkern, dim3((unsigned)((e.n_links + BX - 1) / BX)), dim3(BX), 0,
+                               e.stream, sg, e.d_lkdir, e.d_lkderiv, e.d_lkc4, e.d_gq, e.d_gphi,
+                               (uint32_t)e.n_links, prm, (const T*)fwd.f, (const T*)fwd.wa,
+                               e.d_lknode, NodeMeta{e.d_info, e.d_wave}, g);
+        }
         return hipGetLastError();
     });
 }

@@ -25,8 +25,6 @@ struct lbm {
 
 namespace {
 
-constexpr int64_t kDefaultPadBytes = 0;
-
 int fail(lbm_t* h, int code, const std::string& msg) {
     if (h) h->e.err = msg;
     return code;
@@ -104,18 +102,33 @@ void free_snap(Snapshot& s) {
 }
 
 size_t f_bytes(const Engine& e) { return (size_t)e.Q * (size_t)e.S * e.elem; }
+size_t u_bytes(const Engine& e) { return (size_t)e.D * (size_t)e.S * e.elem; }
 
-// Stride between direction planes.  Planes whose byte size is a multiple of
-// a large power of two would start the Q concurrent streams of a pull at the
-// same offset modulo the memory channel interleave; a pad of a few cache
-// lines staggers them.  LBM_PLANE_PAD (values) overrides the default.
-int64_t plane_stride(int64_t N, size_t elem) {
-    int64_t pad = -1;
-    if (const char* v = std::getenv("LBM_PLANE_PAD")) pad = std::atoll(v);
-    if (pad < 0) pad = (int64_t)(kDefaultPadBytes / elem);
-    int64_t S = ((N + 63) / 64) * 64 + pad;
-    return S;
+// the reverse sweep can run on recorded velocities (see Engine::u_last)
+bool velocity_mode(const Engine& e) { return !e.want_ds && !e.two_node; }
+
+void free_list(std::vector<void*>& v) {
+    for (auto& p : v)
+        if (p) (void)hipFree(p);
+    v.clear();
 }
+
+int alloc_list(lbm_t* h, std::vector<void*>& v, size_t count, size_t bytes) {
+    if (v.size() == count) return LBM_OK;
+    free_list(v);
+    v.assign(count, nullptr);
+    for (auto& p : v)
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+            free_list(v);
+            return fail(h, LBM_ENOMEM, "device allocation of recorded velocities failed");
+        }
+    return LBM_OK;
+}
+
+// Stride between direction planes: N rounded up to whole waves (pads of
+// 128 B to 64 KB between planes measured no different).
+int64_t plane_stride(int64_t N) { return ((N + 63) / 64) * 64; }
 size_t wa_bytes(const Engine& e) {
     return (size_t)std::max<int64_t>(e.n_links, 1) * e.elem;
 }
@@ -275,6 +288,9 @@ void free_run(Engine& e) {
     for (auto& s : e.pool) free_snap(s);
     e.ckpt.clear();
     e.pool.clear();
+    free_list(e.u_last);
+    free_list(e.u_pool);
+    e.run_urec = false;
     for (auto& l : e.lam) {
         if (l) (void)hipFree(l);
         l = nullptr;
@@ -290,8 +306,10 @@ int zero(lbm_t* h, void* p, size_t bytes) {
 }
 
 // one forward step from buf[cur] into buf[cur^1] (or between given
-// snapshots), with the objective accumulated when `accumulate`
-int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumulate) {
+// snapshots), with the objective accumulated when `accumulate`; u_rec, when
+// given, receives the velocity of the state the step starts from
+int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumulate,
+                 void* u_rec = nullptr) {
     Engine& e = h->e;
     e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)e.t);
     lbe::StepObjective so;
@@ -313,7 +331,11 @@ int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumul
         so.a_in = e.obj_a_in;
         so.a_out = e.obj_a_out;
     }
-    HIPCHK(h, lbe::launch_step(e, in, out, so));
+    if (e.poison) {   // LBM_DEBUG: what the step does not write stays NaN
+        HIPCHK(h, lbe::launch_fill_nan(e, out.f, (size_t)e.Q * (size_t)e.S));
+        HIPCHK(h, lbe::launch_fill_nan(e, out.wa, (size_t)e.n_links));
+    }
+    HIPCHK(h, lbe::launch_step(e, in, out, so, u_rec));
     if (in_window && e.obj_kind == LBM_OBJ_FORCE_X)
         HIPCHK(h, lbe::launch_force_objective(e, out, e.d_obj_acc, e.obj_tag,
                                               1.0 / (double)(e.obj_t1 - e.obj_t0)));
@@ -342,6 +364,11 @@ int adjoint_begin(lbm_t* h) {
             l = nullptr;
             return fail(h, LBM_ENOMEM, "adjoint array allocation failed");
         }
+    }
+    e.adj_um = e.run_urec && velocity_mode(e);
+    if (e.adj_um && (rc = alloc_list(h, e.u_pool, (size_t)e.run_every, u_bytes(e)))) {
+        e.adj_um = false;
+        return rc;
     }
     if ((int64_t)e.pool.size() != e.run_every + 1) {
         for (auto& s : e.pool) free_snap(s);
@@ -383,6 +410,7 @@ int adjoint_steps(lbm_t* h, int64_t n) {
     Engine& e = h->e;
     const int64_t nseg = (int64_t)e.ckpt.size();
     const int64_t t_saved = e.t;
+    const bool um = e.adj_um;   // fixed for the whole sweep
     int lc = 0;   // lam[lc] holds lambda(t+1)
     int rc = LBM_OK;
     for (; n > 0 && e.adj_next >= 0; --n, --e.adj_next) {
@@ -403,7 +431,9 @@ int adjoint_steps(lbm_t* h, int64_t n) {
             const int64_t nrep = j + 1 == nseg ? len : len - 1;
             for (int64_t k = 0; k < nrep; ++k) {
                 e.t = t_seg + k;   // forward_step reads e.t for the objective window and wall data
-                if ((rc = forward_step(h, state(k), e.pool[k + 1], false))) break;
+                if ((rc = forward_step(h, state(k), e.pool[k + 1], false,
+                                       um ? e.u_pool[k] : nullptr)))
+                    break;
             }
             if (rc) break;
             e.adj_seg = j;
@@ -422,9 +452,15 @@ int adjoint_steps(lbm_t* h, int64_t n) {
         if (!in_w) ao.kind = LBM_OBJ_NONE;
         hipError_t st = hipSuccess;
         e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
-        if (e.two_node) st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
+        if (e.poison)   // LBM_DEBUG: lambda(t) slots the step does not write stay NaN
+            st = lbe::launch_fill_nan(e, e.lam[lc ^ 1], (size_t)e.Q * (size_t)e.S);
+        if (e.two_node && st == hipSuccess)
+            st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
         if (st == hipSuccess)
-            st = lbe::launch_adjoint_step(e, state(r), state(r + 1), e.lam[lc], e.lam[lc ^ 1], ao);
+            st = lbe::launch_adjoint_step(
+                e, state(r), state(r + 1),
+                !um ? nullptr : (r == len - 1 && j + 1 < nseg ? e.u_last[j] : e.u_pool[r]),
+                e.lam[lc], e.lam[lc ^ 1], ao);
         if (st != hipSuccess) {
             rc = fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));
             break;
@@ -476,12 +512,11 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
     e.nz = nz;
     e.N = N;
     e.elem = precision == LBM_FP64 ? 8 : 4;
-    e.S = plane_stride(N, e.elem);
+    e.S = plane_stride(N);
     if (e.S * (int64_t)e.elem >= (1LL << 32)) {
         delete h;
         return LBM_EINVAL;
     }
-    if (const char* v = std::getenv("LBM_XCD_REMAP")) e.xcd_remap = std::atoi(v) != 0;
     // launch-bound sizes replay graphs of 64 steps (LBM_GRAPH_STEPS overrides;
     // an even count, 0 disables)
     e.graph_steps = N <= (1LL << 20) ? 64 : 0;
@@ -489,6 +524,11 @@ int lbm_create(lbm_t** out, int lattice, int precision, int64_t nx, int64_t ny,
         const int gsteps = std::atoi(v);
         e.graph_steps = gsteps > 0 ? (gsteps + 1) / 2 * 2 : 0;
     }
+    // LBM_DEBUG=1: poison mode (every step's outputs are filled with NaN
+    // first, so a read of a slot the previous step did not write shows up
+    // as a non-finite reduction); steps are launched one by one
+    if (const char* v = std::getenv("LBM_DEBUG")) e.poison = std::atoi(v) != 0;
+    if (e.poison) e.graph_steps = 0;
     for (int k = 0; k < Q; ++k) e.s[k] = s[k];
     e.rho0 = rho0;
     for (int a = 0; a < 3; ++a) e.g[a] = (g && a < D) ? g[a] : 0.0;
@@ -689,6 +729,41 @@ int lbm_set_parameters(lbm_t* h, const double* s, const double* g) {
     if (g)
         for (int a = 0; a < e.D; ++a) e.g[a] = g[a];
     return LBM_OK;
+}
+
+int lbm_collision_rates(int lattice, int kind, double s_nu, double magic, double* s_out) {
+    if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19 && lattice != LBM_D3Q15) return LBM_EINVAL;
+    if (!s_out || !(s_nu > 0.0 && s_nu < 2.0)) return LBM_EINVAL;
+    if (kind != LBM_COLLISION_BGK && kind != LBM_COLLISION_TRT) return LBM_EINVAL;
+    double s_minus = s_nu;
+    if (kind == LBM_COLLISION_TRT) {
+        if (!(magic > 0.0) || !std::isfinite(magic)) return LBM_EINVAL;
+        s_minus = 1.0 / (0.5 + magic / (1.0 / s_nu - 0.5));
+    }
+    const int Q = lat_Q(lattice), D = lat_D(lattice);
+    for (int k = 0; k < Q; ++k) {
+        // row k is even when M[k][ibar] = M[k][i] for every direction i
+        bool even = true;
+        for (int i = 0; i < Q; ++i) {
+            int ib = 0;
+            for (int j = 0; j < Q; ++j) {
+                bool opp = true;
+                for (int a = 0; a < D; ++a) opp = opp && lat_e(lattice, j, a) == -lat_e(lattice, i, a);
+                if (opp) ib = j;
+            }
+            even = even && lat_M(lattice, k, ib) == lat_M(lattice, k, i);
+        }
+        s_out[k] = even ? s_nu : s_minus;
+    }
+    return LBM_OK;
+}
+
+int lbm_set_collision(lbm_t* h, int kind, double s_nu, double magic) {
+    if (!h) return LBM_EINVAL;
+    double s[19];
+    const int rc = lbm_collision_rates(h->e.lattice, kind, s_nu, magic, s);
+    if (rc) return fail(h, rc, "collision: kind must be BGK or TRT, s_nu in (0, 2), magic > 0");
+    return lbm_set_parameters(h, s, nullptr);
 }
 
 static int init_common(lbm_t* h, const double* df, const double* rho, const double* u) {
@@ -1018,6 +1093,16 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
     e.run_t0 = e.t;
     e.run_n = n;
     e.run_every = every;
+    // the velocity of each segment's last state, for a reverse sweep that
+    // reads velocities (the last segment's comes from its replay)
+    e.run_urec = velocity_mode(e);
+    if (e.run_urec) {
+        const int rc = alloc_list(h, e.u_last, (size_t)nck, u_bytes(e));
+        if (rc) {
+            e.run_urec = false;
+            return rc;
+        }
+    }
     // a checkpoint takes the current state's buffers (the state it must
     // keep) and hands its own, unused ones to the ping-pong pair: no copies
     drop_graphs(e);
@@ -1028,7 +1113,8 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
             std::swap(e.ckpt[s / every], e.buf[e.cur]);
             in = &e.ckpt[s / every];
         }
-        if ((rc = forward_step(h, *in, e.buf[e.cur ^ 1], true))) return rc;
+        void* urec = e.run_urec && (s + 1) % every == 0 && s + 1 < n ? e.u_last[s / every] : nullptr;
+        if ((rc = forward_step(h, *in, e.buf[e.cur ^ 1], true, urec))) return rc;
         e.cur ^= 1;
         ++e.t;
         e.stepped = true;

@@ -35,8 +35,8 @@ struct Engine {
     int device = 0;          // HIP device current at lbm_create
     int64_t nx = 0, ny = 0, nz = 0, N = 0;
     int64_t S = 0;           // stride (values) between direction planes, >= N
-    bool xcd_remap = false;  // deal contiguous row slabs to each XCD (measured slower)
     int graph_steps = 0;     // >0: replay captured graphs of this many steps
+    bool poison = false;     // LBM_DEBUG: outputs filled with NaN before each step
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // by starting buffer
     double s[19] = {0};
     double rho0 = 1.0;
@@ -98,6 +98,14 @@ struct Engine {
     std::vector<Snapshot> pool;         // replay pool, every + 1 states
     int64_t run_t0 = -1, run_n = 0, run_every = 0;
     void* lam[2] = {nullptr, nullptr};  // adjoint arrays (Q*N values of T)
+    // With the rate gradients off and the single-node scheme, the reverse
+    // sweep reads the velocity of each forward state (D planes of T) instead
+    // of the state itself: the checkpointed run records it for the last
+    // state of every segment but the last, the replay for the others.
+    bool run_urec = false;              // the last run recorded u_last
+    bool adj_um = false;                // the current sweep reads velocities
+    std::vector<void*> u_last;          // per segment: u at its last state
+    std::vector<void*> u_pool;          // per replayed state r of a segment
     double* d_gq = nullptr;             // dJ/dgamma per link
     double* d_gphi = nullptr;           // dJ/dphi per link (L*D)
     void* d_stage = nullptr;            // per link: values staged for the link gradients (4 L doubles)
@@ -138,8 +146,9 @@ struct StepObjective {
     double a_in = 0.0, a_out = 0.0;
 };
 
+// u_rec (optional): D planes of T receiving u(x, t) of the pulled state
 hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
-                       const StepObjective& obj);
+                       const StepObjective& obj, void* u_rec = nullptr);
 // initial state: df (Q*N, deviation) or fields rho (N), u (N*D); device pointers
 hipError_t launch_init(Engine& e, const double* df, const double* rho,
                        const double* u, const Snapshot& out);
@@ -160,6 +169,8 @@ hipError_t launch_force(Engine& e, const Snapshot& post, double* partials,
 // accumulate the x force on one tag into per-block accumulators
 hipError_t launch_force_objective(Engine& e, const Snapshot& post, double* acc,
                                   int tag, double weight);
+// LBM_DEBUG: fill n values of T (the handle's precision) at p with NaN
+hipError_t launch_fill_nan(Engine& e, void* p, size_t n);
 // out[c] = sum_b partials[b*cols + c], deterministic
 hipError_t launch_sum_blocks(Engine& e, const double* partials, int64_t rows,
                              int64_t cols, double* out);
@@ -183,8 +194,10 @@ struct AdjointObjective {
 };
 // One reverse step: lambda(t) from lambda(t+1) with the forward states at t
 // (`fwd`) and t+1 (`next`), accumulating the gradients.
+// u_rec: D planes of T with u(x, t) recorded by the forward step (only read
+// with the rate gradients off), or null to take it from `fwd`
 hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& next,
-                               const void* lam_in, void* lam_out,
+                               const void* u_rec, const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
 // per-link values (width doubles each) from the sorted order into the

@@ -7,6 +7,7 @@
 //                Eq. (213) during the previous step (the "write-ahead" slot).
 // Pulling f_i(x, t) = A_i(x - e_i) (+ seam term), or wa[k] on a cut link,
 // gives the pre-collision state of Eq. (21) at time t.
+#include <algorithm>
 #include <mutex>
 
 #include "engine.hpp"
@@ -89,15 +90,16 @@ __device__ __forceinline__ double objective_term(const StepObjective& ob, uint32
 // their own slots, which nothing reads: a full store keeps every written
 // cache line whole (partial lines cost HBM read-modify-write cycles).  Lanes
 // whose 64-byte segment of the planes holds no fluid node skip both.
-template <class L, class T, int XB, bool ROWS>
+// REC: also record the velocity u(x, t) of the pulled state into D planes
+// of u_rec (stride g.S; NaN at solid nodes), for the reverse sweep.
+template <class L, class T, int XB, bool ROWS, bool REC>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
        T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
-       Grid g, Params<L, T> p, StepObjective ob) {
+       Grid g, Params<L, T> p, StepObjective ob, T* __restrict__ u_rec) {
     __shared__ LinkStage<T> stage[BX / 64];
     const NodePos pos = node_of_thread<ROWS>(g);
-    uint32_t lb = blockIdx.x;
-    if (g.chunk) lb = (lb % NXCD) * g.chunk + lb / NXCD;
+    const uint32_t lb = blockIdx.x;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint2 wv = lb < g.nblocks ? nm.wave[lb * (BX / 64) + wid] : uint2{WAVE_IDLE, 0u};
     const uint32_t kind = wave_kind(wv);
@@ -112,6 +114,8 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             constexpr int i = decltype(I)::value;
             st_nt(B + (size_t)i * g.S, pos.n, f[i]);
         });
+        if constexpr (REC)
+            for (int a = 0; a < L::D; ++a) st_nt(u_rec + (size_t)a * g.S, pos.n, mac.u[a]);
     } else if (kind == WAVE_MIXED) {
         const uint32_t lane = threadIdx.x & 63u;
         const uint32_t nlw = wave_links(wv), wbase = wv.y;
@@ -144,6 +148,9 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
                 constexpr int i = decltype(I)::value;
                 st_nt(B + (size_t)i * g.S, pos.n, sol ? nan : f[i]);
             });
+            if constexpr (REC)
+                for (int a = 0; a < L::D; ++a)
+                    st_nt(u_rec + (size_t)a * g.S, pos.n, sol ? nan : mac.u[a]);
         }
         wave_link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0, p.wall_scale, wbase, nlw, lane,
                              stage[wid]);
@@ -272,8 +279,7 @@ k_mass(const T* __restrict__ A, const T* __restrict__ wa, NodeMeta nm,
             macc<L::E[i][2]>(j[2], v);
         });
     }
-    uint32_t b = blockIdx.x;
-    if (g.chunk) b = (b % NXCD) * g.chunk + b / NXCD;
+    const uint32_t b = blockIdx.x;
     double vals[4] = {r, j[0], j[1], j[2]};
     for (int c = 0; c < 1 + L::D; ++c) {
         const double s = block_sum(vals[c]);
@@ -406,6 +412,14 @@ k_force_obj(const T* __restrict__ B, const T* __restrict__ wa,
     if (threadIdx.x == 0) acc[blockIdx.x] += weight * s;
 }
 
+// NaN into n values (debug mode: slots a step leaves unwritten stay NaN)
+template <class T>
+__global__ void __launch_bounds__(BX) k_fill_nan(T* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * BX;
+    for (uint64_t i = (uint64_t)blockIdx.x * BX + threadIdx.x; i < n; i += stride)
+        p[i] = (T)__builtin_nan("");
+}
+
 // out[c] = sum over rows of partials[row*cols + c]; one block per column,
 // fixed summation order
 __global__ void __launch_bounds__(BX)
@@ -430,13 +444,10 @@ static Grid make_grid(const Engine& e) {
     g.S = (uint32_t)e.S;
     g.nblocks = (uint32_t)((e.N + BX - 1) / BX);
     g.bpr = e.nx % BX == 0 ? (uint32_t)(e.nx / BX) : 0u;
-    g.chunk = e.xcd_remap ? (g.nblocks + NXCD - 1) / NXCD : 0;
     return g;
 }
 
-unsigned launch_blocks(const Grid& g) {
-    return g.chunk ? g.chunk * NXCD : g.nblocks;
-}
+unsigned launch_blocks(const Grid& g) { return g.nblocks; }
 
 int64_t step_blocks(const Engine& e) {
     return make_grid(e).nblocks;
@@ -489,17 +500,18 @@ static hipError_t dispatch(const Engine& e, F&& f) {
 }
 
 hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
-                       const StepObjective& obj) {
+                       const StepObjective& obj, void* u_rec) {
     const Grid g = make_grid(e);
     return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        auto kern = g.bpr ? k_step<L, T, XB, true> : k_step<L, T, XB, false>;
+        auto kern = u_rec ? (g.bpr ? k_step<L, T, XB, true, true> : k_step<L, T, XB, false, true>)
+                          : (g.bpr ? k_step<L, T, XB, true, false> : k_step<L, T, XB, false, false>);
         hipLaunchKernelGGL(kern, dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
                            (T*)out.wa, meta(e), e.d_lkcoef, g,
-                           make_params<L, T>(e), obj);
+                           make_params<L, T>(e), obj, (T*)u_rec);
         return hipGetLastError();
     });
 }
@@ -596,6 +608,18 @@ hipError_t launch_force_objective(Engine& e, const Snapshot& post, double* acc,
                            make_params<L, T>(e), tag, weight, acc);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_fill_nan(Engine& e, void* p, size_t n) {
+    if (n == 0) return hipSuccess;
+    const unsigned nb = (unsigned)std::min<size_t>((n + BX - 1) / BX, 65536);
+    if (e.precision == 0)
+        hipLaunchKernelGGL(k_fill_nan<double>, dim3(nb), dim3(BX), 0, e.stream, (double*)p,
+                           (uint64_t)n);
+    else
+        hipLaunchKernelGGL(k_fill_nan<float>, dim3(nb), dim3(BX), 0, e.stream, (float*)p,
+                           (uint64_t)n);
+    return hipGetLastError();
 }
 
 hipError_t launch_sum_blocks(Engine& e, const double* partials, int64_t rows,

@@ -87,6 +87,31 @@ k_adjoint_pattern(const T* __restrict__ fsrc, const T* __restrict__ lsrc, T* __r
     });
 }
 
+// The pull pattern in a blocked layout: consecutive blocks of 2^lb nodes,
+// each holding its Q planes one after the other (element (i, n) at
+// (n >> lb) * (Q << lb) + (i << lb) + (n & (2^lb - 1))); otherwise as
+// k_pull_pattern.
+template <class L, class T>
+__global__ void __launch_bounds__(BX)
+k_blocked_pull_pattern(const T* __restrict__ src, T* __restrict__ dst, Grid g, uint32_t lb) {
+    const NodePos pos = node_of_thread(g);
+    if (!pos.in) return;
+    const Pull<XBC_PERIODIC> pl(g, pos);
+    const uint32_t mask = (1u << lb) - 1u;
+    auto at = [&](uint32_t i, uint32_t n) {
+        return (n >> lb) * ((uint32_t)L::Q << lb) + (i << lb) + (n & mask);
+    };
+    T v[L::Q];
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        v[i] = ld(src, at(i, pl.template src<L, i>()));
+    });
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        st_nt(dst, at(i, pos.n), v[i]);
+    });
+}
+
 // The in-place "AA" access pattern, one buffer, no arithmetic.  Even pass:
 // node x reads every plane at x and writes plane i's value into plane ibar at
 // x (node-local).  Odd pass: node x reads plane ibar at x - e_i and writes
@@ -175,7 +200,6 @@ int pattern_copy(int lattice, int precision, void* dst, const void* src, const v
     g.N = (uint32_t)N;
     g.S = (uint32_t)N;
     g.nblocks = (uint32_t)((N + lbe::BX - 1) / lbe::BX);
-    g.chunk = 0u;
     g.bpr = 0u;
     hipStream_t s;
     hipEvent_t e0, e1;
@@ -250,7 +274,6 @@ extern "C" int lbm_aa_pattern_copy(int lattice, int precision, void* buf, int64_
     g.N = (uint32_t)N;
     g.S = (uint32_t)N;
     g.nblocks = (uint32_t)((N + lbe::BX - 1) / lbe::BX);
-    g.chunk = 0u;
     g.bpr = 0u;
     hipStream_t s;
     hipEvent_t ev[3];
@@ -303,6 +326,65 @@ extern "C" int lbm_aa_pattern_copy(int lattice, int precision, void* buf, int64_
     if (ms_even) *ms_even = t_even / reps;
     if (ms_odd) *ms_odd = t_odd / reps;
     for (auto& e : ev) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
+extern "C" int lbm_blocked_pull_pattern_copy(int lattice, int precision, int32_t block,
+                                             void* dst, const void* src, int64_t nx, int64_t ny,
+                                             int64_t nz, int32_t reps, double* ms_per_copy) {
+    if (!dst || !src || nx < 1 || ny < 1 || nz < 1 || reps < 1) return LBM_EINVAL;
+    if (lattice < 0 || lattice > 2 || (precision != LBM_FP64 && precision != LBM_FP32))
+        return LBM_EINVAL;
+    if (lattice == LBM_D2Q9 && nz != 1) return LBM_EINVAL;
+    if (block < 64 || block > (1 << 20) || (block & (block - 1))) return LBM_EINVAL;
+    const int64_t N = nx * ny * nz;
+    const int Q = lattice == LBM_D2Q9 ? 9 : (lattice == LBM_D3Q15 ? 15 : 19);
+    const int64_t elem = precision == LBM_FP64 ? 8 : 4;
+    if (N % block != 0 || N >= (1LL << 31) || N * Q * elem >= (1LL << 32)) return LBM_EINVAL;
+    uint32_t lb = 0;
+    while ((1 << lb) < block) ++lb;
+    lbe::Grid g;
+    g.nx = (uint32_t)nx;
+    g.ny = (uint32_t)ny;
+    g.nz = (uint32_t)nz;
+    g.N = (uint32_t)N;
+    g.S = (uint32_t)N;
+    g.nblocks = (uint32_t)((N + lbe::BX - 1) / lbe::BX);
+    g.bpr = 0u;
+    hipStream_t s;
+    hipEvent_t e0, e1;
+    if (hipStreamCreate(&s) != hipSuccess) return LBM_EDEVICE;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return LBM_EDEVICE;
+    }
+    auto launch = [&]() {
+        auto go = [&](auto lat) {
+            using L = decltype(lat);
+            auto typed = [&](auto zero) {
+                using T = decltype(zero);
+                hipLaunchKernelGGL((lbe::k_blocked_pull_pattern<L, T>), dim3(g.nblocks),
+                                   dim3(lbe::BX), 0, s, (const T*)src, (T*)dst, g, lb);
+            };
+            if (precision == LBM_FP64) typed(0.0);
+            else typed(0.0f);
+        };
+        if (lattice == LBM_D2Q9) go(lbe::D2Q9{});
+        else if (lattice == LBM_D3Q15) go(lbe::D3Q15{});
+        else go(lbe::D3Q19{});
+    };
+    launch();   // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) launch();
+    (void)hipEventRecord(e1, s);
+    int rc = LBM_OK;
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) rc = LBM_EDEVICE;
+    float ms = 0.f;
+    if (rc == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = LBM_EDEVICE;
+    if (ms_per_copy) *ms_per_copy = ms / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(s);
     return rc;
 }

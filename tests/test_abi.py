@@ -79,3 +79,22 @@ def test_create_rejects_planes_of_4gib_or_more(binding):
     EINVAL = -1
     assert lib.lbm_create(ctypes.byref(h), 1, 1, 1024, 1024, 1024, s, 1.0, g) == EINVAL
     assert lib.lbm_create(ctypes.byref(h), 1, 0, 1024, 1024, 512, s, 1.0, g) == EINVAL
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q15", "D3Q19"])
+@pytest.mark.parametrize("kind", ["bgk", "trt"])
+def test_collision_rates_follow_the_row_parity(binding, lattice, kind):
+    """lbm_collision_rates (no GPU): even moment rows get s_nu, odd rows
+    s_minus from (1/s_nu - 1/2)(1/s_minus - 1/2) = magic (BGK: s_nu), with
+    the row parity taken from the oracle's own moment matrix."""
+    from oracle import lattice as L
+    lat = L.get(lattice)
+    even = np.all(lat.M[:, lat.opp] == lat.M, axis=1)
+    s_nu, magic = 1.3, 0.21
+    got = binding.collision_rates(lattice, kind, s_nu, magic)
+    s_minus = s_nu if kind == "bgk" else 1.0 / (0.5 + magic / (1.0 / s_nu - 0.5))
+    assert np.allclose(got, np.where(even, s_nu, s_minus), rtol=0, atol=1e-15)
+    if kind == "trt":
+        assert abs((1 / s_nu - 0.5) * (1 / got[~even][0] - 0.5) - magic) < 1e-14
+    with pytest.raises(binding.LBMError):
+        binding.collision_rates(lattice, kind, 2.0, magic)

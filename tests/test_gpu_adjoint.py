@@ -28,13 +28,18 @@ def _gpu():
     require_gpu()
 
 
-def _gpu_grad(geom, s, kw, obj, steps, every, df0, precision="fp64"):
+def _gpu_grad(geom, s, kw, obj, steps, every, df0, precision="fp64", rates=True):
+    """rates=False turns the rate gradients off; with the single-node scheme
+    the reverse sweep then reads recorded velocities instead of the forward
+    populations."""
     from paper_1712_08288_amd import binding
     sv = binding.solver_for(geom, s, precision=precision, g=kw.get("g"),
                             dp=kw.get("dp", 0.0), l_rule=kw.get("l_rule", "min"),
                             b=kw.get("b", 1.0), two_node=kw.get("two_node", False))
     if kw.get("wall_decay", 1.0) != 1.0:
         sv.set_wall_decay(kw["wall_decay"])
+    if not rates:
+        sv.set_rate_gradient(False)
     sv.init_deviation(df0)
     sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1, planes=obj.planes)
     sv.run_checkpointed(steps, every)
@@ -137,6 +142,77 @@ def test_adjoint_matches_oracle_reverse(case):
     sv.close()
 
 
+SINGLE_NODE = [c for c in CASES if not c[3].get("two_node", False)]
+
+
+@pytest.mark.parametrize("case", SINGLE_NODE, ids=[c[0] for c in SINGLE_NODE])
+def test_velocity_mode_matches_oracle_reverse(case):
+    """Rate gradients off: the reverse sweep reads the velocities the forward
+    steps recorded instead of pulling the forward populations.  Against the
+    oracle's reverse sweep at 1e-10, and against the population-reading sweep
+    of the same run (the same arithmetic on the same velocity)."""
+    name, mk_geom, mk_s, kw, obj, steps = case
+    geom, s = mk_geom(), mk_s()
+    print("case", name, flush=True)
+    Q = len(VELOCITIES[geom.lattice])
+    df0 = states.random_deviation(Q, geom.n_nodes, seed=3, amp=2e-3)
+    if geom.x_bc == "outflow":
+        df0 = states.outlet_consistent(df0, geom.shape, VELOCITIES[geom.lattice])
+    base = dict(kw)
+    g0 = base.pop("g", None)
+    o = Oracle(geom, s, g=g0, **base)
+    J_o, st = forward(o, o.init_deviation(df0), steps, obj)
+    r = reverse(o, st, obj)
+    sv, J, gu = _gpu_grad(geom, s, kw, obj, steps, 3, df0, rates=False)
+    sv.close()
+    sv, J2, gf = _gpu_grad(geom, s, kw, obj, steps, 3, df0)
+    sv.close()
+    assert J == J2
+    fl = geom.solid == 0
+    for key in ("q", "wall_u", "g"):
+        if r[key].size == 0:
+            continue
+        scale = max(np.abs(r[key]).max(), 1e-300)
+        assert np.abs(gu[key] - r[key]).max() <= 1e-10 * scale, key
+        assert np.abs(gu[key] - gf[key]).max() <= 1e-14 * scale, key
+    lam_scale = np.abs(r["lam0"][:, fl]).max()
+    assert np.abs(gu["lam0"][:, fl] - r["lam0"][:, fl]).max() <= 1e-10 * lam_scale
+    assert np.abs(gu["lam0"][:, fl] - gf["lam0"][:, fl]).max() <= 1e-14 * lam_scale
+    assert np.all(gu["s"] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_velocity_mode_is_independent_of_the_checkpoints(precision):
+    """Velocities recorded at segment ends (checkpointed run) and by the
+    replay (other states) cover every step for any interval, and the sweep
+    in uneven pieces equals the whole sweep, bit for bit."""
+    from paper_1712_08288_amd import binding
+    name, mk_geom, mk_s, kw, obj, steps = [c for c in CASES if c[0] == "d3q19_pdrop_seam"][0]
+    geom, s = mk_geom(), mk_s()
+    df0 = states.random_deviation(19, geom.n_nodes, seed=6, amp=2e-3)
+    out = []
+    for every in (1, 2, 4, steps, steps + 3):
+        sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, every, df0, precision=precision, rates=False)
+        out.append((J, gr))
+        sv.close()
+    for J, gr in out[1:]:
+        assert J == out[0][0]
+        for key in ("q", "wall_u", "g", "lam0"):
+            assert np.array_equal(gr[key], out[0][1][key]), key
+    sv = binding.solver_for(geom, s, precision=precision, dp=kw["dp"], l_rule=kw["l_rule"])
+    sv.set_rate_gradient(False)
+    sv.init_deviation(df0)
+    sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1, planes=obj.planes)
+    sv.run_checkpointed(steps, 4)
+    for piece in (3, 1, 2, steps):
+        sv.adjoint_step(piece)
+    gr = sv.grad()
+    gr["lam0"] = sv.get_adjoint()
+    for key in ("q", "wall_u", "g", "lam0"):
+        assert np.array_equal(gr[key], out[0][1][key]), key
+    sv.close()
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     name, mk_geom, mk_s, kw, obj, steps = CASES[0]
     geom, s = mk_geom(), mk_s()
@@ -236,6 +312,29 @@ def test_pressure_drop_gradient_against_central_differences():
     dsn = gr["s"][visc].sum()
     assert abs(fd - dsn) <= 1e-6 * abs(dsn), (fd, dsn)
     sv.close()
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[4]], ids=[CASES[1][0], CASES[4][0]])
+def test_debug_poison_mode_leaves_the_adjoint_unchanged(monkeypatch, case):
+    """With LBM_DEBUG=1 the replayed states and every lambda(t) array are
+    filled with NaN before they are written: the gradients and lambda(0)
+    must be bitwise those of the normal mode."""
+    name, mk_geom, mk_s, kw, obj, steps = case
+    geom, s = mk_geom(), mk_s()
+    Q = len(VELOCITIES[geom.lattice])
+    df0 = states.random_deviation(Q, geom.n_nodes, seed=4, amp=2e-3)
+    if geom.x_bc == "outflow":
+        df0 = states.outlet_consistent(df0, geom.shape, VELOCITIES[geom.lattice])
+    res = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("LBM_DEBUG", mode)
+        sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, 3, df0)
+        res[mode] = (J, gr)
+        sv.close()
+    monkeypatch.delenv("LBM_DEBUG", raising=False)
+    assert res["0"][0] == res["1"][0]
+    for key in ("q", "wall_u", "g", "s", "lam0"):
+        assert np.array_equal(res["0"][1][key], res["1"][1][key]), key
 
 
 @pytest.mark.parametrize("case", [CASES[2], [c for c in CASES if c[0] == "d3q19_meanux_rows256_seam"][0]],
