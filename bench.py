@@ -120,7 +120,8 @@ def pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
     plane read at the pull source, written at the node; D3Q19 FP32), raw
     bytes moved per second."""
     n = int(np.prod(shape))
-    a = torch.empty(19 * n, dtype=torch.float32, device="cuda").fill_(1.0)
+    a = torch.empty(binding.population_elements("D3Q19", shape), dtype=torch.float32,
+                    device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     ms = binding.pull_pattern_copy("D3Q19", "fp32", b, a, shape, reps=reps)
     del a, b
@@ -133,7 +134,8 @@ def adjoint_pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
     forward state pulled, the adjoint gathered from x + e_i, the result
     written; D3Q19 FP32), raw bytes moved per second."""
     n = int(np.prod(shape))
-    a = torch.empty(19 * n, dtype=torch.float32, device="cuda").fill_(1.0)
+    a = torch.empty(binding.population_elements("D3Q19", shape), dtype=torch.float32,
+                    device="cuda").fill_(1.0)
     b = torch.empty_like(a).fill_(2.0)
     c = torch.empty_like(a)
     ms = binding.adjoint_pattern_copy("D3Q19", "fp32", c, a, b, shape, reps=reps)
@@ -144,22 +146,23 @@ def adjoint_pattern_ceiling(binding, torch, shape=(256, 256, 256), reps=20):
 
 def pattern_study(binding, torch, shape=(256, 256, 256), reps=20):
     """Raw GB/s of D3Q19 access patterns without arithmetic, FP32 and FP64:
-    the step's pull (planes of N nodes), the same pull with node blocks of
-    B nodes holding their Q planes, the in-place two-pass (AA) pattern, the
-    adjoint's pattern, and a flat copy of the same bytes."""
+    the step's pull in the engine's layout (blocks of 2048 nodes holding
+    their Q direction runs), the same pull with blocks of B nodes (B = N:
+    one plane per direction), the in-place two-pass (AA) pattern on planes,
+    the adjoint's pattern, and a flat copy of the same bytes."""
     n = int(np.prod(shape))
     out = {"shape": list(shape)}
     for prec, dt, s in (("fp32", torch.float32, 4), ("fp64", torch.float64, 8)):
-        a = torch.ones(19 * n, dtype=dt, device="cuda")
+        a = torch.ones(binding.population_elements("D3Q19", shape), dtype=dt, device="cuda")
         b = torch.empty_like(a)
         raw = 2 * 19 * n * s
         r = {}
         ms = binding.stream_copy(b, a, 19 * n * s, mode=0, reps=reps)
         r["copy"] = round(raw / (ms * 1e-3) / 1e9, 1)
-        r["pull_planes"] = round(raw / (binding.pull_pattern_copy("D3Q19", prec, b, a, shape, reps=reps) * 1e-3) / 1e9, 1)
-        for B in (64, 256, 1024, 4096, 16384):
+        r["pull"] = round(raw / (binding.pull_pattern_copy("D3Q19", prec, b, a, shape, reps=reps) * 1e-3) / 1e9, 1)
+        for B in (256, 1024, 4096, 16384, n):
             ms = binding.blocked_pull_pattern_copy("D3Q19", prec, B, b, a, shape, reps=reps)
-            r["pull_blocks_%d" % B] = round(raw / (ms * 1e-3) / 1e9, 1)
+            r["pull_planes" if B == n else "pull_blocks_%d" % B] = round(raw / (ms * 1e-3) / 1e9, 1)
         e_ms, o_ms = binding.aa_pattern_copy("D3Q19", prec, a, shape, reps=reps)
         r["aa_even"] = round(raw / (e_ms * 1e-3) / 1e9, 1)
         r["aa_odd"] = round(raw / (o_ms * 1e-3) / 1e9, 1)
@@ -250,7 +253,7 @@ def pattern_rate(binding, torch, lattice, shape, prec, Q):
     this grid and precision (the kernel's own ceiling)."""
     n = int(np.prod(shape))
     dt = torch.float32 if prec == "fp32" else torch.float64
-    a = torch.ones(Q * n, dtype=dt, device="cuda")
+    a = torch.ones(binding.population_elements(lattice, shape), dtype=dt, device="cuda")
     b = torch.empty_like(a)
     ms = binding.pull_pattern_copy(lattice, prec, b, a, shape, reps=10)
     del a, b

@@ -170,10 +170,44 @@ def stream_copy(dst, src, nbytes, mode=0, reps=10):
     return float(ms[0])
 
 
+# Nodes per block of the population arrays: population i of node n is
+# element (n // B) * Q * B + i * B + n % B.
+POPULATION_BLOCK = 2048
+
+
+def population_elements(lattice, shape):
+    """Elements of one population array (distributions or adjoint) of this
+    lattice on an nx x ny x nz grid: Q * nx*ny*nz rounded up to whole
+    blocks of POPULATION_BLOCK nodes."""
+    Q = {"D2Q9": 9, "D3Q15": 15, "D3Q19": 19}[lattice]
+    n = int(np.prod((tuple(shape) + (1, 1))[:3]))
+    return Q * (-(-n // POPULATION_BLOCK) * POPULATION_BLOCK)
+
+
+def population_index(lattice, shape):
+    """Index array (Q, nx*ny*nz) of the element that holds population i of
+    node n in the blocked layout."""
+    Q = {"D2Q9": 9, "D3Q15": 15, "D3Q19": 19}[lattice]
+    n = np.arange(int(np.prod((tuple(shape) + (1, 1))[:3])), dtype=np.int64)
+    B = POPULATION_BLOCK
+    i = np.arange(Q, dtype=np.int64)[:, None]
+    return (n // B) * Q * B + i * B + n % B
+
+
+def _check_population_buffers(lattice, shape, *bufs):
+    need = population_elements(lattice, shape)
+    for t in bufs:
+        if hasattr(t, "numel") and t.numel() < need:
+            raise LBMError(-1, "population buffer of %d elements, %d needed"
+                           % (t.numel(), need))
+
+
 def pull_pattern_copy(lattice, precision, dst, src, shape, reps=10):
     """Time the step's pull pattern without arithmetic on a periodic
-    nx x ny x nz grid (dst/src: torch tensors or device pointers of at least
-    Q * nx*ny*nz elements).  Returns ms per pass."""
+    nx x ny x nz grid, in the engine's blocked population layout (dst/src:
+    torch tensors or device pointers of at least population_elements(lattice,
+    shape) elements).  Returns ms per pass."""
+    _check_population_buffers(lattice, shape, dst, src)
     d = dst.data_ptr() if hasattr(dst, "data_ptr") else int(dst)
     s = src.data_ptr() if hasattr(src, "data_ptr") else int(src)
     nx, ny, nz = (tuple(shape) + (1, 1))[:3]
@@ -187,8 +221,9 @@ def pull_pattern_copy(lattice, precision, dst, src, shape, reps=10):
 
 def adjoint_pattern_copy(lattice, precision, dst, f_src, lam_src, shape, reps=10):
     """Time the adjoint step's access pattern without arithmetic (f read at
-    x - e_i, lambda at x + e_i, their sum written at x).  Returns ms per
-    pass."""
+    x - e_i, lambda at x + e_i, their sum written at x; blocked population
+    layout, buffers as pull_pattern_copy).  Returns ms per pass."""
+    _check_population_buffers(lattice, shape, dst, f_src, lam_src)
     ptr = [t.data_ptr() if hasattr(t, "data_ptr") else int(t) for t in (dst, f_src, lam_src)]
     nx, ny, nz = (tuple(shape) + (1, 1))[:3]
     ms = np.zeros(1)
@@ -201,7 +236,8 @@ def adjoint_pattern_copy(lattice, precision, dst, f_src, lam_src, shape, reps=10
 
 def blocked_pull_pattern_copy(lattice, precision, block, dst, src, shape, reps=10):
     """Time the pull pattern in a layout of node blocks of `block` nodes that
-    each hold their Q planes (dst/src: at least Q * nx*ny*nz elements).
+    each hold their Q direction runs (dst/src: at least Q * nx*ny*nz
+    elements; block = nx*ny*nz is the one-plane-per-direction layout).
     Returns ms per pass."""
     d = dst.data_ptr() if hasattr(dst, "data_ptr") else int(dst)
     s = src.data_ptr() if hasattr(src, "data_ptr") else int(src)

@@ -125,14 +125,14 @@ __device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w, int& opp
 template <class L, class T, int i, bool UM>
 __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict__ lam_in,
                                                 const T* __restrict__ nxt,
-                                                uint32_t n, uint32_t S,
+                                                uint32_t n,
                                                 const LinkCoef* __restrict__ lkcoef,
                                                 const int32_t* __restrict__ lktag,
                                                 const LinkStaging<T>& sg,
                                                 const Params<L, T>& p, const AdjArgs& a,
                                                 const T (&f)[L::Q], T (&mu)[L::Q]) {
     constexpr int ib = TAB<L>.opp[i];
-    double ak = (double)ld(lam_in + (size_t)i * S, n);
+    double ak = (double)ldp<L::Q>(lam_in, i, n);
     if (a.obj_kind == 1 && L::E[i][0] != 0 && lktag[k] == a.obj_tag) {
         // drag: (e_ibar)_x (f'_ibar(y,t) + f_i(y,t+1))
         const double dfx = -(double)L::E[i][0] * a.w_force;
@@ -144,8 +144,8 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
     mu[ib] += (T)(c.c3 * ak);
     sg.ak[k] = ak;
     if constexpr (!UM) sg.fib[k] = f[ib];
-    sg.fpi[k] = ld(nxt + (size_t)i * S, n);
-    sg.fpib[k] = ld(nxt + (size_t)ib * S, n);
+    sg.fpi[k] = ldp<L::Q>(nxt, i, n);
+    sg.fpib[k] = ldp<L::Q>(nxt, ib, n);
 }
 
 // The terms of such a link that bypass the collision: c0 a_k onto
@@ -153,13 +153,13 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
 // moments are taken (a_k read again: these links are rare).
 template <class L, class T, int i>
 __device__ __forceinline__ void own_link_bypass(uint32_t k, const T* __restrict__ lam_in,
-                                                uint32_t n, uint32_t S,
+                                                uint32_t n,
                                                 const LinkCoef* __restrict__ lkcoef,
                                                 const int32_t* __restrict__ lktag,
                                                 const Params<L, T>& p, const AdjArgs& a,
                                                 T (&mu)[L::Q]) {
     constexpr int ib = TAB<L>.opp[i];
-    double ak = (double)ld(lam_in + (size_t)i * S, n);
+    double ak = (double)ldp<L::Q>(lam_in, i, n);
     if (a.obj_kind == 1 && L::E[i][0] != 0 && lktag[k] == a.obj_tag)
         ak += -(double)L::E[i][0] * a.w_force;
     mu[i] += (T)(p.c0 * ak);
@@ -172,15 +172,17 @@ __device__ __forceinline__ void own_link_bypass(uint32_t k, const T* __restrict_
 //   dJ/dphi_k   += a_k c4 3 w_i rho0 e_i,
 // from the values the adjoint kernel staged (coalesced, one thread per link).
 // UM (the adjoint ran on recorded velocities, without the forward state):
-// f_ibar(y, t) is read here from the forward state at t instead -- the pull
-// of direction ibar at y, or the link slot when (y, ibar) is a cut link too.
+// f_ibar(y, t) is read here from the forward state at t instead -- from the
+// node that the pull of direction ibar at y reads (plus the seam term), or
+// from the link slot when (y, ibar) is a cut link too (fib_src).
 template <class L, class T, int XB, bool UM>
 __global__ void __launch_bounds__(BX)
 k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
             const LinkDeriv* __restrict__ lkderiv, const double* __restrict__ lkc4,
             double* __restrict__ gq, double* __restrict__ gphi, uint32_t n_links,
             Params<L, T> p, const T* __restrict__ A, const T* __restrict__ wa,
-            const int32_t* __restrict__ lknode, NodeMeta nm, Grid g) {
+            const int32_t* __restrict__ lknode, const uint32_t* __restrict__ fib_src,
+            Grid g) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     if (k >= n_links) return;
     int e[3] = {0, 0, 0}, ib = 0;
@@ -190,9 +192,18 @@ k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
     const LinkDeriv dc = lkderiv[k];
     T fib;
     if constexpr (UM) {
-        const uint32_t n = (uint32_t)lknode[k];
-        const NodeLinks nl = node_links(nm, g, nm.info[n], n);
-        fib = ((nl.mask >> ib) & 1u) ? wa[link_index(nl, ib)] : pull_one<L, T, XB>(A, g, p, n, ib);
+        const uint32_t src = fib_src[k];
+        if (src >> 31) {
+            fib = wa[src & 0x7FFFFFFFu];
+        } else {
+            fib = ldp<L::Q>(A, ib, src);
+            if constexpr (XB == XBC_PRESSURE) {
+                // direction ibar = -e_i crossed the seam into x = 0 (+) or x = nx-1 (-)
+                const uint32_t x = (uint32_t)lknode[k] % g.nx;
+                if (e[0] == -1 && x == 0) fib += T(w) * p.drho;
+                else if (e[0] == 1 && x + 1 == g.nx) fib -= T(w) * p.drho;
+            }
+        }
     } else {
         fib = sg.fib[k];
     }
@@ -310,7 +321,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
             }
             unroll<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                lg[i] = ld(lam_in + (size_t)i * g.S, i == 0 ? pos.n : ps.template dst<L, i>());
+                lg[i] = ldp<Q>(lam_in, i, i == 0 ? pos.n : ps.template dst<L, i>());
             });
         } else {
             unroll<Q>([&](auto I) {
@@ -354,7 +365,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
                     if constexpr (XB == XBC_OUTFLOW && L::E[i][0] == -1) {
                         if (ps.x_out) {
                             const uint32_t n2 = ps.template dst_clamped<L, i>(pos.ix);
-                            if (!is_solid(nm.info[n2])) mu[i] += ld(lam_in + (size_t)i * g.S, n2);
+                            if (!is_solid(nm.info[n2])) mu[i] += ldp<Q>(lam_in, i, n2);
                         }
                     }
                 }
@@ -377,8 +388,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
                                     if constexpr (!UM) st.v[0][k] = f[ib];
                                 } else {
                                     own_link_direct<L, T, i, UM>(wbase + k, lam_in, nxt, pos.n,
-                                                                 g.S, lkcoef, lktag, sg, p, a, f,
-                                                                 mu);
+                                                                 lkcoef, lktag, sg, p, a, f, mu);
                                 }
                             }
                             k += bit;
@@ -429,7 +439,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
                                     mu[i] += st.v[2][k];
                                     mu[ib] += st.v[3][k];
                                 } else {
-                                    own_link_bypass<L, T, i>(wbase + k, lam_in, pos.n, g.S,
+                                    own_link_bypass<L, T, i>(wbase + k, lam_in, pos.n,
                                                              lkcoef, lktag, p, a, mu);
                                 }
                             }
@@ -477,7 +487,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
                 macc<L::E[jd][1]>(out, b[1]);
                 macc<L::E[jd][2]>(out, b[2]);
                 if (a.obj_kind == 2) macc<L::E[jd][0]>(out, wux);
-                st_nt(lam_out + (size_t)jd * g.S, pos.n, out);
+                stp_nt<Q>(lam_out, jd, pos.n, out);
             };
             finish(std::integral_constant<int, 0>{}, e0);
             unroll<NP>([&](auto P) {
@@ -514,9 +524,9 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
             if (link_lane) {
                 dir_data<L>(ld_dir, le, lw, lib);
                 c = lkcoef[kl];
-                ak = (double)lam_in[(size_t)ld_dir * g.S + ld_node];
-                sg.fpi[kl] = nxt[(size_t)ld_dir * g.S + ld_node];
-                sg.fpib[kl] = nxt[(size_t)lib * g.S + ld_node];
+                ak = (double)ldp<Q>(lam_in, ld_dir, ld_node);
+                sg.fpi[kl] = ldp<Q>(nxt, ld_dir, ld_node);
+                sg.fpib[kl] = ldp<Q>(nxt, lib, ld_node);
             }
             const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
             const bool sol = is_solid(info);
@@ -553,7 +563,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
             if (live && sol) {
                 unroll<Q>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    st_nt(lam_out + (size_t)i * g.S, pos.n, (T)__builtin_nan(""));
+                    stp_nt<Q>(lam_out, i, pos.n, (T)__builtin_nan(""));
                 });
             }
         }
@@ -594,9 +604,9 @@ k_two_node_pre(const T* __restrict__ A_next, T* __restrict__ lam_in,
             ex = L::E[ii][0];
         }
     });
-    double ak = (double)lam_in[(size_t)i * g.S + n];
+    double ak = (double)ldp<L::Q>(lam_in, i, n);
     if (a.obj_kind == 1 && ex != 0 && lktag[k] == a.obj_tag) ak += -(double)ex * a.w_force;
-    T* dst = lam_in + (size_t)ib * g.S + n;
+    T* dst = lam_in + pop_at<L::Q>(ib, n);
     *dst = (T)((double)*dst + c * ak);
     gq[k] += ak * d1d[k] * (double)pull_one<L, T, XB>(A_next, g, p, n, ib);
 }
@@ -604,12 +614,12 @@ k_two_node_pre(const T* __restrict__ A_next, T* __restrict__ lam_in,
 template <class L, class T>
 __global__ void __launch_bounds__(BX)
 k_adjoint_out(const T* __restrict__ lam, const uint32_t* __restrict__ info,
-              uint32_t N, uint32_t S, double* __restrict__ out) {
+              uint32_t N, double* __restrict__ out) {
     const uint32_t n = blockIdx.x * BX + threadIdx.x;
     if (n >= N) return;
     const bool fluid = !is_solid(info[n]);
     for (int i = 0; i < L::Q; ++i)
-        out[(size_t)i * N + n] = fluid ? (double)lam[(size_t)i * S + n] : 0.0;
+        out[(size_t)i * N + n] = fluid ? (double)ldp<L::Q>(lam, i, n) : 0.0;
 }
 
 // ----------------------------------------------------------------------------
@@ -722,7 +732,7 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& n
             hipLaunchKernelGGL(lkern, dim3((unsigned)((e.n_links + BX - 1) / BX)), dim3(BX), 0,
                                e.stream, sg, e.d_lkdir, e.d_lkderiv, e.d_lkc4, e.d_gq, e.d_gphi,
                                (uint32_t)e.n_links, prm, (const T*)fwd.f, (const T*)fwd.wa,
-                               e.d_lknode, NodeMeta{e.d_info, e.d_wave}, g);
+                               e.d_lknode, e.d_fib_src, g);
         }
         return hipGetLastError();
     });
@@ -775,7 +785,7 @@ hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out) {
         using L = decltype(lat);
         using T = decltype(prec);
         hipLaunchKernelGGL((k_adjoint_out<L, T>), dim3(nb), dim3(BX), 0, e.stream,
-                           (const T*)lam, e.d_info, (uint32_t)e.N, (uint32_t)e.S, out);
+                           (const T*)lam, e.d_info, (uint32_t)e.N, out);
         return hipGetLastError();
     });
 }

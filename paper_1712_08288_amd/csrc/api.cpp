@@ -126,9 +126,10 @@ int alloc_list(lbm_t* h, std::vector<void*>& v, size_t count, size_t bytes) {
     return LBM_OK;
 }
 
-// Stride between direction planes: N rounded up to whole waves (pads of
-// 128 B to 64 KB between planes measured no different).
-int64_t plane_stride(int64_t N) { return ((N + 63) / 64) * 64; }
+// Nodes per array slot count: N rounded up to whole population blocks (the
+// population arrays hold Q * S values in blocks of 2048 nodes; the velocity
+// records hold D planes of stride S).
+int64_t plane_stride(int64_t N) { return ((N + 2047) / 2048) * 2048; }
 size_t wa_bytes(const Engine& e) {
     return (size_t)std::max<int64_t>(e.n_links, 1) * e.elem;
 }
@@ -667,6 +668,7 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         if ((rc = upload(h, e.d_perm, p32.data(), p32.size()))) return rc;
     }
     if ((rc = upload(h, e.d_lktag, e.tag_h.data(), e.tag_h.size()))) return rc;
+    if ((rc = upload(h, e.d_fib_src, tab.fib_src.data(), tab.fib_src.size()))) return rc;
     if ((rc = upload_coefficients(h))) return rc;
     for (auto& b : e.buf) {
         if (b.wa) (void)hipFree(b.wa);
@@ -1276,6 +1278,7 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_lknode);
     free_dev(e.d_perm);
     free_dev(e.d_lktag);
+    free_dev(e.d_fib_src);
     free_dev(e.d_lkcoef);
     free_dev(e.d_lkderiv);
     free_dev(e.d_lkc4);

@@ -73,6 +73,7 @@ struct Engine {
     double wall_decay = 1.0;            // wall data phi(t) = phi(0) * wall_decay^t
     double wall_scale = 1.0;            // wall_decay^t of the step being launched
     std::vector<uint8_t> ibar_is_link;  // sorted link k: (x_f, ibar) is a link too
+    uint32_t* d_fib_src = nullptr;      // sorted link k: where f_ibar(x_f, t) is (geometry.hpp)
     double* d_lkc1d = nullptr;          // c1 applied at the next pull (Eq. (211)), else 0
     double* d_lkd1d = nullptr;          // its gamma derivative
 

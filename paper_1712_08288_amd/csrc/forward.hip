@@ -2,7 +2,9 @@
 // boundary scheme, initialisation, observation and reductions.
 //
 // Storage (per precision T = float or double, deviation form f - w rho0):
-//   A[i*N + n]   post-collision value f'_i(n, t-1) at every node n;
+//   A            post-collision value f'_i(n, t-1) at every node n, in
+//                blocks of NB nodes that each hold their Q direction runs
+//                (element pop_at<Q>(i, n));
 //   wa[k]        for cut link k = (x_f, i): the value f_i(x_f, t) produced by
 //                Eq. (213) during the previous step (the "write-ahead" slot).
 // Pulling f_i(x, t) = A_i(x - e_i) (+ seam term), or wa[k] on a cut link,
@@ -112,7 +114,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         if (ob.acc) obj_local = objective_term(ob, pos.ix, (double)mac.rho, (double)mac.u[0]);
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            st_nt(B + (size_t)i * g.S, pos.n, f[i]);
+            stp_nt<L::Q>(B, i, pos.n, f[i]);
         });
         if constexpr (REC)
             for (int a = 0; a < L::D; ++a) st_nt(u_rec + (size_t)a * g.S, pos.n, mac.u[a]);
@@ -146,7 +148,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             const T nan = (T)__builtin_nan("");
             unroll<L::Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                st_nt(B + (size_t)i * g.S, pos.n, sol ? nan : f[i]);
+                stp_nt<L::Q>(B, i, pos.n, sol ? nan : f[i]);
             });
             if constexpr (REC)
                 for (int a = 0; a < L::D; ++a)
@@ -210,7 +212,7 @@ k_init(const double* __restrict__ df, const double* __restrict__ rho,
             if (sg > 0) v -= seam_of<L, i, false>(p);
             else if (sg < 0) v += seam_of<L, i, false>(p);
         }
-        A[(size_t)i * g.S + pl.template src<L, i>()] = v;
+        A[pop_at<L::Q>(i, pl.template src<L, i>())] = v;
     });
 }
 
@@ -360,7 +362,7 @@ k_force(const T* __restrict__ B, const T* __restrict__ wa,
             constexpr int ii = decltype(I)::value;
             if (ii == i) {
                 constexpr int ib = TAB<L>.opp[ii];
-                fp_ib = (double)B[(size_t)ib * g.S + n];
+                fp_ib = (double)ldp<L::Q>(B, ib, n);
                 wi = L::W[ii];
                 ex = L::E[ii][0];
                 ey = L::E[ii][1];
@@ -400,7 +402,7 @@ k_force_obj(const T* __restrict__ B, const T* __restrict__ wa,
             if constexpr (L::E[ii][0] != 0) {
                 if (ii == i) {
                     constexpr int ib = TAB<L>.opp[ii];
-                    const double v = (double)B[(size_t)ib * g.S + n] +
+                    const double v = (double)ldp<L::Q>(B, ib, n) +
                                      link_value<L, T, XB>(B, wa, g, p, k, n, ii) +
                                      2.0 * L::W[ii] * p.rho0_d;
                     fx = -L::E[ii][0] * v;

@@ -22,7 +22,7 @@ enum XBC : int { XBC_PERIODIC = 0, XBC_PRESSURE = 1, XBC_OUTFLOW = 2 };
 struct Grid {
     uint32_t nx, ny, nz;
     uint32_t N;          // nx*ny*nz
-    uint32_t S;          // stride between direction planes of device arrays (>= N)
+    uint32_t S;          // N rounded up to whole population blocks (velocity-plane stride)
     uint32_t nblocks;    // blocks = ceil(N / BX)
     uint32_t bpr;        // nx / BX when BX divides nx (blocks per row), else 0
 };
@@ -336,6 +336,27 @@ __device__ __forceinline__ void st_nt(T* __restrict__ plane, uint32_t idx, T v) 
     __builtin_nontemporal_store(v, (T*)((char*)plane + idx * (uint32_t)sizeof(T)));
 }
 
+// Every array of Q populations per node (distributions, adjoint) is stored
+// in blocks of NB consecutive nodes, each holding its Q planes of NB values
+// one after the other: population i of node n lies at
+// (n / NB) * Q * NB + i * NB + n % NB.  On the 256^3 pull pattern this moves
+// 6.05 TB/s against 5.70 for whole planes of N values (blocks of 512 to
+// 65536 nodes measured; from 2048 up FP32 is flat, FP64 best at 2048-4096).
+constexpr uint32_t NB = 2048;
+
+template <int Q>
+__device__ __forceinline__ size_t pop_at(int i, uint32_t n) {
+    return (size_t)(n / NB) * ((size_t)NB * Q) + (size_t)i * NB + (n % NB);
+}
+template <int Q, class T>
+__device__ __forceinline__ T ldp(const T* __restrict__ a, int i, uint32_t n) {
+    return a[pop_at<Q>(i, n)];
+}
+template <int Q, class T>
+__device__ __forceinline__ void stp_nt(T* __restrict__ a, int i, uint32_t n, T v) {
+    __builtin_nontemporal_store(v, a + pop_at<Q>(i, n));
+}
+
 // ----------------------------------------------------------------------------
 // link lookup: the links of a node are contiguous, sorted by direction.
 struct NodeLinks {
@@ -414,7 +435,7 @@ __device__ __forceinline__ void pull_planes(const T* __restrict__ A, const Grid&
             f[i] = 0;
             return;
         }
-        f[i] = ld(A + (size_t)i * g.S, pl.template src<L, i>());
+        f[i] = ldp<L::Q>(A, i, pl.template src<L, i>());
         if constexpr (XB == XBC_PRESSURE && L::E[i][0] != 0) {
             const int sg = seam_sign<L, i>(pos.ix, g.nx);
             if (sg > 0) f[i] += seam_of<L, i, FTAB>(p);
@@ -538,7 +559,7 @@ __device__ __forceinline__ T pull_one(const T* __restrict__ A, const Grid& g,
             int sz = (int)iz - L::E[ii][2];
             sz = sz < 0 ? sz + (int)g.nz : (sz >= (int)g.nz ? sz - (int)g.nz : sz);
             const uint32_t src = (uint32_t)sx + g.nx * ((uint32_t)sy + g.ny * (uint32_t)sz);
-            out = A[(size_t)ii * g.S + src];
+            out = ldp<L::Q>(A, ii, src);
             if (XB == XBC_PRESSURE) {
                 if (sg > 0) out += seam_of<L, ii, false>(p);
                 else if (sg < 0) out -= seam_of<L, ii, false>(p);

@@ -23,11 +23,11 @@ k_pull_pattern(const T* __restrict__ src, T* __restrict__ dst, Grid g) {
     T v[L::Q];
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        v[i] = ld(src + (size_t)i * g.S, pl.template src<L, i>());
+        v[i] = ldp<L::Q>(src, i, pl.template src<L, i>());
     });
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        st_nt(dst + (size_t)i * g.S, pos.n, v[i]);
+        stp_nt<L::Q>(dst, i, pos.n, v[i]);
     });
 }
 
@@ -74,16 +74,16 @@ k_adjoint_pattern(const T* __restrict__ fsrc, const T* __restrict__ lsrc, T* __r
     T f[L::Q], lg[L::Q];
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        f[i] = ld(fsrc + (size_t)i * g.S, pl.template src<L, i>());
+        f[i] = ldp<L::Q>(fsrc, i, pl.template src<L, i>());
     });
     // x + e_i is the pull source of the opposite direction
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        lg[i] = ld(lsrc + (size_t)i * g.S, pl.template src<L, TAB<L>.opp[i]>());
+        lg[i] = ldp<L::Q>(lsrc, i, pl.template src<L, TAB<L>.opp[i]>());
     });
     unroll<L::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        st_nt(dst + (size_t)i * g.S, pos.n, f[i] + lg[i]);
+        stp_nt<L::Q>(dst, i, pos.n, f[i] + lg[i]);
     });
 }
 
@@ -337,7 +337,7 @@ extern "C" int lbm_blocked_pull_pattern_copy(int lattice, int precision, int32_t
     if (lattice < 0 || lattice > 2 || (precision != LBM_FP64 && precision != LBM_FP32))
         return LBM_EINVAL;
     if (lattice == LBM_D2Q9 && nz != 1) return LBM_EINVAL;
-    if (block < 64 || block > (1 << 20) || (block & (block - 1))) return LBM_EINVAL;
+    if (block < 64 || block > (1 << 30) || (block & (block - 1))) return LBM_EINVAL;
     const int64_t N = nx * ny * nz;
     const int Q = lattice == LBM_D2Q9 ? 9 : (lattice == LBM_D3Q15 ? 15 : 19);
     const int64_t elem = precision == LBM_FP64 ? 8 : 4;
