@@ -17,7 +17,8 @@
  * Units: lattice units, h = dt = c = 1, c_s^2 = 1/3.
  * Layout: node index n = x + nx*(y + ny*z), x fastest; 2D lattices have
  * nz = 1.  Distributions are handled as deviations from the rest state,
- * delta f_i = f_i - w_i rho0, stored structure-of-arrays [Q][N] on the GPU.
+ * delta f_i = f_i - w_i rho0, stored on the GPU in blocks of 2048 nodes that
+ * each hold their Q direction runs; host arrays use planes [Q][N].
  *
  * Conventions for every call:
  *  - Return value: LBM_OK (0) or a negative LBM_E* code; the message is
@@ -260,10 +261,16 @@ int lbm_objective(lbm_t *h, double *J);
  * buffers with the current state, without a copy, and the snapshot buffers
  * are kept for the next run with the same snapshot count.  Memory: ceil(n /
  * every) snapshots, plus `every` replay states and two adjoint arrays
- * allocated by lbm_adjoint(), all of lbm_state_bytes(); with the rate
- * gradients off and the single-node scheme, also ceil(n / every) + `every`
- * velocity fields of D values per node (see lbm_set_rate_gradient).  The
- * objective accumulates as in lbm_step.  Errors: ESTATE, EINVAL, ENOMEM. */
+ * allocated by lbm_adjoint(), all of lbm_state_bytes().
+ * With the rate gradients off and the single-node scheme the reverse sweep
+ * reads step records instead of states (see lbm_set_rate_gradient): the run
+ * records the last step of every segment, lbm_adjoint() replays each
+ * segment through two states recording its other steps, and every = 1
+ * records every step and keeps no snapshot (no replay at all).  A record is
+ * D values per node plus 3 per cut link, in the handle's precision; memory
+ * ceil(n / every) records, plus every - 1 records and two states for the
+ * replay when every > 1.  The objective accumulates as in lbm_step.
+ * Errors: ESTATE, EINVAL, ENOMEM. */
 int lbm_run_checkpointed(lbm_t *h, int64_t n, int64_t every);
 
 /* Reverse sweep over the last lbm_run_checkpointed() run: for each segment
@@ -295,11 +302,14 @@ int64_t lbm_adjoint_remaining(const lbm_t *h);
 /* Choose whether lbm_adjoint() accumulates dJ/ds for the relaxation rates
  * (a block reduction of Q extra sums per step; default on).  When off,
  * lbm_grad() reports zeros for ds, and with the single-node scheme the
- * reverse sweep reads the velocity u of each forward state instead of the
- * state itself (the equilibrium's Jacobian depends on u alone): the
- * checkpointed run then records u of each segment's last state and the
- * replay the others (D values per node each; the gradients are the same).
- * Takes effect at the next lbm_run_checkpointed() and sweep. */
+ * reverse sweep reads, for each forward step, a record of the velocity u of
+ * the state it starts from (the equilibrium's Jacobian depends on u alone)
+ * and of the three forward values of each cut link's gradient, f_ibar(x_f,
+ * t), f'_i(x_f, t) and f'_ibar(x_f, t), instead of the states (see
+ * lbm_run_checkpointed; the gradients are the same).  Takes effect at the
+ * next lbm_run_checkpointed(); a sweep over a run that kept records only
+ * (every = 1) while the rate gradients are on or Eq. (211) is selected
+ * fails with ESTATE. */
 int lbm_set_rate_gradient(lbm_t *h, int on);
 
 /* Gradients of J from the last lbm_adjoint(), in double: dq[k] = dJ/dgamma_k

@@ -119,9 +119,10 @@ __device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w, int& opp
 }
 
 // Link k = (y, i) of a mixed wave, handled by the lane of its node y: the
-// contribution of its adjoint a_k to mu and to lambda(y, t), and f_ibar(y, t)
-// staged for the link-gradient kernel.  Used for links past the 64th of a
-// wave (the first 64 go through the wave's LDS slab).
+// contribution of its adjoint a_k to mu and to lambda(y, t), and (unless UM:
+// the step record holds them) the forward values staged for the
+// link-gradient kernel.  Used for links past the 64th of a wave (the first
+// 64 go through the wave's LDS slab).
 template <class L, class T, int i, bool UM>
 __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict__ lam_in,
                                                 const T* __restrict__ nxt,
@@ -143,9 +144,11 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
     mu[i] += (T)(c.c2 * ak);
     mu[ib] += (T)(c.c3 * ak);
     sg.ak[k] = ak;
-    if constexpr (!UM) sg.fib[k] = f[ib];
-    sg.fpi[k] = ldp<L::Q>(nxt, i, n);
-    sg.fpib[k] = ldp<L::Q>(nxt, ib, n);
+    if constexpr (!UM) {
+        sg.fib[k] = f[ib];
+        sg.fpi[k] = ldp<L::Q>(nxt, i, n);
+        sg.fpib[k] = ldp<L::Q>(nxt, ib, n);
+    }
 }
 
 // The terms of such a link that bypass the collision: c0 a_k onto
@@ -170,19 +173,14 @@ __device__ __forceinline__ void own_link_bypass(uint32_t k, const T* __restrict_
 // of f_i(y, t+1) (plus the drag term):
 //   dJ/dgamma_k += a_k (dc1 f_ibar(y,t) + dc2 f'_i(y,t) + dc3 f'_ibar(y,t) + dwall),
 //   dJ/dphi_k   += a_k c4 3 w_i rho0 e_i,
-// from the values the adjoint kernel staged (coalesced, one thread per link).
-// UM (the adjoint ran on recorded velocities, without the forward state):
-// f_ibar(y, t) is read here from the forward state at t instead -- from the
-// node that the pull of direction ibar at y reads (plus the seam term), or
-// from the link slot when (y, ibar) is a cut link too (fib_src).
-template <class L, class T, int XB, bool UM>
+// from the values the adjoint kernel staged, or (a sweep on step records)
+// from the forward step's record (coalesced, one thread per link).
+template <class L, class T>
 __global__ void __launch_bounds__(BX)
 k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
             const LinkDeriv* __restrict__ lkderiv, const double* __restrict__ lkc4,
             double* __restrict__ gq, double* __restrict__ gphi, uint32_t n_links,
-            Params<L, T> p, const T* __restrict__ A, const T* __restrict__ wa,
-            const int32_t* __restrict__ lknode, const uint32_t* __restrict__ fib_src,
-            Grid g) {
+            Params<L, T> p) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     if (k >= n_links) return;
     int e[3] = {0, 0, 0}, ib = 0;
@@ -190,24 +188,7 @@ k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
     dir_data<L>(lkdir[k], e, w, ib);
     const double ak = sg.ak[k];
     const LinkDeriv dc = lkderiv[k];
-    T fib;
-    if constexpr (UM) {
-        const uint32_t src = fib_src[k];
-        if (src >> 31) {
-            fib = wa[src & 0x7FFFFFFFu];
-        } else {
-            fib = ldp<L::Q>(A, ib, src);
-            if constexpr (XB == XBC_PRESSURE) {
-                // direction ibar = -e_i crossed the seam into x = 0 (+) or x = nx-1 (-)
-                const uint32_t x = (uint32_t)lknode[k] % g.nx;
-                if (e[0] == -1 && x == 0) fib += T(w) * p.drho;
-                else if (e[0] == 1 && x + 1 == g.nx) fib -= T(w) * p.drho;
-            }
-        }
-    } else {
-        fib = sg.fib[k];
-    }
-    gq[k] += ak * (dc.d1 * (double)fib + dc.d2 * (double)sg.fpi[k] +
+    gq[k] += ak * (dc.d1 * (double)sg.fib[k] + dc.d2 * (double)sg.fpi[k] +
                    dc.d3 * (double)sg.fpib[k] + p.wall_scale * dc.dwall);
     const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * p.wall_scale * ak;
 #pragma unroll
@@ -256,7 +237,9 @@ __device__ __forceinline__ NodePos node_of_wave(const Grid& g, const WaveList& w
 // UM: the forward state enters the collision adjoint only through its
 // velocity (the equilibrium's Jacobian depends on u alone), so with the rate
 // gradients off the kernel reads u(y, t) recorded by the forward step (D
-// planes of U) instead of pulling the Q populations of f(y, t).
+// planes of U) instead of pulling the Q populations of f(y, t), and the
+// link values of the gradients come from the same step record: A, wa and
+// nxt are not read.
 template <class L, class T, int XB, bool WANT_DS, bool ROWS, bool UM>
 __global__ void __launch_bounds__(BX)
 k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict__ wa,
@@ -525,8 +508,10 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
                 dir_data<L>(ld_dir, le, lw, lib);
                 c = lkcoef[kl];
                 ak = (double)ldp<Q>(lam_in, ld_dir, ld_node);
-                sg.fpi[kl] = ldp<Q>(nxt, ld_dir, ld_node);
-                sg.fpib[kl] = ldp<Q>(nxt, lib, ld_node);
+                if constexpr (!UM) {
+                    sg.fpi[kl] = ldp<Q>(nxt, ld_dir, ld_node);
+                    sg.fpib[kl] = ldp<Q>(nxt, lib, ld_node);
+                }
             }
             const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
             const bool sol = is_solid(info);
@@ -683,8 +668,8 @@ int64_t adjoint_blocks(const Engine& e) {
     return std::max<int64_t>(1, (int64_t)wave_blocks(e.n_wact));
 }
 
-hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& next,
-                               const void* u_rec, const void* lam_in, void* lam_out,
+hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* next,
+                               const void* rec, const void* lam_in, void* lam_out,
                                const AdjointObjective& obj) {
     const Grid g = adj_grid(e);
     const uint32_t wpr = e.nx % 64 == 0 ? (uint32_t)(e.nx / 64) : 0u;
@@ -703,7 +688,8 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& n
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        const bool um = u_rec != nullptr && !a.want_ds;
+        const bool um = rec != nullptr && !a.want_ds;
+        if (!um && (!fwd || !next)) return hipErrorInvalidValue;
         auto kern = a.want_ds ? (wpr ? k_adjoint<L, T, XB, true, true, false>
                                      : k_adjoint<L, T, XB, true, false, false>)
                     : um      ? (wpr ? k_adjoint<L, T, XB, false, true, true>
@@ -711,29 +697,33 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& n
                               : (wpr ? k_adjoint<L, T, XB, false, true, false>
                                      : k_adjoint<L, T, XB, false, false, false>);
         const Params<L, T> prm = adj_params<L, T>(e);
-        // staging: [a_k: L doubles][f_ibar][f'_i][f'_ibar: L values of T each]
+        // staging: [a_k: L doubles][f_ibar][f'_i][f'_ibar: L values of T each];
+        // on step records the forward values come from the record
         const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
         LinkStaging<T> sg;
         sg.ak = (double*)e.d_stage;
         sg.fib = (T*)(sg.ak + L1);
         sg.fpi = sg.fib + L1;
         sg.fpib = sg.fpi + L1;
+        const StepRecord<T> r = um ? record_at<T>(e, rec) : StepRecord<T>{};
+        if (um) {
+            sg.fib = r.fib;
+            sg.fpi = r.fpi;
+            sg.fpib = r.fpib;
+        }
         if (waves.count)
             hipLaunchKernelGGL(kern, dim3(wave_blocks(waves.count)), dim3(BX), 0, e.stream,
-                               (const T*)fwd.f, (const T*)u_rec, (const T*)fwd.wa,
-                               (const T*)next.f,
+                               um ? nullptr : (const T*)fwd->f, (const T*)r.u,
+                               um ? nullptr : (const T*)fwd->wa, um ? nullptr : (const T*)next->f,
                                (const T*)lam_in, (T*)lam_out,
                                NodeMeta{e.d_info, e.d_wave}, waves, e.d_lkcoef,
                                e.d_lktag, e.d_lkdir, e.d_lknode, sg,
                                e.d_gglob, g, prm, a);
         // per-link gradients, from what the mixed waves staged
-        if (e.n_links) {
-            auto lkern = um ? k_link_grad<L, T, XB, true> : k_link_grad<L, T, XB, false>;
-            hipLaunchKernelGGL(lkern, dim3((unsigned)((e.n_links + BX - 1) / BX)), dim3(BX), 0,
-                               e.stream, sg, e.d_lkdir, e.d_lkderiv, e.d_lkc4, e.d_gq, e.d_gphi,
-                               (uint32_t)e.n_links, prm, (const T*)fwd.f, (const T*)fwd.wa,
-                               e.d_lknode, e.d_fib_src, g);
-        }
+        if (e.n_links)
+            hipLaunchKernelGGL((k_link_grad<L, T>), dim3((unsigned)((e.n_links + BX - 1) / BX)),
+                               dim3(BX), 0, e.stream, sg, e.d_lkdir, e.d_lkderiv, e.d_lkc4,
+                               e.d_gq, e.d_gphi, (uint32_t)e.n_links, prm);
         return hipGetLastError();
     });
 }

@@ -102,9 +102,10 @@ void free_snap(Snapshot& s) {
 }
 
 size_t f_bytes(const Engine& e) { return (size_t)e.Q * (size_t)e.S * e.elem; }
-size_t u_bytes(const Engine& e) { return (size_t)e.D * (size_t)e.S * e.elem; }
+size_t rec_bytes(const Engine& e) { return (size_t)lbe::record_values(e) * e.elem; }
 
-// the reverse sweep can run on recorded velocities (see Engine::u_last)
+// the reverse sweep can run on step records instead of the forward states
+// (see Engine::rec_last)
 bool velocity_mode(const Engine& e) { return !e.want_ds && !e.two_node; }
 
 void free_list(std::vector<void*>& v) {
@@ -121,7 +122,7 @@ int alloc_list(lbm_t* h, std::vector<void*>& v, size_t count, size_t bytes) {
         if (hipMalloc(&p, bytes) != hipSuccess) {
             p = nullptr;
             free_list(v);
-            return fail(h, LBM_ENOMEM, "device allocation of recorded velocities failed");
+            return fail(h, LBM_ENOMEM, "device allocation of step records failed");
         }
     return LBM_OK;
 }
@@ -289,8 +290,8 @@ void free_run(Engine& e) {
     for (auto& s : e.pool) free_snap(s);
     e.ckpt.clear();
     e.pool.clear();
-    free_list(e.u_last);
-    free_list(e.u_pool);
+    free_list(e.rec_last);
+    free_list(e.rec_pool);
     e.run_urec = false;
     for (auto& l : e.lam) {
         if (l) (void)hipFree(l);
@@ -307,10 +308,11 @@ int zero(lbm_t* h, void* p, size_t bytes) {
 }
 
 // one forward step from buf[cur] into buf[cur^1] (or between given
-// snapshots), with the objective accumulated when `accumulate`; u_rec, when
-// given, receives the velocity of the state the step starts from
+// snapshots), with the objective accumulated when `accumulate`; rec, when
+// given, receives the step record (velocity of the state the step starts
+// from, link values)
 int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumulate,
-                 void* u_rec = nullptr) {
+                 void* rec = nullptr) {
     Engine& e = h->e;
     e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)e.t);
     lbe::StepObjective so;
@@ -335,8 +337,9 @@ int forward_step(lbm_t* h, const Snapshot& in, const Snapshot& out, bool accumul
     if (e.poison) {   // LBM_DEBUG: what the step does not write stays NaN
         HIPCHK(h, lbe::launch_fill_nan(e, out.f, (size_t)e.Q * (size_t)e.S));
         HIPCHK(h, lbe::launch_fill_nan(e, out.wa, (size_t)e.n_links));
+        if (rec) HIPCHK(h, lbe::launch_fill_nan(e, rec, (size_t)lbe::record_values(e)));
     }
-    HIPCHK(h, lbe::launch_step(e, in, out, so, u_rec));
+    HIPCHK(h, lbe::launch_step(e, in, out, so, rec));
     if (in_window && e.obj_kind == LBM_OBJ_FORCE_X)
         HIPCHK(h, lbe::launch_force_objective(e, out, e.d_obj_acc, e.obj_tag,
                                               1.0 / (double)(e.obj_t1 - e.obj_t0)));
@@ -356,8 +359,12 @@ namespace {
 
 int adjoint_begin(lbm_t* h) {
     Engine& e = h->e;
-    if (e.run_t0 < 0 || e.ckpt.empty())
-        return fail(h, LBM_ESTATE, "no checkpointed run to reverse");
+    if (e.run_t0 < 0) return fail(h, LBM_ESTATE, "no checkpointed run to reverse");
+    e.adj_um = e.run_urec && velocity_mode(e);
+    if (e.ckpt.empty() && !e.adj_um)
+        return fail(h, LBM_ESTATE,
+                    "the run kept step records only (rate gradients off, single-node scheme); "
+                    "run it again with the current settings");
     int rc;
     const size_t lam_bytes = f_bytes(e);
     for (auto& l : e.lam) {
@@ -366,19 +373,20 @@ int adjoint_begin(lbm_t* h) {
             return fail(h, LBM_ENOMEM, "adjoint array allocation failed");
         }
     }
-    e.adj_um = e.run_urec && velocity_mode(e);
-    if (e.adj_um && (rc = alloc_list(h, e.u_pool, (size_t)e.run_every, u_bytes(e)))) {
-        e.adj_um = false;
+    // on step records the replay of a segment records its steps but the
+    // last (the run recorded that one) through two ping-pong states;
+    // otherwise pool[r] holds the replayed state r of a segment (state 0 is
+    // the checkpoint itself, so pool[0] stays empty)
+    if (e.adj_um && e.run_every > 1 &&
+        (rc = alloc_list(h, e.rec_pool, (size_t)(e.run_every - 1), rec_bytes(e))))
         return rc;
-    }
-    if ((int64_t)e.pool.size() != e.run_every + 1) {
+    const size_t npool = e.adj_um ? (e.run_every > 1 ? 2 : 0) : (size_t)e.run_every + 1;
+    if (e.pool.size() != npool) {
         for (auto& s : e.pool) free_snap(s);
-        // pool[r] holds the replayed state r of a segment; state 0 is the
-        // checkpoint itself, so pool[0] stays empty
-        e.pool.assign(e.run_every + 1, Snapshot{});
-        for (size_t k = 1; k < e.pool.size(); ++k)
-            if ((rc = alloc_snap(h, e.pool[k]))) return rc;
+        e.pool.assign(npool, Snapshot{});
     }
+    for (size_t k = e.adj_um ? 0 : 1; k < e.pool.size(); ++k)
+        if (!e.pool[k].f && (rc = alloc_snap(h, e.pool[k]))) return rc;
     const int NC = e.D + e.Q;
     const int64_t nb = lbe::adjoint_blocks(e);
     const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
@@ -409,7 +417,7 @@ int adjoint_begin(lbm_t* h) {
 // n more reverse steps (fewer at the start of the run)
 int adjoint_steps(lbm_t* h, int64_t n) {
     Engine& e = h->e;
-    const int64_t nseg = (int64_t)e.ckpt.size();
+    const int64_t nseg = (e.run_n + e.run_every - 1) / e.run_every;
     const int64_t t_saved = e.t;
     const bool um = e.adj_um;   // fixed for the whole sweep
     int lc = 0;   // lam[lc] holds lambda(t+1)
@@ -429,12 +437,19 @@ int adjoint_steps(lbm_t* h, int64_t n) {
             return e.pool[k];
         };
         if (e.adj_seg != j) {
-            const int64_t nrep = j + 1 == nseg ? len : len - 1;
-            for (int64_t k = 0; k < nrep; ++k) {
-                e.t = t_seg + k;   // forward_step reads e.t for the objective window and wall data
-                if ((rc = forward_step(h, state(k), e.pool[k + 1], false,
-                                       um ? e.u_pool[k] : nullptr)))
-                    break;
+            if (um) {
+                // records of steps 0 .. len-2 (the run recorded step len-1)
+                for (int64_t k = 0; k + 1 < len; ++k) {
+                    e.t = t_seg + k;
+                    const Snapshot& in = k == 0 ? e.ckpt[j] : e.pool[(k - 1) & 1];
+                    if ((rc = forward_step(h, in, e.pool[k & 1], false, e.rec_pool[k]))) break;
+                }
+            } else {
+                const int64_t nrep = j + 1 == nseg ? len : len - 1;
+                for (int64_t k = 0; k < nrep; ++k) {
+                    e.t = t_seg + k;   // forward_step reads e.t for the objective window and wall data
+                    if ((rc = forward_step(h, state(k), e.pool[k + 1], false))) break;
+                }
             }
             if (rc) break;
             e.adj_seg = j;
@@ -457,11 +472,15 @@ int adjoint_steps(lbm_t* h, int64_t n) {
             st = lbe::launch_fill_nan(e, e.lam[lc ^ 1], (size_t)e.Q * (size_t)e.S);
         if (e.two_node && st == hipSuccess)
             st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
-        if (st == hipSuccess)
-            st = lbe::launch_adjoint_step(
-                e, state(r), state(r + 1),
-                !um ? nullptr : (r == len - 1 && j + 1 < nseg ? e.u_last[j] : e.u_pool[r]),
-                e.lam[lc], e.lam[lc ^ 1], ao);
+        if (st == hipSuccess) {
+            if (um)
+                st = lbe::launch_adjoint_step(e, nullptr, nullptr,
+                                              r == len - 1 ? e.rec_last[j] : e.rec_pool[r],
+                                              e.lam[lc], e.lam[lc ^ 1], ao);
+            else
+                st = lbe::launch_adjoint_step(e, &state(r), &state(r + 1), nullptr, e.lam[lc],
+                                              e.lam[lc ^ 1], ao);
+        }
         if (st != hipSuccess) {
             rc = fail(h, LBM_EDEVICE, std::string("adjoint step: ") + hipGetErrorString(st));
             break;
@@ -668,7 +687,6 @@ int lbm_set_geometry(lbm_t* h, const uint8_t* solid, int64_t n_links,
         if ((rc = upload(h, e.d_perm, p32.data(), p32.size()))) return rc;
     }
     if ((rc = upload(h, e.d_lktag, e.tag_h.data(), e.tag_h.size()))) return rc;
-    if ((rc = upload(h, e.d_fib_src, tab.fib_src.data(), tab.fib_src.size()))) return rc;
     if ((rc = upload_coefficients(h))) return rc;
     for (auto& b : e.buf) {
         if (b.wa) (void)hipFree(b.wa);
@@ -1079,8 +1097,11 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
     if (!e.initialized) return fail(h, LBM_ESTATE, "initialise before running");
     if (n < 1 || every < 1) return fail(h, LBM_EINVAL, "n and every must be >= 1");
     // checkpoint buffers are kept between runs of the same length (the
-    // replay pool and adjoint arrays are kept by lbm_adjoint likewise)
-    const int64_t nck = (n + every - 1) / every;
+    // replay pool and adjoint arrays are kept by lbm_adjoint likewise).  A
+    // sweep on step records needs no snapshot for segments of one step.
+    const int64_t nseg = (n + every - 1) / every;
+    const bool urec = velocity_mode(e);
+    const int64_t nck = urec && every == 1 ? 0 : nseg;
     if ((int64_t)e.ckpt.size() != nck) {
         free_run(e);
         e.ckpt.resize(nck);
@@ -1095,15 +1116,18 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
     e.run_t0 = e.t;
     e.run_n = n;
     e.run_every = every;
-    // the velocity of each segment's last state, for a reverse sweep that
-    // reads velocities (the last segment's comes from its replay)
-    e.run_urec = velocity_mode(e);
-    if (e.run_urec) {
-        const int rc = alloc_list(h, e.u_last, (size_t)nck, u_bytes(e));
+    // the record of each segment's last step, for a reverse sweep on step
+    // records (the replay records the others)
+    e.run_urec = urec;
+    if (urec) {
+        const int rc = alloc_list(h, e.rec_last, (size_t)nseg, rec_bytes(e));
         if (rc) {
             e.run_urec = false;
+            e.run_t0 = -1;
             return rc;
         }
+    } else {
+        free_list(e.rec_last);
     }
     // a checkpoint takes the current state's buffers (the state it must
     // keep) and hands its own, unused ones to the ping-pong pair: no copies
@@ -1111,12 +1135,13 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
     for (int64_t s = 0; s < n; ++s) {
         int rc;
         const Snapshot* in = &e.buf[e.cur];
-        if (s % every == 0) {
+        if (nck && s % every == 0) {
             std::swap(e.ckpt[s / every], e.buf[e.cur]);
             in = &e.ckpt[s / every];
         }
-        void* urec = e.run_urec && (s + 1) % every == 0 && s + 1 < n ? e.u_last[s / every] : nullptr;
-        if ((rc = forward_step(h, *in, e.buf[e.cur ^ 1], true, urec))) return rc;
+        const bool seg_end = (s + 1) % every == 0 || s + 1 == n;
+        void* rec = urec && seg_end ? e.rec_last[s / every] : nullptr;
+        if ((rc = forward_step(h, *in, e.buf[e.cur ^ 1], true, rec))) return rc;
         e.cur ^= 1;
         ++e.t;
         e.stepped = true;
@@ -1278,7 +1303,6 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_lknode);
     free_dev(e.d_perm);
     free_dev(e.d_lktag);
-    free_dev(e.d_fib_src);
     free_dev(e.d_lkcoef);
     free_dev(e.d_lkderiv);
     free_dev(e.d_lkc4);

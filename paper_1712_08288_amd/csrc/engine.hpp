@@ -29,6 +29,21 @@ struct Snapshot {
     void* wa = nullptr;
 };
 
+// What a recording forward step from the state at t keeps for a reverse
+// sweep that does not read the state itself: u(x, t) of the pulled state (D
+// planes of stride S, NaN at solid nodes) and, per cut link k = (y, i) in
+// sorted order, the forward values of its gradient: f_ibar(y, t) as pulled,
+// f'_i(y, t) and f'_ibar(y, t) after the collision.  One record is one
+// allocation of record_values() values of the handle's precision: the u
+// planes, then the three link runs of max(L, 1) values each.
+template <class T>
+struct StepRecord {
+    T* u;
+    T* fib;
+    T* fpi;
+    T* fpib;
+};
+
 struct Engine {
     // configuration
     int lattice = 0, precision = 0, Q = 0, D = 0;
@@ -73,7 +88,6 @@ struct Engine {
     double wall_decay = 1.0;            // wall data phi(t) = phi(0) * wall_decay^t
     double wall_scale = 1.0;            // wall_decay^t of the step being launched
     std::vector<uint8_t> ibar_is_link;  // sorted link k: (x_f, ibar) is a link too
-    uint32_t* d_fib_src = nullptr;      // sorted link k: where f_ibar(x_f, t) is (geometry.hpp)
     double* d_lkc1d = nullptr;          // c1 applied at the next pull (Eq. (211)), else 0
     double* d_lkd1d = nullptr;          // its gamma derivative
 
@@ -96,17 +110,19 @@ struct Engine {
 
     // checkpointed run and adjoint
     std::vector<Snapshot> ckpt;         // snapshot j holds the state at t_run0 + j*every
-    std::vector<Snapshot> pool;         // replay pool, every + 1 states
+    std::vector<Snapshot> pool;         // replay pool: every + 1 states, or two
+                                        // (ping-pong) when the sweep reads records
     int64_t run_t0 = -1, run_n = 0, run_every = 0;
     void* lam[2] = {nullptr, nullptr};  // adjoint arrays (Q*N values of T)
     // With the rate gradients off and the single-node scheme, the reverse
-    // sweep reads the velocity of each forward state (D planes of T) instead
-    // of the state itself: the checkpointed run records it for the last
-    // state of every segment but the last, the replay for the others.
-    bool run_urec = false;              // the last run recorded u_last
-    bool adj_um = false;                // the current sweep reads velocities
-    std::vector<void*> u_last;          // per segment: u at its last state
-    std::vector<void*> u_pool;          // per replayed state r of a segment
+    // sweep reads step records (StepRecord) instead of the forward states:
+    // the checkpointed run records the last step of every segment, the
+    // replay of a segment the others.  With a segment of one step the run
+    // records every step and keeps no snapshot.
+    bool run_urec = false;              // the last run recorded rec_last
+    bool adj_um = false;                // the current sweep reads records
+    std::vector<void*> rec_last;        // per segment: record of its last step
+    std::vector<void*> rec_pool;        // per replayed step r of a segment
     double* d_gq = nullptr;             // dJ/dgamma per link
     double* d_gphi = nullptr;           // dJ/dphi per link (L*D)
     void* d_stage = nullptr;            // per link: values staged for the link gradients (4 L doubles)
@@ -135,6 +151,22 @@ struct Engine {
     std::string err;
 };
 
+// Values (of the handle's precision) of one step record.
+inline int64_t record_values(const Engine& e) {
+    return (int64_t)e.D * e.S + 3 * (e.n_links > 0 ? e.n_links : 1);
+}
+template <class T>
+StepRecord<T> record_at(const Engine& e, const void* rec) {
+    T* base = (T*)rec;
+    const int64_t L1 = e.n_links > 0 ? e.n_links : 1;
+    StepRecord<T> r;
+    r.u = base;
+    r.fib = base + (int64_t)e.D * e.S;
+    r.fpi = r.fib + L1;
+    r.fpib = r.fpi + L1;
+    return r;
+}
+
 // ---- launchers (forward.hip) -------------------------------------------------
 // Objective terms a step accumulates (per-block sums in double, one thread
 // per node): MEAN_UX adds w u_x(x, t); PRESSURE_DROP adds
@@ -147,9 +179,10 @@ struct StepObjective {
     double a_in = 0.0, a_out = 0.0;
 };
 
-// u_rec (optional): D planes of T receiving u(x, t) of the pulled state
+// rec (optional): a step record (StepRecord) receiving u(x, t) of the
+// pulled state and the link values of this step
 hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
-                       const StepObjective& obj, void* u_rec = nullptr);
+                       const StepObjective& obj, void* rec = nullptr);
 // initial state: df (Q*N, deviation) or fields rho (N), u (N*D); device pointers
 hipError_t launch_init(Engine& e, const double* df, const double* rho,
                        const double* u, const Snapshot& out);
@@ -194,11 +227,11 @@ struct AdjointObjective {
     double a_in = 0.0, a_out = 0.0;      // 1 / (fluid nodes of each plane)
 };
 // One reverse step: lambda(t) from lambda(t+1) with the forward states at t
-// (`fwd`) and t+1 (`next`), accumulating the gradients.
-// u_rec: D planes of T with u(x, t) recorded by the forward step (only read
-// with the rate gradients off), or null to take it from `fwd`
-hipError_t launch_adjoint_step(Engine& e, const Snapshot& fwd, const Snapshot& next,
-                               const void* u_rec, const void* lam_in, void* lam_out,
+// (`fwd`) and t+1 (`next`), accumulating the gradients.  rec: the record of
+// forward step t (rate gradients off, single-node scheme; fwd and next are
+// then not read and may be null), or null to read the states.
+hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* next,
+                               const void* rec, const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
 // per-link values (width doubles each) from the sorted order into the

@@ -33,14 +33,16 @@ static_assert(BX == kBlock && BX % 64 == 0, "node launches use kBlock-thread blo
 
 // Eq. (213) for every cut link of the wave, from the pre-collision (fpre)
 // and post-collision (f) values at its fluid node, into the link slots of
-// the next step; nlw links in the wave.
-template <class L, class T>
+// the next step; nlw links in the wave.  REC: also the link values of the
+// step record (f_ibar(y, t), f'_i(y, t), f'_ibar(y, t)).
+template <class L, class T, bool REC>
 __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fpre)[L::Q],
                                                const T (&f)[L::Q],
                                                const LinkCoef* __restrict__ lkcoef,
                                                T* __restrict__ waB, double c0d, double ws,
                                                uint32_t wbase,
-                                               uint32_t nlw, uint32_t lane, LinkStage<T>& st) {
+                                               uint32_t nlw, uint32_t lane, LinkStage<T>& st,
+                                               const StepRecord<T>& rec) {
     if (nl.mask) {
         uint32_t k = nl.base;
         unroll<L::Q>([&](auto I) {
@@ -59,6 +61,11 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
                         const double v = c0d * (double)fpre[i] + c.c1 * (double)fpre[ib] +
                                          c.c2 * (double)f[i] + c.c3 * (double)f[ib] + ws * c.wall;
                         waB[wbase + k] = (T)v;
+                        if constexpr (REC) {
+                            rec.fib[wbase + k] = fpre[ib];
+                            rec.fpi[wbase + k] = f[i];
+                            rec.fpib[wbase + k] = f[ib];
+                        }
                     }
                 }
                 k += bit;
@@ -71,6 +78,11 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
         const double v = c0d * (double)st.v[0][lane] + c.c1 * (double)st.v[1][lane] +
                          c.c2 * (double)st.v[2][lane] + c.c3 * (double)st.v[3][lane] + ws * c.wall;
         waB[wbase + lane] = (T)v;
+        if constexpr (REC) {
+            rec.fib[wbase + lane] = st.v[1][lane];
+            rec.fpi[wbase + lane] = st.v[2][lane];
+            rec.fpib[wbase + lane] = st.v[3][lane];
+        }
     }
 }
 
@@ -92,13 +104,12 @@ __device__ __forceinline__ double objective_term(const StepObjective& ob, uint32
 // their own slots, which nothing reads: a full store keeps every written
 // cache line whole (partial lines cost HBM read-modify-write cycles).  Lanes
 // whose 64-byte segment of the planes holds no fluid node skip both.
-// REC: also record the velocity u(x, t) of the pulled state into D planes
-// of u_rec (stride g.S; NaN at solid nodes), for the reverse sweep.
+// REC: also write the step record (StepRecord) for the reverse sweep.
 template <class L, class T, int XB, bool ROWS, bool REC>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
        T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
-       Grid g, Params<L, T> p, StepObjective ob, T* __restrict__ u_rec) {
+       Grid g, Params<L, T> p, StepObjective ob, StepRecord<T> rec) {
     __shared__ LinkStage<T> stage[BX / 64];
     const NodePos pos = node_of_thread<ROWS>(g);
     const uint32_t lb = blockIdx.x;
@@ -117,7 +128,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             stp_nt<L::Q>(B, i, pos.n, f[i]);
         });
         if constexpr (REC)
-            for (int a = 0; a < L::D; ++a) st_nt(u_rec + (size_t)a * g.S, pos.n, mac.u[a]);
+            for (int a = 0; a < L::D; ++a) st_nt(rec.u + (size_t)a * g.S, pos.n, mac.u[a]);
     } else if (kind == WAVE_MIXED) {
         const uint32_t lane = threadIdx.x & 63u;
         const uint32_t nlw = wave_links(wv), wbase = wv.y;
@@ -152,10 +163,10 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
             });
             if constexpr (REC)
                 for (int a = 0; a < L::D; ++a)
-                    st_nt(u_rec + (size_t)a * g.S, pos.n, sol ? nan : mac.u[a]);
+                    st_nt(rec.u + (size_t)a * g.S, pos.n, sol ? nan : mac.u[a]);
         }
-        wave_link_tail<L, T>(nl, fpre, f, lkcoef, waB, p.c0, p.wall_scale, wbase, nlw, lane,
-                             stage[wid]);
+        wave_link_tail<L, T, REC>(nl, fpre, f, lkcoef, waB, p.c0, p.wall_scale, wbase, nlw,
+                                  lane, stage[wid], rec);
     }
     if (ob.acc) {   // uniform over the launch
         const double s = block_sum(obj_local);
@@ -502,18 +513,19 @@ static hipError_t dispatch(const Engine& e, F&& f) {
 }
 
 hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
-                       const StepObjective& obj, void* u_rec) {
+                       const StepObjective& obj, void* rec) {
     const Grid g = make_grid(e);
     return dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
-        auto kern = u_rec ? (g.bpr ? k_step<L, T, XB, true, true> : k_step<L, T, XB, false, true>)
-                          : (g.bpr ? k_step<L, T, XB, true, false> : k_step<L, T, XB, false, false>);
+        auto kern = rec ? (g.bpr ? k_step<L, T, XB, true, true> : k_step<L, T, XB, false, true>)
+                        : (g.bpr ? k_step<L, T, XB, true, false> : k_step<L, T, XB, false, false>);
+        const StepRecord<T> r = rec ? record_at<T>(e, rec) : StepRecord<T>{};
         hipLaunchKernelGGL(kern, dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
                            (T*)out.wa, meta(e), e.d_lkcoef, g,
-                           make_params<L, T>(e), obj, (T*)u_rec);
+                           make_params<L, T>(e), obj, r);
         return hipGetLastError();
     });
 }

@@ -102,9 +102,7 @@ int build_geometry(const GeomDomain& d, const uint8_t* solid, const GeomLinks& l
     }
     out.n_tags = max_tag + 1;
     out.ibar_is_link.assign(L, 0);
-    out.fib_src.assign(L, 0u);
-    for (int64_t k = 0, first = 0; k < L; ++k) {
-        if (k > 0 && out.node[k] != out.node[k - 1]) first = k;   // the node's first link
+    for (int64_t k = 0; k < L; ++k) {
         const int i = out.dir[k];
         int ib = 0;
         for (int j = 0; j < Q; ++j) {
@@ -114,14 +112,6 @@ int build_geometry(const GeomDomain& d, const uint8_t* solid, const GeomLinks& l
         }
         const int64_t y = out.node[k];
         out.ibar_is_link[k] = (mask[y] >> ib) & 1u;
-        if (out.ibar_is_link[k]) {
-            int64_t kb = first;
-            while (out.node[kb] != y || out.dir[kb] != ib) ++kb;   // within the node's links
-            out.fib_src[k] = 0x80000000u | (uint32_t)kb;
-        } else {
-            const int64_t x = y % d.nx, yy = (y / d.nx) % d.ny, z = y / (d.nx * d.ny);
-            out.fib_src[k] = (uint32_t)pull_source(d, x, yy, z, ib);
-        }
     }
     // per node: bit 31 solid, else the link-direction mask and, in bits
     // 19..30, the number of links at earlier nodes of its wave; per wave of a

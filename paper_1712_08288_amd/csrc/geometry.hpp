@@ -46,10 +46,6 @@ struct GeomTables {
     std::vector<double> q, wall_u;      // wall_u (L, D)
     std::vector<int32_t> tag;
     std::vector<uint8_t> ibar_is_link;  // (x_f, ibar) is a link too
-    // where f_ibar(x_f, t) of link k = (x_f, i) is found: bit 31 set, the
-    // index of the link (x_f, ibar) (its slot); else the node that the pull
-    // of direction ibar at x_f reads
-    std::vector<uint32_t> fib_src;
     std::vector<int64_t> fluid_per_x;   // fluid nodes of each plane x = const
     // per node: bit 31 solid; else bits 0..Q-1 the link directions and bits
     // 19..30 the links at earlier nodes of its wave

@@ -120,24 +120,6 @@ void check_tables(const Case& c, const lbe::GeomTables& t, const std::string& na
         check(t.node[k] == c.node[t.perm[k]] && t.dir[k] == c.dir[t.perm[k]], name + ": permuted copy");
     }
     for (int64_t k = 0; k < L; ++k) check(seen[k] == 1, name + ": perm is a permutation");
-    // where f_ibar of each link is read: the opposite link's slot, or the
-    // (fluid) node that the pull of the opposite direction reads
-    check((int64_t)t.fib_src.size() == L, name + ": fib_src size");
-    for (int64_t k = 0; k < L && (int64_t)t.fib_src.size() == L; ++k) {
-        int ib = 0;
-        for (int j = 0; j < c.d.Q; ++j)
-            if (c.d.e[j][0] == -c.d.e[t.dir[k]][0] && c.d.e[j][1] == -c.d.e[t.dir[k]][1] &&
-                c.d.e[j][2] == -c.d.e[t.dir[k]][2])
-                ib = j;
-        const uint32_t src = t.fib_src[k];
-        if (src >> 31) {
-            const int64_t kb = src & 0x7FFFFFFFu;
-            check(kb < L && t.node[kb] == t.node[k] && t.dir[kb] == ib, name + ": opposite link");
-        } else {
-            const int64_t sn = source(c.d, t.node[k], ib);
-            check((int64_t)src == sn && !c.solid[sn], name + ": f_ibar pull source");
-        }
-    }
     int64_t fluid = 0, links_in_waves = 0, nonidle = 0;
     for (int64_t n = 0; n < N; ++n) fluid += c.solid[n] ? 0 : 1;
     check(fluid == t.n_fluid, name + ": fluid count");

@@ -213,6 +213,36 @@ def test_velocity_mode_is_independent_of_the_checkpoints(precision):
     sv.close()
 
 
+def test_record_only_run_needs_velocity_mode_at_the_sweep():
+    """A run with one step per segment in velocity mode keeps step records
+    and no snapshot: a sweep after switching the rate gradients on has no
+    state to read and fails with ESTATE; a new run then sweeps normally."""
+    from paper_1712_08288_amd import binding
+    name, mk_geom, mk_s, kw, obj, steps = [c for c in CASES if c[0] == "d3q19_pdrop_seam"][0]
+    geom, s = mk_geom(), mk_s()
+    df0 = states.random_deviation(19, geom.n_nodes, seed=6, amp=2e-3)
+    sv0, _, want = _gpu_grad(geom, s, kw, obj, steps, 4, df0)
+    sv0.close()
+    sv = binding.solver_for(geom, s, precision="fp64", dp=kw["dp"], l_rule=kw["l_rule"])
+    sv.set_rate_gradient(False)
+    sv.init_deviation(df0)
+    sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1, planes=obj.planes)
+    sv.run_checkpointed(steps, 1)
+    sv.set_rate_gradient(True)
+    with pytest.raises(binding.LBMError) as ex:
+        sv.adjoint()
+    assert ex.value.name == "ESTATE"
+    sv.init_deviation(df0)
+    sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1, planes=obj.planes)
+    sv.run_checkpointed(steps, 1)
+    sv.adjoint()
+    gr = sv.grad()
+    for key in ("q", "wall_u", "g", "s"):
+        scale = max(np.abs(want[key]).max(), 1e-300)
+        assert np.abs(gr[key] - want[key]).max() <= 1e-14 * scale, key
+    sv.close()
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     name, mk_geom, mk_s, kw, obj, steps = CASES[0]
     geom, s = mk_geom(), mk_s()
