@@ -13,13 +13,17 @@
 // and J_ij = d f^eq_i / d f_j = w_i [1 + (3 e_i + 9 (e_i.u) e_i - 3 u).e_j]
 // (derivative of Eq. (42)), so that (J^T v)_j = a + b.e_j with
 // a = sum_i w_i v_i and b = sum_i w_i v_i (3 e_i + 9 (e_i.u) e_i - 3 u).
-// Gradients accumulated on the way, in double (the per-link ones in a
-// kernel over the links, the others in per-block sums of the node kernel):
-//   dJ/dgamma_k += a_k (dc1 f_ibar + dc2 g_i + dc3 g_ibar + dwall),
-//   dJ/dphi_k   += a_k c4 3 w_i rho0 e_i,
+// Gradients accumulated on the way, in double (the per-link ones by the
+// lanes that carry the links, the others in per-block sums):
+//   dJ/dgamma_k += a_k (dc1 f_ibar + dc2 g_i + dc3 g_ibar + ws dwall),
+//   dJ/dphi_k   += a_k ws c4 3 w_i rho0 e_i,
 //   dJ/dg       += sum_i mu_i 3 w_i rho0 e_i,
 //   dJ/ds_k     += -(M mu)_k (M (f - f^eq))_k / |M_k|^2,
-// where a_k is the adjoint of the link value f_i(y, t+1).
+// where a_k is the adjoint of the link value f_i(y, t+1) and ws the
+// wall-data factor of step t.  The wall terms share the factor a_k ws, so
+// per link only two sums are kept, gq_k = sum a_k (dc1 f_ibar + dc2 g_i +
+// dc3 g_ibar) and gs_k = sum a_k ws; the gradients are formed from them
+// when read (k_link_finish).
 #include "engine.hpp"
 #include "kernels.hpp"
 
@@ -72,16 +76,23 @@ struct AdjArgs {
     double a_in, a_out;
 };
 
-// Per-link values one adjoint step hands to the link-gradient kernel: the
-// link adjoint a_k (with the drag term), f_ibar(y, t), and f'_i(y, t),
-// f'_ibar(y, t) as the forward step stored them at y.
-template <class T>
-struct LinkStaging {
-    double* ak;
-    T* fib;
-    T* fpi;
-    T* fpib;
+// The per-link gradient sums of the sweep (see the header): gq and gs, with
+// the gamma-derivatives of the coefficients they need.
+struct LinkGrad {
+    const LinkDeriv* deriv;
+    double* gq;
+    double* gs;
 };
+
+// One step's contribution of link k with adjoint a_k (drag term included)
+// and the forward values f_ibar(y, t), f'_i(y, t), f'_ibar(y, t).
+template <class T>
+__device__ __forceinline__ void link_gradient(const LinkGrad& lg, uint32_t k, double ak, T fib,
+                                              T fpi, T fpib, double ws) {
+    const double d1 = lg.deriv[k].d1, d2 = lg.deriv[k].d2, d3 = lg.deriv[k].d3;
+    lg.gq[k] += ak * (d1 * (double)fib + d2 * (double)fpi + d3 * (double)fpib);
+    lg.gs[k] += ak * ws;
+}
 
 template <int NC>
 __device__ __forceinline__ void block_accumulate(const double (&v)[NC], double* __restrict__ dst) {
@@ -119,17 +130,17 @@ __device__ __forceinline__ void dir_data(int d, int (&e)[3], double& w, int& opp
 }
 
 // Link k = (y, i) of a mixed wave, handled by the lane of its node y: the
-// contribution of its adjoint a_k to mu and to lambda(y, t), and (unless UM:
-// the step record holds them) the forward values staged for the
-// link-gradient kernel.  Used for links past the 64th of a wave (the first
-// 64 go through the wave's LDS slab).
+// contribution of its adjoint a_k to mu and to lambda(y, t), and its
+// gradient sums (forward values from the step record when UM, else from
+// the pulled state and the state at t + 1).  Used for links past the 64th
+// of a wave (the first 64 go through the wave's LDS slab).
 template <class L, class T, int i, bool UM>
 __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict__ lam_in,
                                                 const T* __restrict__ nxt,
-                                                uint32_t n,
+                                                const StepRecord<T>& rec, uint32_t n,
                                                 const LinkCoef* __restrict__ lkcoef,
                                                 const int32_t* __restrict__ lktag,
-                                                const LinkStaging<T>& sg,
+                                                const LinkGrad& lgr,
                                                 const Params<L, T>& p, const AdjArgs& a,
                                                 const T (&f)[L::Q], T (&mu)[L::Q]) {
     constexpr int ib = TAB<L>.opp[i];
@@ -143,12 +154,11 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
     const LinkCoef c = lkcoef[k];
     mu[i] += (T)(c.c2 * ak);
     mu[ib] += (T)(c.c3 * ak);
-    sg.ak[k] = ak;
-    if constexpr (!UM) {
-        sg.fib[k] = f[ib];
-        sg.fpi[k] = ldp<L::Q>(nxt, i, n);
-        sg.fpib[k] = ldp<L::Q>(nxt, ib, n);
-    }
+    if constexpr (UM)
+        link_gradient(lgr, k, ak, rec.fib[k], rec.fpi[k], rec.fpib[k], p.wall_scale);
+    else
+        link_gradient(lgr, k, ak, f[ib], ldp<L::Q>(nxt, i, n), ldp<L::Q>(nxt, ib, n),
+                      p.wall_scale);
 }
 
 // The terms of such a link that bypass the collision: c0 a_k onto
@@ -169,31 +179,28 @@ __device__ __forceinline__ void own_link_bypass(uint32_t k, const T* __restrict_
     mu[ib] += (T)(lkcoef[k].c1 * ak);
 }
 
-// Per-link gradients of one adjoint step, link k = (y, i) with adjoint a_k
-// of f_i(y, t+1) (plus the drag term):
-//   dJ/dgamma_k += a_k (dc1 f_ibar(y,t) + dc2 f'_i(y,t) + dc3 f'_ibar(y,t) + dwall),
-//   dJ/dphi_k   += a_k c4 3 w_i rho0 e_i,
-// from the values the adjoint kernel staged, or (a sweep on step records)
-// from the forward step's record (coalesced, one thread per link).
-template <class L, class T>
+// The gradients of every link from its two sums, in the caller's link
+// order: dq[perm k] = gq_k + dwall_k gs_k and
+// dphi[perm k][a] = c4_k 3 w_i rho0 e_ia gs_k (either output may be null).
+template <class L>
 __global__ void __launch_bounds__(BX)
-k_link_grad(LinkStaging<T> sg, const uint8_t* __restrict__ lkdir,
-            const LinkDeriv* __restrict__ lkderiv, const double* __restrict__ lkc4,
-            double* __restrict__ gq, double* __restrict__ gphi, uint32_t n_links,
-            Params<L, T> p) {
+k_link_finish(const double* __restrict__ gq, const double* __restrict__ gs,
+              const LinkDeriv* __restrict__ deriv, const double* __restrict__ lkc4,
+              const uint8_t* __restrict__ lkdir, const int32_t* __restrict__ perm,
+              double rho0, uint32_t n_links, double* __restrict__ dq,
+              double* __restrict__ dphi) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     if (k >= n_links) return;
-    int e[3] = {0, 0, 0}, ib = 0;
-    double w = 0.0;
-    dir_data<L>(lkdir[k], e, w, ib);
-    const double ak = sg.ak[k];
-    const LinkDeriv dc = lkderiv[k];
-    gq[k] += ak * (dc.d1 * (double)sg.fib[k] + dc.d2 * (double)sg.fpi[k] +
-                   dc.d3 * (double)sg.fpib[k] + p.wall_scale * dc.dwall);
-    const double c4w = lkc4[k] * 3.0 * w * p.rho0_d * p.wall_scale * ak;
+    const size_t pk = (size_t)(uint32_t)perm[k];
+    if (dq) dq[pk] = gq[k] + deriv[k].dwall * gs[k];
+    if (dphi) {
+        int e[3] = {0, 0, 0}, ib = 0;
+        double w = 0.0;
+        dir_data<L>(lkdir[k], e, w, ib);
+        const double c = lkc4[k] * 3.0 * w * rho0 * gs[k];
 #pragma unroll
-    for (int al = 0; al < L::D; ++al)
-        if (e[al] != 0) gphi[(size_t)k * L::D + al] += c4w * e[al];
+        for (int al = 0; al < L::D; ++al) dphi[pk * L::D + al] = c * e[al];
+    }
 }
 
 // The waves of the adjoint launch, slot s < count (s = 4 blockIdx.x + wave in
@@ -231,9 +238,9 @@ __device__ __forceinline__ NodePos node_of_wave(const Grid& g, const WaveList& w
 // links cooperatively (see LinkStage): the link lanes read the link data
 // and a_k = lambda_i(y, t+1) (plus the drag term) with coalesced loads and
 // hand c2 a_k, c3 a_k (+ drag), c0 a_k and c1 a_k to the node's lane
-// through LDS; the node's lane hands back f_ibar(y, t), which the link
-// lanes stage for the link-gradient kernel together with a_k and the
-// forward step's stored f'_i(y, t), f'_ibar(y, t).
+// through LDS; the node's lane hands back f_ibar(y, t), from which with
+// a_k and the forward step's stored f'_i(y, t), f'_ibar(y, t) the link
+// lanes add the link's gradient sums.
 // UM: the forward state enters the collision adjoint only through its
 // velocity (the equilibrium's Jacobian depends on u alone), so with the rate
 // gradients off the kernel reads u(y, t) recorded by the forward step (D
@@ -242,18 +249,21 @@ __device__ __forceinline__ NodePos node_of_wave(const Grid& g, const WaveList& w
 // nxt are not read.
 template <class L, class T, int XB, bool WANT_DS, bool ROWS, bool UM>
 __global__ void __launch_bounds__(BX)
-k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict__ wa,
+k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
           const T* __restrict__ nxt,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
           NodeMeta nm, WaveList wl, const LinkCoef* __restrict__ lkcoef,
           const int32_t* __restrict__ lktag,
           const uint8_t* __restrict__ lkdir, const int32_t* __restrict__ lknode,
-          LinkStaging<T> sg, double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
+          LinkGrad lgr, double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
     constexpr int Q = L::Q, D = L::D, NP = NPAIR<L>;
     static_assert(!(UM && WANT_DS), "the rate gradients need the forward populations");
     constexpr int NC = D + Q;                 // layout of the per-block sums
     constexpr int NR = WANT_DS ? NC : D;      // columns reduced here
     __shared__ LinkStage<T> stage[BX / 64];
+    // the link lanes' a_k, parked while the node's work runs (registers are
+    // scarcest there)
+    __shared__ double ak_park[BX / 64][64];
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t slot = blockIdx.x * (BX / 64) + wid;
@@ -298,7 +308,7 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
         const bool live = !MX || (pos.in && lane_in_live_segment<T>(wx, lane));
         if (live) {
             if constexpr (UM) {
-                for (int a = 0; a < D; ++a) uv[a] = ld(U + (size_t)a * g.S, pos.n);
+                for (int a = 0; a < D; ++a) uv[a] = ld(rec.u + (size_t)a * g.S, pos.n);
             } else {
                 pull_planes<L, T, XB>(A, g, pos, p, NodeLinks{0u, 0u}, f);
             }
@@ -370,8 +380,9 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
                                     mu[ib] += st.v[1][k];
                                     if constexpr (!UM) st.v[0][k] = f[ib];
                                 } else {
-                                    own_link_direct<L, T, i, UM>(wbase + k, lam_in, nxt, pos.n,
-                                                                 lkcoef, lktag, sg, p, a, f, mu);
+                                    own_link_direct<L, T, i, UM>(wbase + k, lam_in, nxt, rec,
+                                                                 pos.n, lkcoef, lktag, lgr, p, a,
+                                                                 f, mu);
                                 }
                             }
                             k += bit;
@@ -497,20 +508,20 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
         if constexpr (!MX) {
             node(std::true_type{}, NodeLinks{0u, 0u});
         } else {
-            // link lanes: the link's adjoint a_k = lambda_i(y, t+1) and the forward
-            // step's stored f'_i(y, t), f'_ibar(y, t), staged for the link
-            // gradients at once
+            // link lanes: the link's adjoint a_k = lambda_i(y, t+1) and (reading
+            // states) the forward step's stored f'_i(y, t), f'_ibar(y, t)
             int le[3] = {0, 0, 0}, lib = 0;
             double lw = 0.0;
             double ak = 0.0;
+            T fpi = T(0), fpib = T(0);
             LinkCoef c{0.0, 0.0, 0.0, 0.0};
             if (link_lane) {
                 dir_data<L>(ld_dir, le, lw, lib);
                 c = lkcoef[kl];
                 ak = (double)ldp<Q>(lam_in, ld_dir, ld_node);
                 if constexpr (!UM) {
-                    sg.fpi[kl] = ldp<Q>(nxt, ld_dir, ld_node);
-                    sg.fpib[kl] = ldp<Q>(nxt, lib, ld_node);
+                    fpi = ldp<Q>(nxt, ld_dir, ld_node);
+                    fpib = ldp<Q>(nxt, lib, ld_node);
                 }
             }
             const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
@@ -530,18 +541,25 @@ k_adjoint(const T* __restrict__ A, const T* __restrict__ U, const T* __restrict_
                     dfx = -(double)le[0] * a.w_force;
                     ak += dfx;
                 }
-                sg.ak[kl] = ak;
                 st.v[0][lane] = (T)(c.c2 * ak);
                 st.v[1][lane] = (T)(c.c3 * ak + dfx);
                 st.v[2][lane] = (T)(p.c0 * ak);
                 st.v[3][lane] = (T)(c.c1 * ak);
+                // the link's gradient sums: at once from the record (UM); else
+                // once the node's lane has handed back f_ibar(y, t)
+                if constexpr (UM)
+                    link_gradient(lgr, kl, ak, rec.fib[kl], rec.fpi[kl], rec.fpib[kl],
+                                  p.wall_scale);
+                else
+                    ak_park[wid][lane] = ak;
             }
             wave_lds_sync();
             if (!sol) node(std::false_type{}, nl);
             wave_lds_sync();
-            // link lanes: stage f_ibar(y, t) handed back by the node's lane
             if constexpr (!UM)
-                if (link_lane) sg.fib[kl] = st.v[0][lane];
+                if (link_lane)
+                    link_gradient(lgr, kl, ak_park[wid][lane], st.v[0][lane], fpi, fpib,
+                                  p.wall_scale);
             // the solid lanes store NaN (nothing reads lambda at solid nodes) so
             // that the wave writes whole lines of lam_out: partial lines cost
             // HBM read-modify-write cycles
@@ -697,35 +715,32 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* n
                               : (wpr ? k_adjoint<L, T, XB, false, true, false>
                                      : k_adjoint<L, T, XB, false, false, false>);
         const Params<L, T> prm = adj_params<L, T>(e);
-        // staging: [a_k: L doubles][f_ibar][f'_i][f'_ibar: L values of T each];
-        // on step records the forward values come from the record
-        const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
-        LinkStaging<T> sg;
-        sg.ak = (double*)e.d_stage;
-        sg.fib = (T*)(sg.ak + L1);
-        sg.fpi = sg.fib + L1;
-        sg.fpib = sg.fpi + L1;
         const StepRecord<T> r = um ? record_at<T>(e, rec) : StepRecord<T>{};
-        if (um) {
-            sg.fib = r.fib;
-            sg.fpi = r.fpi;
-            sg.fpib = r.fpib;
-        }
+        const LinkGrad lgr{e.d_lkderiv, e.d_gq, e.d_gs};
         if (waves.count)
             hipLaunchKernelGGL(kern, dim3(wave_blocks(waves.count)), dim3(BX), 0, e.stream,
-                               um ? nullptr : (const T*)fwd->f, (const T*)r.u,
+                               um ? nullptr : (const T*)fwd->f, r,
                                um ? nullptr : (const T*)fwd->wa, um ? nullptr : (const T*)next->f,
                                (const T*)lam_in, (T*)lam_out,
                                NodeMeta{e.d_info, e.d_wave}, waves, e.d_lkcoef,
-                               e.d_lktag, e.d_lkdir, e.d_lknode, sg,
+                               e.d_lktag, e.d_lkdir, e.d_lknode, lgr,
                                e.d_gglob, g, prm, a);
-        // per-link gradients, from what the mixed waves staged
-        if (e.n_links)
-            hipLaunchKernelGGL((k_link_grad<L, T>), dim3((unsigned)((e.n_links + BX - 1) / BX)),
-                               dim3(BX), 0, e.stream, sg, e.d_lkdir, e.d_lkderiv, e.d_lkc4,
-                               e.d_gq, e.d_gphi, (uint32_t)e.n_links, prm);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_link_gradients(Engine& e, double* dq, double* dphi) {
+    if (!e.n_links || (!dq && !dphi)) return hipSuccess;
+    auto go = [&](auto lat) {
+        using L = decltype(lat);
+        hipLaunchKernelGGL((k_link_finish<L>), dim3((unsigned)((e.n_links + BX - 1) / BX)),
+                           dim3(BX), 0, e.stream, e.d_gq, e.d_gs, e.d_lkderiv, e.d_lkc4,
+                           e.d_lkdir, e.d_perm, e.rho0, (uint32_t)e.n_links, dq, dphi);
+        return hipGetLastError();
+    };
+    if (e.lattice == 0) return go(D2Q9{});
+    if (e.lattice == 2) return go(D3Q15{});
+    return go(D3Q19{});
 }
 
 hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in,
@@ -751,22 +766,6 @@ hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in
                            adj_params<L, T>(e), a);
         return hipGetLastError();
     });
-}
-
-__global__ void __launch_bounds__(BX)
-k_links_to_caller(const double* __restrict__ in, double* __restrict__ out,
-                  const int32_t* __restrict__ perm, uint32_t n_links, int width) {
-    const uint32_t k = blockIdx.x * BX + threadIdx.x;
-    if (k >= n_links) return;
-    const size_t p = (size_t)(uint32_t)perm[k];
-    for (int a = 0; a < width; ++a) out[p * width + a] = in[(size_t)k * width + a];
-}
-
-hipError_t launch_links_to_caller(Engine& e, const double* in, double* out, int width) {
-    if (!e.n_links) return hipSuccess;
-    hipLaunchKernelGGL(k_links_to_caller, dim3((unsigned)((e.n_links + BX - 1) / BX)), dim3(BX),
-                       0, e.stream, in, out, e.d_perm, (uint32_t)e.n_links, width);
-    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out) {

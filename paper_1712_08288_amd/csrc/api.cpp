@@ -392,19 +392,17 @@ int adjoint_begin(lbm_t* h) {
     const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
     if (!e.d_gq || e.gglob_len != nb || e.gq_len != (int64_t)L1) {
         free_dev(e.d_gq);
-        free_dev(e.d_gphi);
+        free_dev(e.d_gs);
         free_dev(e.d_gglob);
-        free_dev(e.d_stage);
         if (hipMalloc((void**)&e.d_gq, L1 * 8) != hipSuccess ||
-            hipMalloc(&e.d_stage, 4 * L1 * 8) != hipSuccess ||
-            hipMalloc((void**)&e.d_gphi, L1 * e.D * 8) != hipSuccess ||
+            hipMalloc((void**)&e.d_gs, L1 * 8) != hipSuccess ||
             hipMalloc((void**)&e.d_gglob, (size_t)nb * NC * 8) != hipSuccess)
             return fail(h, LBM_ENOMEM, "gradient accumulator allocation failed");
         e.gglob_len = nb;
         e.gq_len = (int64_t)L1;
     }
     if ((rc = zero(h, e.d_gq, L1 * 8))) return rc;
-    if ((rc = zero(h, e.d_gphi, L1 * e.D * 8))) return rc;
+    if ((rc = zero(h, e.d_gs, L1 * 8))) return rc;
     if ((rc = zero(h, e.d_gglob, (size_t)nb * NC * 8))) return rc;
     if ((rc = zero(h, e.lam[0], lam_bytes))) return rc;
     e.adj_next = e.run_n - 1;
@@ -1185,24 +1183,21 @@ int lbm_grad(lbm_t* h, double* dq, double* dwall_u, double* dg, double* ds) {
     Engine& e = h->e;
     if (!e.have_grad) return fail(h, LBM_ESTATE, "run lbm_adjoint first");
     const int D = e.D, Q = e.Q, NC = D + Q;
+    const int64_t L = e.n_links;
     int rc;
-    std::vector<double> gq(e.n_links), gphi((size_t)e.n_links * D);
-    if (e.n_links) {
-        HIPCHK(h, hipMemcpyAsync(gq.data(), e.d_gq, e.n_links * 8, hipMemcpyDeviceToHost, e.stream));
-        HIPCHK(h, hipMemcpyAsync(gphi.data(), e.d_gphi, e.n_links * D * 8,
-                                 hipMemcpyDeviceToHost, e.stream));
-    }
-    if ((rc = ensure_scratch(h, NC))) return rc;
+    // scratch: [global sums NC][dq L][dphi L*D], the per-link ones already in
+    // the caller's order
+    if ((rc = ensure_scratch(h, NC + L * (1 + D)))) return rc;
+    double* d_dq = e.d_scratch + NC;
+    double* d_dphi = d_dq + L;
     HIPCHK(h, lbe::launch_sum_blocks(e, e.d_gglob, e.gglob_len, NC, e.d_scratch));
+    HIPCHK(h, lbe::launch_link_gradients(e, dq ? d_dq : nullptr, dwall_u ? d_dphi : nullptr));
     std::vector<double> glob(NC);
     HIPCHK(h, hipMemcpyAsync(glob.data(), e.d_scratch, NC * 8, hipMemcpyDeviceToHost, e.stream));
+    if (dq && L) HIPCHK(h, hipMemcpyAsync(dq, d_dq, L * 8, hipMemcpyDeviceToHost, e.stream));
+    if (dwall_u && L)
+        HIPCHK(h, hipMemcpyAsync(dwall_u, d_dphi, L * D * 8, hipMemcpyDeviceToHost, e.stream));
     if ((rc = sync(h))) return rc;
-    for (int64_t k = 0; k < e.n_links; ++k) {
-        const int64_t p = e.perm[k];
-        if (dq) dq[p] = gq[k];
-        if (dwall_u)
-            for (int a = 0; a < D; ++a) dwall_u[p * D + a] = gphi[k * D + a];
-    }
     if (dg)
         for (int a = 0; a < D; ++a) dg[a] = glob[a];
     if (ds)
@@ -1214,9 +1209,7 @@ int lbm_grad_device(lbm_t* h, void* dq_dev, void* dwall_u_dev, double* dg, doubl
     if (!h) return LBM_EINVAL;
     Engine& e = h->e;
     if (!e.have_grad) return fail(h, LBM_ESTATE, "run lbm_adjoint first");
-    if (dq_dev) HIPCHK(h, lbe::launch_links_to_caller(e, e.d_gq, (double*)dq_dev, 1));
-    if (dwall_u_dev)
-        HIPCHK(h, lbe::launch_links_to_caller(e, e.d_gphi, (double*)dwall_u_dev, e.D));
+    HIPCHK(h, lbe::launch_link_gradients(e, (double*)dq_dev, (double*)dwall_u_dev));
     if (!dg && !ds) return LBM_OK;
     return lbm_grad(h, nullptr, nullptr, dg, ds);
 }
@@ -1310,9 +1303,8 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_lkd1d);
     free_dev(e.d_obj_acc);
     free_dev(e.d_gq);
-    free_dev(e.d_gphi);
+    free_dev(e.d_gs);
     free_dev(e.d_gglob);
-    free_dev(e.d_stage);
     free_dev(e.d_scratch);
     if (e.ev0) (void)hipEventDestroy(e.ev0);
     if (e.ev1) (void)hipEventDestroy(e.ev1);

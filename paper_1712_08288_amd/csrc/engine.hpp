@@ -123,9 +123,8 @@ struct Engine {
     bool adj_um = false;                // the current sweep reads records
     std::vector<void*> rec_last;        // per segment: record of its last step
     std::vector<void*> rec_pool;        // per replayed step r of a segment
-    double* d_gq = nullptr;             // dJ/dgamma per link
-    double* d_gphi = nullptr;           // dJ/dphi per link (L*D)
-    void* d_stage = nullptr;            // per link: values staged for the link gradients (4 L doubles)
+    double* d_gq = nullptr;             // per link: sum of a_k (dc1 f_ibar + dc2 f'_i + dc3 f'_ibar)
+    double* d_gs = nullptr;             // per link: sum of a_k ws (the wall-data terms' factor)
     double* d_gglob = nullptr;          // per-block partials of dJ/dg (D) and dJ/ds (Q)
     int64_t gglob_len = 0;
     bool have_grad = false;
@@ -234,9 +233,10 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* n
                                const void* rec, const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
-// per-link values (width doubles each) from the sorted order into the
-// caller's order, device to device
-hipError_t launch_links_to_caller(Engine& e, const double* in, double* out, int width);
+// per-link gradients from the sweep's sums, in the caller's link order, into
+// device buffers: dq (L doubles) and dphi (L*D, link-major); either may be
+// null
+hipError_t launch_link_gradients(Engine& e, double* dq, double* dphi);
 // Eq. (211) links: move c1 * (adjoint of f_i(x_f, t+1)) onto the adjoint of
 // f_ibar(x_f, t+1) and add the gamma-derivative of that term, using the
 // forward state at t+1 in `next`.
