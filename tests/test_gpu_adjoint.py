@@ -344,11 +344,14 @@ def test_pressure_drop_gradient_against_central_differences():
     sv.close()
 
 
+@pytest.mark.parametrize("rates", [True, False], ids=["states", "records"])
 @pytest.mark.parametrize("case", [CASES[1], CASES[4]], ids=[CASES[1][0], CASES[4][0]])
-def test_debug_poison_mode_leaves_the_adjoint_unchanged(monkeypatch, case):
-    """With LBM_DEBUG=1 the replayed states and every lambda(t) array are
-    filled with NaN before they are written: the gradients and lambda(0)
-    must be bitwise those of the normal mode."""
+def test_debug_poison_mode_leaves_the_adjoint_unchanged(monkeypatch, case, rates):
+    """With LBM_DEBUG=1 the replayed states, the step records and every
+    lambda(t) array are filled with NaN before they are written: the
+    gradients and lambda(0) must be bitwise those of the normal mode (with
+    the rate gradients off and the single-node scheme the sweep reads step
+    records)."""
     name, mk_geom, mk_s, kw, obj, steps = case
     geom, s = mk_geom(), mk_s()
     Q = len(VELOCITIES[geom.lattice])
@@ -358,7 +361,7 @@ def test_debug_poison_mode_leaves_the_adjoint_unchanged(monkeypatch, case):
     res = {}
     for mode in ("0", "1"):
         monkeypatch.setenv("LBM_DEBUG", mode)
-        sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, 3, df0)
+        sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, 3, df0, rates=rates)
         res[mode] = (J, gr)
         sv.close()
     monkeypatch.delenv("LBM_DEBUG", raising=False)
