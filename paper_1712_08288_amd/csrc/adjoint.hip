@@ -76,12 +76,14 @@ struct AdjArgs {
     double a_in, a_out;
 };
 
-// The per-link gradient sums of the sweep (see the header): gq and gs, with
-// the gamma-derivatives of the coefficients they need.
+// The per-link gradient sums of the sweep (see the header): gq at g[k] and
+// gs at g[L1 + k], with the gamma-derivatives of the coefficients they
+// need.  Pointers are few on purpose: every kernel argument the adjoint
+// keeps costs scalar registers, which bound its occupancy.
 struct LinkGrad {
     const LinkDeriv* deriv;
-    double* gq;
-    double* gs;
+    double* g;
+    uint32_t L1;     // max(L, 1): the stride of the runs of g and of a record
 };
 
 // One step's contribution of link k with adjoint a_k (drag term included)
@@ -90,8 +92,15 @@ template <class T>
 __device__ __forceinline__ void link_gradient(const LinkGrad& lg, uint32_t k, double ak, T fib,
                                               T fpi, T fpib, double ws) {
     const double d1 = lg.deriv[k].d1, d2 = lg.deriv[k].d2, d3 = lg.deriv[k].d3;
-    lg.gq[k] += ak * (d1 * (double)fib + d2 * (double)fpi + d3 * (double)fpib);
-    lg.gs[k] += ak * ws;
+    lg.g[k] += ak * (d1 * (double)fib + d2 * (double)fpi + d3 * (double)fpib);
+    lg.g[lg.L1 + k] += ak * ws;
+}
+// The same with the three forward values read from the link runs of a step
+// record (fib at lk[k], f'_i at lk[L1 + k], f'_ibar at lk[2 L1 + k]).
+template <class T>
+__device__ __forceinline__ void link_gradient_rec(const LinkGrad& lg, const T* __restrict__ lk,
+                                                  uint32_t k, double ak, double ws) {
+    link_gradient(lg, k, ak, lk[k], lk[lg.L1 + k], lk[2 * lg.L1 + k], ws);
 }
 
 template <int NC>
@@ -155,7 +164,7 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
     mu[i] += (T)(c.c2 * ak);
     mu[ib] += (T)(c.c3 * ak);
     if constexpr (UM)
-        link_gradient(lgr, k, ak, rec.fib[k], rec.fpi[k], rec.fpib[k], p.wall_scale);
+        link_gradient_rec(lgr, rec.fib, k, ak, p.wall_scale);
     else
         link_gradient(lgr, k, ak, f[ib], ldp<L::Q>(nxt, i, n), ldp<L::Q>(nxt, ib, n),
                       p.wall_scale);
@@ -247,8 +256,13 @@ __device__ __forceinline__ NodePos node_of_wave(const Grid& g, const WaveList& w
 // planes of U) instead of pulling the Q populations of f(y, t), and the
 // link values of the gradients come from the same step record: A, wa and
 // nxt are not read.
+// FP64 on step records asks for 4 waves per SIMD: the kernel needs 130
+// VGPRs, and fitting 128 (two values spilled to scratch) made the reverse
+// step 3.5% faster at 256^3; the other variants are left to the compiler
+// (forcing more waves on them spilled more and was slower).
 template <class L, class T, int XB, bool WANT_DS, bool ROWS, bool UM>
 __global__ void __launch_bounds__(BX)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && UM ? 4 : 1)))
 k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
           const T* __restrict__ nxt,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
@@ -548,8 +562,7 @@ k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
                 // the link's gradient sums: at once from the record (UM); else
                 // once the node's lane has handed back f_ibar(y, t)
                 if constexpr (UM)
-                    link_gradient(lgr, kl, ak, rec.fib[kl], rec.fpi[kl], rec.fpib[kl],
-                                  p.wall_scale);
+                    link_gradient_rec(lgr, rec.fib, kl, ak, p.wall_scale);
                 else
                     ak_park[wid][lane] = ak;
             }
@@ -716,7 +729,7 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* n
                                      : k_adjoint<L, T, XB, false, false, false>);
         const Params<L, T> prm = adj_params<L, T>(e);
         const StepRecord<T> r = um ? record_at<T>(e, rec) : StepRecord<T>{};
-        const LinkGrad lgr{e.d_lkderiv, e.d_gq, e.d_gs};
+        const LinkGrad lgr{e.d_lkderiv, e.d_gq, (uint32_t)std::max<int64_t>(e.n_links, 1)};
         if (waves.count)
             hipLaunchKernelGGL(kern, dim3(wave_blocks(waves.count)), dim3(BX), 0, e.stream,
                                um ? nullptr : (const T*)fwd->f, r,

@@ -392,17 +392,17 @@ int adjoint_begin(lbm_t* h) {
     const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
     if (!e.d_gq || e.gglob_len != nb || e.gq_len != (int64_t)L1) {
         free_dev(e.d_gq);
-        free_dev(e.d_gs);
         free_dev(e.d_gglob);
-        if (hipMalloc((void**)&e.d_gq, L1 * 8) != hipSuccess ||
-            hipMalloc((void**)&e.d_gs, L1 * 8) != hipSuccess ||
+        e.d_gs = nullptr;
+        // the two per-link sums in one allocation: gq, then gs
+        if (hipMalloc((void**)&e.d_gq, 2 * L1 * 8) != hipSuccess ||
             hipMalloc((void**)&e.d_gglob, (size_t)nb * NC * 8) != hipSuccess)
             return fail(h, LBM_ENOMEM, "gradient accumulator allocation failed");
+        e.d_gs = e.d_gq + L1;
         e.gglob_len = nb;
         e.gq_len = (int64_t)L1;
     }
-    if ((rc = zero(h, e.d_gq, L1 * 8))) return rc;
-    if ((rc = zero(h, e.d_gs, L1 * 8))) return rc;
+    if ((rc = zero(h, e.d_gq, 2 * L1 * 8))) return rc;
     if ((rc = zero(h, e.d_gglob, (size_t)nb * NC * 8))) return rc;
     if ((rc = zero(h, e.lam[0], lam_bytes))) return rc;
     e.adj_next = e.run_n - 1;
@@ -1303,7 +1303,7 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_lkd1d);
     free_dev(e.d_obj_acc);
     free_dev(e.d_gq);
-    free_dev(e.d_gs);
+    e.d_gs = nullptr;
     free_dev(e.d_gglob);
     free_dev(e.d_scratch);
     if (e.ev0) (void)hipEventDestroy(e.ev0);

@@ -124,7 +124,8 @@ struct Engine {
     std::vector<void*> rec_last;        // per segment: record of its last step
     std::vector<void*> rec_pool;        // per replayed step r of a segment
     double* d_gq = nullptr;             // per link: sum of a_k (dc1 f_ibar + dc2 f'_i + dc3 f'_ibar)
-    double* d_gs = nullptr;             // per link: sum of a_k ws (the wall-data terms' factor)
+    double* d_gs = nullptr;             // per link: sum of a_k ws (the wall-data terms' factor);
+                                        // d_gq + max(L, 1), same allocation
     double* d_gglob = nullptr;          // per-block partials of dJ/dg (D) and dJ/ds (Q)
     int64_t gglob_len = 0;
     bool have_grad = false;
