@@ -289,6 +289,8 @@ def per_config_forward(binding, torch, windows=3):
             pat = pattern_rate(binding, torch, geom.lattice, geom.shape, prec, Q)
             res[prec] = {"ms_per_step": round(ms, 5), "kernel_ms": round(kms, 5),
                          "mlups": round(geom.n_nodes / (ms * 1e-3) / 1e6, 1),
+                         "fluid_mlups": round(geom.n_fluid / (ms * 1e-3) / 1e6, 1),
+                         "algorithmic_GBps": round(by / (kms * 1e-3) / 1e9, 1),
                          "hbm_frac": round(by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          "pattern_ceiling_GBps": round(pat, 1),
                          "frac_of_pattern": round(by / (kms * 1e-3) / 1e9 / pat, 4)}
@@ -744,8 +746,10 @@ def main():
             "frac_of_pattern_ceiling": round((traffic or kbytes32) / (kms32 * 1e-3) / 1e9 / pattern, 4),
         },
         "windows_ms_per_step": [round(v, 4) for v in walls32],
+        "fluid_mlups": round(NF / (ms32 * 1e-3) / 1e6, 1),
         "fp64": {
             "mlups": round(mlups64, 1), "ms_per_step": round(ms64, 4),
+            "fluid_mlups": round(NF / (ms64 * 1e-3) / 1e6, 1),
             "kernel_ms": round(kms64, 4),
             "hbm_frac": round(bytes64 / (kms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "fp32_over_fp64_speedup": round(ms64 / ms32, 3),
