@@ -303,6 +303,47 @@ def per_config_forward(binding, torch, windows=3):
     return out
 
 
+def next_rows_forward(binding, torch, geom, w, steps=100, windows=3):
+    """The forward step of the follow-on variants on the benchmark workload
+    (256^3, same spheres and seam): the two-node scheme Eq. (211), the b
+    family Eq. (213) at b = 0.7, TRT through the MRT rates, and the D3Q15
+    lattice on the same spheres; FP32 (and FP64 for D3Q15).  Kernel time
+    from HIP events, medians over `windows` windows; the HBM fraction by the
+    scope table's bytes for the variant's Q."""
+    from workloads import configs
+    from workloads import geometry as G
+    out = {}
+
+    def one(g, s, prec, Q, collision=None, **kw):
+        sv = binding.solver_for(g, s, g=w.g, precision=prec, dp=w.dp, l_rule=w.l_rule, **kw)
+        if collision:
+            sv.set_collision(*collision)
+        sv.init()
+        sv.step(20)
+        walls, kers = timed_windows(sv, steps, windows)
+        sv.close()
+        ms, kms = float(np.median(walls)), float(np.median(kers))
+        by = algorithmic_bytes(Q, 4 if prec == "fp32" else 8, g.n_nodes, g.n_fluid, g.n_links)
+        return {"ms_per_step": round(ms, 5), "kernel_ms": round(kms, 5),
+                "mlups": round(g.n_nodes / (ms * 1e-3) / 1e6, 1),
+                "hbm_frac": round(by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    out["two_node_eq211_fp32"] = one(geom, w.s, "fp32", 19, two_node=True)
+    out["b_0.7_eq213_fp32"] = one(geom, w.s, "fp32", 19, b=0.7)
+    out["trt_fp32"] = one(geom, w.s, "fp32", 19, collision=("trt", 1.0 / 0.7))
+    n = geom.shape[0]
+    g15 = G.random_spheres(n, n, n, 120, 10.0, 20.0, 3, x_bc="pressure", lattice="D3Q15")
+    s15 = configs.d3q15_paper_rates(1.0 / 0.7)
+    res = {"n_fluid": g15.n_fluid, "n_links": g15.n_links}
+    for prec in ("fp32", "fp64"):
+        res[prec] = one(g15, s15, prec, 15)
+        res[prec]["pattern_ceiling_GBps"] = round(
+            pattern_rate(binding, torch, "D3Q15", g15.shape, prec, 15), 1)
+    out["d3q15_256"] = res
+    del g15
+    return out
+
+
 def all_configs(binding, torch):
     """Every benchmark workload: MLUPS and HBM fraction per precision,
     accuracy figures, and the checkpointed adjoints of C4 and C5."""
@@ -787,6 +828,8 @@ def main():
         },
     }
     if not args.no_configs:
+        _progress("follow-on variants of the step")
+        out["next_rows"] = next_rows_forward(binding, torch, geom, w)
         del geom
         _progress("forward step of every workload")
         out["per_config"] = per_config_forward(binding, torch)
