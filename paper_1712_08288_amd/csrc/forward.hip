@@ -111,6 +111,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
        T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
        Grid g, Params<L, T> p, StepObjective ob, StepRecord<T> rec) {
     __shared__ LinkStage<T> stage[BX / 64];
+    __shared__ double c1s[BX / 64][64];   // Eq. (211): c1 of the wave's links
     const NodePos pos = node_of_thread<ROWS>(g);
     const uint32_t lb = blockIdx.x;
     const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -135,6 +136,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         // slot reads and the info word first, the plane reads without
         // waiting for either
         const T wa0 = lane < nlw ? waA[wbase + lane] : T(0);
+        const double c1v = p.c1d && lane < nlw ? p.c1d[wbase + lane] : 0.0;
         const bool live = pos.in && lane_in_live_segment<T>(wv.x, lane);
         const uint32_t info = live ? nm.info[pos.n] : kInfoSolid;
         T f[L::Q];
@@ -146,7 +148,7 @@ k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
         const bool sol = is_solid(info);
         const NodeLinks nl = sol ? NodeLinks{0u, 0u} : node_links(info, 0u);
         wave_link_values<L, T>(waA, wbase, lane, wa0, nl, stage[wid], f);
-        if (p.c1d) complete_two_node<L, T>(p.c1d + wbase, nl, f);
+        if (p.c1d) wave_two_node<L, T>(p.c1d + wbase, lane, c1v, nl, c1s[wid], f);
         T fpre[L::Q];
         unroll<L::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;

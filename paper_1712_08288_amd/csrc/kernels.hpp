@@ -525,6 +525,32 @@ __device__ __forceinline__ void wave_link_values(const T* __restrict__ wa, uint3
     wave_lds_sync();
 }
 
+// Eq. (211) completion for a mixed wave (see complete_two_node; c1d indexed
+// like nl.base): the c1 values of the wave's first 64 links come from their
+// link lanes, which load them coalesced with the slot reads (c1v =
+// c1d[lane] below the wave's link count), through a per-wave LDS row.
+template <class L, class T>
+__device__ __forceinline__ void wave_two_node(const double* __restrict__ c1d, uint32_t lane,
+                                              double c1v, const NodeLinks& nl,
+                                              double (&c1s)[64], T (&f)[L::Q]) {
+    c1s[lane] = c1v;
+    wave_lds_sync();
+    if (!nl.mask) return;
+    uint32_t k = nl.base;
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ib = TAB<L>.opp[i];
+        if constexpr (i > 0) {
+            const uint32_t bit = (nl.mask >> i) & 1u;
+            if (bit) {
+                const double c = k < 64u ? c1s[k] : c1d[k];
+                if (c != 0.0) f[i] = (T)((double)f[i] + c * (double)f[ib]);
+            }
+            k += bit;
+        }
+    });
+}
+
 // Pull the pre-collision state f(x, t) of one fluid node.
 template <class L, class T, int XB, bool PRED = false, bool FTAB = false>
 __device__ __forceinline__ void pull(const T* __restrict__ A, const T* __restrict__ wa,
