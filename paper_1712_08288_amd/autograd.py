@@ -10,6 +10,11 @@ of steps, the checkpoint interval and the objective.  forward() runs the
 steps with a snapshot every `every` steps (sqrt(n) checkpointing when
 every ~ sqrt(n)); backward() replays each segment and runs the adjoint
 kernel backwards through it, returning dJ/dq, dJ/dwall_u, dJ/dg, dJ/ds.
+When s does not require a gradient, forward() turns the solver's rate
+gradients off (lbm_set_rate_gradient), so that with the single-node scheme
+the reverse sweep reads the forward step records instead of the states
+(every = 1 then keeps no snapshot at all); the returned gradient of s is
+then None.
 """
 
 from dataclasses import dataclass, field
@@ -47,6 +52,7 @@ class LBMObjective(torch.autograd.Function):
         else:
             problem.init(sv)
         sv.set_objective(problem.objective, problem.tag, *problem.window, planes=problem.planes)
+        sv.set_rate_gradient(bool(ctx.needs_input_grad[3]))
         sv.run_checkpointed(problem.steps, problem.every)
         J = sv.objective()
         problem.last_J = J
@@ -72,6 +78,8 @@ class LBMObjective(torch.autograd.Function):
         outs = []
         for key, (dev, dt, shape) in zip(("q", "wall_u", "g", "s"), ctx.meta):
             outs.append((gr[key] * scale).to(dtype=dt).reshape(shape).to(dev))
+        if not ctx.needs_input_grad[3]:
+            outs[3] = None
         return outs[0], outs[1], outs[2], outs[3], None
 
 

@@ -416,6 +416,34 @@ def test_autograd_function_matches_adjoint(dev):
     sv2.close()
 
 
+@pytest.mark.parametrize("every", [4, 1])
+def test_autograd_without_rate_gradient_reads_step_records(every):
+    """With s not requiring a gradient the autograd function turns the rate
+    gradients off, so the sweep reads step records (every = 1: no snapshot):
+    the other gradients equal those of the state-reading sweep to 1e-14."""
+    import torch
+    from paper_1712_08288_amd import binding
+    from paper_1712_08288_amd.autograd import Problem, objective
+    name, mk_geom, mk_s, kw, obj, steps = CASES[1]
+    geom, s = mk_geom(), mk_s()
+    sv = binding.solver_for(geom, s, l_rule=kw["l_rule"])
+    prob = Problem(sv, steps=steps, every=every, objective="force_x", tag=1,
+                   window=(obj.t0, obj.t1))
+    q = torch.tensor(geom.q, device="cuda", requires_grad=True)
+    wu = torch.tensor(geom.wall_u, device="cuda", requires_grad=True)
+    g = torch.zeros(2, dtype=torch.float64, device="cuda", requires_grad=True)
+    ss = torch.tensor(s, dtype=torch.float64, device="cuda")
+    J = objective(q, wu, g, ss, prob)
+    J.backward()
+    sv2, J2, gr = _gpu_grad(geom, s, kw, obj, steps, 4, np.zeros((9, geom.n_nodes)))
+    assert float(J) == J2
+    for got, key in ((q.grad, "q"), (wu.grad, "wall_u"), (g.grad, "g")):
+        scale = max(np.abs(gr[key]).max(), 1e-300)
+        assert np.abs(got.cpu().numpy() - gr[key]).max() <= 1e-14 * scale, key
+    sv.close()
+    sv2.close()
+
+
 def test_device_gradients_equal_host_gradients():
     """lbm_grad_device puts the per-link gradients in the caller's order on
     the device, bit for bit what lbm_grad returns on the host."""
