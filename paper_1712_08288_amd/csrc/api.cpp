@@ -377,10 +377,11 @@ int adjoint_begin(lbm_t* h) {
     // last (the run recorded that one) through two ping-pong states;
     // otherwise pool[r] holds the replayed state r of a segment (state 0 is
     // the checkpoint itself, so pool[0] stays empty)
-    if (e.adj_um && e.run_every > 1 &&
-        (rc = alloc_list(h, e.rec_pool, (size_t)(e.run_every - 1), rec_bytes(e))))
+    const int64_t seg = std::min(e.run_every, e.run_n);   // the longest segment
+    if (e.adj_um && seg > 1 &&
+        (rc = alloc_list(h, e.rec_pool, (size_t)(seg - 1), rec_bytes(e))))
         return rc;
-    const size_t npool = e.adj_um ? (e.run_every > 1 ? 2 : 0) : (size_t)e.run_every + 1;
+    const size_t npool = e.adj_um ? (seg > 1 ? 2 : 0) : (size_t)seg + 1;
     if (e.pool.size() != npool) {
         for (auto& s : e.pool) free_snap(s);
         e.pool.assign(npool, Snapshot{});

@@ -248,7 +248,7 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     geom, s = mk_geom(), mk_s()
     df0 = states.random_deviation(9, geom.n_nodes, seed=5, amp=2e-3)
     out = []
-    for every in (1, 3, 5, steps):
+    for every in (1, 3, 5, steps, 10 ** 6):   # an interval past the run: one segment
         sv, J, gr = _gpu_grad(geom, s, kw, obj, steps, every, df0)
         out.append((J, gr))
         sv.close()
