@@ -262,15 +262,15 @@ int lbm_objective(lbm_t *h, double *J);
  * are kept for the next run with the same snapshot count.  Memory: ceil(n /
  * every) snapshots, plus `every` replay states and two adjoint arrays
  * allocated by lbm_adjoint(), all of lbm_state_bytes().
- * With the rate gradients off and the single-node scheme the reverse sweep
- * reads step records instead of states (see lbm_set_rate_gradient): the run
- * records the last step of every segment, lbm_adjoint() replays each
- * segment through two states recording its other steps, and every = 1
- * records every step and keeps no snapshot (no replay at all).  A record is
- * D values per node plus 3 per cut link, in the handle's precision; memory
- * ceil(n / every) records, plus every - 1 records and two states for the
- * replay when every > 1.  The objective accumulates as in lbm_step.
- * Errors: ESTATE, EINVAL, ENOMEM. */
+ * With the rate gradients off the reverse sweep reads step records instead
+ * of states (see lbm_set_rate_gradient): the run records the last step of
+ * every segment, lbm_adjoint() replays each segment through two states
+ * recording its other steps, and every = 1 records every step and keeps no
+ * snapshot (no replay at all).  A record is D values per node plus 3 per
+ * cut link, in the handle's precision; memory ceil(n / every) records, plus
+ * every - 1 records and two states for the replay when every > 1 (and, with
+ * Eq. (211), two more runs of one value per link).  The objective
+ * accumulates as in lbm_step.  Errors: ESTATE, EINVAL, ENOMEM. */
 int lbm_run_checkpointed(lbm_t *h, int64_t n, int64_t every);
 
 /* Reverse sweep over the last lbm_run_checkpointed() run: for each segment
@@ -301,15 +301,16 @@ int64_t lbm_adjoint_remaining(const lbm_t *h);
 
 /* Choose whether lbm_adjoint() accumulates dJ/ds for the relaxation rates
  * (a block reduction of Q extra sums per step; default on).  When off,
- * lbm_grad() reports zeros for ds, and with the single-node scheme the
- * reverse sweep reads, for each forward step, a record of the velocity u of
- * the state it starts from (the equilibrium's Jacobian depends on u alone)
- * and of the three forward values of each cut link's gradient, f_ibar(x_f,
- * t), f'_i(x_f, t) and f'_ibar(x_f, t), instead of the states (see
- * lbm_run_checkpointed; the gradients are the same).  Takes effect at the
- * next lbm_run_checkpointed(); a sweep over a run that kept records only
- * (every = 1) while the rate gradients are on or Eq. (211) is selected
- * fails with ESTATE. */
+ * lbm_grad() reports zeros for ds, and the reverse sweep reads, for each
+ * forward step, a record of the velocity u of the state it starts from (the
+ * equilibrium's Jacobian depends on u alone) and of the three forward values
+ * of each cut link's gradient, f_ibar(x_f, t), f'_i(x_f, t) and
+ * f'_ibar(x_f, t), instead of the states (see lbm_run_checkpointed; the
+ * gradients are the same).  Takes effect at the next lbm_run_checkpointed();
+ * a sweep over a run that kept records only (every = 1) while the rate
+ * gradients are on fails with ESTATE, and so does any sweep after the
+ * boundary scheme (Eq. (210)/(213) or Eq. (211)) was changed since the
+ * run. */
 int lbm_set_rate_gradient(lbm_t *h, int on);
 
 /* Gradients of J from the last lbm_adjoint(), in double: dq[k] = dJ/dgamma_k

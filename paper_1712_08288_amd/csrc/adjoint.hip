@@ -598,10 +598,13 @@ k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
 // Eq. (211) links k = (x_f, i) with a deferred c1: the link value is
 // f_i(x_f, t+1) = (terms at t) + c1 f_ibar(x_f, t+1), so its adjoint a_k also
 // reaches f_ibar(x_f, t+1) (whose own adjoint the node x_f + e_i gathers in
-// the next kernel) and dJ/dgamma gets a_k dc1 f_ibar(x_f, t+1).
+// the next kernel) and dJ/dgamma gets a_k dc1 f_ibar(x_f, t+1).  That value
+// is pulled from the state at t+1 (A_next), or read from fib_next (the
+// link values of the step record of t+1, or of the run's final state).
 template <class L, class T, int XB>
 __global__ void __launch_bounds__(BX)
-k_two_node_pre(const T* __restrict__ A_next, T* __restrict__ lam_in,
+k_two_node_pre(const T* __restrict__ A_next, const T* __restrict__ fib_next,
+               T* __restrict__ lam_in,
                const int32_t* __restrict__ lknode, const uint8_t* __restrict__ lkdir,
                const int32_t* __restrict__ lktag, const double* __restrict__ c1d,
                const double* __restrict__ d1d, double* __restrict__ gq,
@@ -624,7 +627,27 @@ k_two_node_pre(const T* __restrict__ A_next, T* __restrict__ lam_in,
     if (a.obj_kind == 1 && ex != 0 && lktag[k] == a.obj_tag) ak += -(double)ex * a.w_force;
     T* dst = lam_in + pop_at<L::Q>(ib, n);
     *dst = (T)((double)*dst + c * ak);
-    gq[k] += ak * d1d[k] * (double)pull_one<L, T, XB>(A_next, g, p, n, ib);
+    const T fib = fib_next ? fib_next[k] : pull_one<L, T, XB>(A_next, g, p, n, ib);
+    gq[k] += ak * d1d[k] * (double)fib;
+}
+
+// The value f_ibar(x_f, t) that the pull of the opposite direction reads at
+// each link's node from the state A (for Eq. (211) links the plain pull:
+// their opposite direction is no cut link), into out[k].
+template <class L, class T, int XB>
+__global__ void __launch_bounds__(BX)
+k_link_pull(const T* __restrict__ A, const int32_t* __restrict__ lknode,
+            const uint8_t* __restrict__ lkdir, uint32_t n_links, Grid g, Params<L, T> p,
+            T* __restrict__ out) {
+    const uint32_t k = blockIdx.x * BX + threadIdx.x;
+    if (k >= n_links) return;
+    int ib = 0;
+    const int i = lkdir[k];
+    unroll<L::Q>([&](auto I) {
+        constexpr int ii = decltype(I)::value;
+        if (ii == i) ib = TAB<L>.opp[ii];
+    });
+    out[k] = pull_one<L, T, XB>(A, g, p, (uint32_t)lknode[k], ib);
 }
 
 template <class L, class T>
@@ -756,8 +779,8 @@ hipError_t launch_link_gradients(Engine& e, double* dq, double* dphi) {
     return go(D3Q19{});
 }
 
-hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in,
-                                   const AdjointObjective& obj) {
+hipError_t launch_two_node_adjoint(Engine& e, const Snapshot* next, const void* fib_next,
+                                   void* lam_in, const AdjointObjective& obj) {
     if (e.n_links == 0) return hipSuccess;
     const Grid g = adj_grid(e);
     AdjArgs a;
@@ -774,9 +797,25 @@ hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in
         using T = decltype(prec);
         constexpr int XB = decltype(xb)::value;
         hipLaunchKernelGGL((k_two_node_pre<L, T, XB>), dim3(nb), dim3(BX), 0, e.stream,
-                           (const T*)next.f, (T*)lam_in, e.d_lknode, e.d_lkdir, e.d_lktag,
+                           next ? (const T*)next->f : nullptr, (const T*)fib_next,
+                           (T*)lam_in, e.d_lknode, e.d_lkdir, e.d_lktag,
                            e.d_lkc1d, e.d_lkd1d, e.d_gq, (uint32_t)e.n_links, g,
                            adj_params<L, T>(e), a);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_link_pull(Engine& e, const Snapshot& s, void* out) {
+    if (e.n_links == 0) return hipSuccess;
+    const Grid g = adj_grid(e);
+    const unsigned nb = (unsigned)((e.n_links + BX - 1) / BX);
+    return adj_dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
+        using L = decltype(lat);
+        using T = decltype(prec);
+        constexpr int XB = decltype(xb)::value;
+        hipLaunchKernelGGL((k_link_pull<L, T, XB>), dim3(nb), dim3(BX), 0, e.stream,
+                           (const T*)s.f, e.d_lknode, e.d_lkdir, (uint32_t)e.n_links, g,
+                           adj_params<L, T>(e), (T*)out);
         return hipGetLastError();
     });
 }

@@ -105,8 +105,13 @@ size_t f_bytes(const Engine& e) { return (size_t)e.Q * (size_t)e.S * e.elem; }
 size_t rec_bytes(const Engine& e) { return (size_t)lbe::record_values(e) * e.elem; }
 
 // the reverse sweep can run on step records instead of the forward states
-// (see Engine::rec_last)
-bool velocity_mode(const Engine& e) { return !e.want_ds && !e.two_node; }
+// (see Engine::rec_last): everything but the rate gradients
+bool velocity_mode(const Engine& e) { return !e.want_ds; }
+
+// the link run (f_ibar(x_f, t) of every link) of a step record
+const void* record_links(const Engine& e, const void* rec) {
+    return (const char*)rec + (size_t)e.D * (size_t)e.S * e.elem;
+}
 
 void free_list(std::vector<void*>& v) {
     for (auto& p : v)
@@ -292,6 +297,8 @@ void free_run(Engine& e) {
     e.pool.clear();
     free_list(e.rec_last);
     free_list(e.rec_pool);
+    free_dev(e.fib_final);
+    free_dev(e.fib_next);
     e.run_urec = false;
     for (auto& l : e.lam) {
         if (l) (void)hipFree(l);
@@ -363,8 +370,10 @@ int adjoint_begin(lbm_t* h) {
     e.adj_um = e.run_urec && velocity_mode(e);
     if (e.ckpt.empty() && !e.adj_um)
         return fail(h, LBM_ESTATE,
-                    "the run kept step records only (rate gradients off, single-node scheme); "
+                    "the run kept step records only (rate gradients off); "
                     "run it again with the current settings");
+    if (e.two_node != e.run_two_node || (e.adj_um && e.two_node && !e.fib_final))
+        return fail(h, LBM_ESTATE, "the boundary scheme changed since the run; run it again");
     int rc;
     const size_t lam_bytes = f_bytes(e);
     for (auto& l : e.lam) {
@@ -381,6 +390,11 @@ int adjoint_begin(lbm_t* h) {
     if (e.adj_um && seg > 1 &&
         (rc = alloc_list(h, e.rec_pool, (size_t)(seg - 1), rec_bytes(e))))
         return rc;
+    if (e.adj_um && e.two_node && !e.fib_next &&
+        hipMalloc(&e.fib_next, wa_bytes(e)) != hipSuccess) {
+        e.fib_next = nullptr;
+        return fail(h, LBM_ENOMEM, "device allocation of link values failed");
+    }
     const size_t npool = e.adj_um ? (seg > 1 ? 2 : 0) : (size_t)seg + 1;
     if (e.pool.size() != npool) {
         for (auto& s : e.pool) free_snap(s);
@@ -436,6 +450,19 @@ int adjoint_steps(lbm_t* h, int64_t n) {
             return e.pool[k];
         };
         if (e.adj_seg != j) {
+            // Eq. (211) on records: keep f_ibar(x_f, .) at the first step of
+            // segment j+1 (its record is about to be overwritten) for the
+            // last step of segment j
+            if (um && e.two_node && e.adj_seg == j + 1 &&
+                std::min(e.run_every, e.run_n - (j + 1) * e.run_every) >= 2) {
+                const hipError_t cs = hipMemcpyAsync(e.fib_next, record_links(e, e.rec_pool[0]),
+                                                     wa_bytes(e), hipMemcpyDeviceToDevice,
+                                                     e.stream);
+                if (cs != hipSuccess) {
+                    rc = fail(h, LBM_EDEVICE, std::string("link values: ") + hipGetErrorString(cs));
+                    break;
+                }
+            }
             if (um) {
                 // records of steps 0 .. len-2 (the run recorded step len-1)
                 for (int64_t k = 0; k + 1 < len; ++k) {
@@ -469,8 +496,24 @@ int adjoint_steps(lbm_t* h, int64_t n) {
         e.wall_scale = e.wall_decay == 1.0 ? 1.0 : std::pow(e.wall_decay, (double)t);
         if (e.poison)   // LBM_DEBUG: lambda(t) slots the step does not write stay NaN
             st = lbe::launch_fill_nan(e, e.lam[lc ^ 1], (size_t)e.Q * (size_t)e.S);
-        if (e.two_node && st == hipSuccess)
-            st = lbe::launch_two_node_adjoint(e, state(r + 1), e.lam[lc], ao);
+        if (e.two_node && st == hipSuccess) {
+            if (um) {
+                // f_ibar(x_f, t+1): the record of step t+1, or where the
+                // next segment or the run ends
+                const void* fibn;
+                if (r + 1 < len)
+                    fibn = record_links(e, r + 1 == len - 1 ? e.rec_last[j] : e.rec_pool[r + 1]);
+                else if (j + 1 == nseg)
+                    fibn = e.fib_final;
+                else if (std::min(e.run_every, e.run_n - (j + 1) * e.run_every) >= 2)
+                    fibn = e.fib_next;
+                else
+                    fibn = record_links(e, e.rec_last[j + 1]);
+                st = lbe::launch_two_node_adjoint(e, nullptr, fibn, e.lam[lc], ao);
+            } else {
+                st = lbe::launch_two_node_adjoint(e, &state(r + 1), nullptr, e.lam[lc], ao);
+            }
+        }
         if (st == hipSuccess) {
             if (um)
                 st = lbe::launch_adjoint_step(e, nullptr, nullptr,
@@ -1118,6 +1161,7 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
     // the record of each segment's last step, for a reverse sweep on step
     // records (the replay records the others)
     e.run_urec = urec;
+    e.run_two_node = e.two_node;
     if (urec) {
         const int rc = alloc_list(h, e.rec_last, (size_t)nseg, rec_bytes(e));
         if (rc) {
@@ -1140,10 +1184,27 @@ int lbm_run_checkpointed(lbm_t* h, int64_t n, int64_t every) {
         }
         const bool seg_end = (s + 1) % every == 0 || s + 1 == n;
         void* rec = urec && seg_end ? e.rec_last[s / every] : nullptr;
-        if ((rc = forward_step(h, *in, e.buf[e.cur ^ 1], true, rec))) return rc;
+        if ((rc = forward_step(h, *in, e.buf[e.cur ^ 1], true, rec))) {
+            e.run_t0 = -1;   // no sweep over a run that did not finish
+            return rc;
+        }
         e.cur ^= 1;
         ++e.t;
         e.stepped = true;
+    }
+    // Eq. (211) on records: f_ibar(x_f, t) of every link at the final state,
+    // for the run's last reverse step
+    if (urec && e.two_node) {
+        if (!e.fib_final && hipMalloc(&e.fib_final, wa_bytes(e)) != hipSuccess) {
+            e.fib_final = nullptr;
+            e.run_t0 = -1;
+            return fail(h, LBM_ENOMEM, "device allocation of link values failed");
+        }
+        const hipError_t st = lbe::launch_link_pull(e, e.buf[e.cur], e.fib_final);
+        if (st != hipSuccess) {
+            e.run_t0 = -1;
+            return fail(h, LBM_EDEVICE, std::string("link values: ") + hipGetErrorString(st));
+        }
     }
     e.have_grad = false;
     e.adj_started = false;

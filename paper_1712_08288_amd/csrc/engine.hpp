@@ -114,13 +114,19 @@ struct Engine {
                                         // (ping-pong) when the sweep reads records
     int64_t run_t0 = -1, run_n = 0, run_every = 0;
     void* lam[2] = {nullptr, nullptr};  // adjoint arrays (Q*N values of T)
-    // With the rate gradients off and the single-node scheme, the reverse
-    // sweep reads step records (StepRecord) instead of the forward states:
+    // With the rate gradients off the reverse sweep reads step records
+    // (StepRecord) instead of the forward states:
     // the checkpointed run records the last step of every segment, the
     // replay of a segment the others.  With a segment of one step the run
     // records every step and keeps no snapshot.
     bool run_urec = false;              // the last run recorded rec_last
+    bool run_two_node = false;          // the last run used Eq. (211)
     bool adj_um = false;                // the current sweep reads records
+    // Eq. (211) on records: f_ibar(x_f, .) of every link at the run's final
+    // state, and at the first step of the segment after the one being
+    // reversed (kept before the replay pool is overwritten); L values each
+    void* fib_final = nullptr;
+    void* fib_next = nullptr;
     std::vector<void*> rec_last;        // per segment: record of its last step
     std::vector<void*> rec_pool;        // per replayed step r of a segment
     double* d_gq = nullptr;             // per link: sum of a_k (dc1 f_ibar + dc2 f'_i + dc3 f'_ibar)
@@ -239,9 +245,14 @@ hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
 // null
 hipError_t launch_link_gradients(Engine& e, double* dq, double* dphi);
 // Eq. (211) links: move c1 * (adjoint of f_i(x_f, t+1)) onto the adjoint of
-// f_ibar(x_f, t+1) and add the gamma-derivative of that term, using the
-// forward state at t+1 in `next`.
-hipError_t launch_two_node_adjoint(Engine& e, const Snapshot& next, void* lam_in,
-                                   const AdjointObjective& obj);
+// f_ibar(x_f, t+1) and add the gamma-derivative of that term, with
+// f_ibar(x_f, t+1) pulled from the forward state at t+1 (`next`) or read
+// from fib_next (L values of T: the link run of the record of step t+1);
+// exactly one of the two is given.
+hipError_t launch_two_node_adjoint(Engine& e, const Snapshot* next, const void* fib_next,
+                                   void* lam_in, const AdjointObjective& obj);
+// out[k] = f_ibar(x_f, t) as the pull of the opposite direction at link k's
+// node reads it from the state s (L values of T)
+hipError_t launch_link_pull(Engine& e, const Snapshot& s, void* out);
 
 }  // namespace lbe

@@ -142,15 +142,13 @@ def test_adjoint_matches_oracle_reverse(case):
     sv.close()
 
 
-SINGLE_NODE = [c for c in CASES if not c[3].get("two_node", False)]
-
-
-@pytest.mark.parametrize("case", SINGLE_NODE, ids=[c[0] for c in SINGLE_NODE])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_velocity_mode_matches_oracle_reverse(case):
-    """Rate gradients off: the reverse sweep reads the velocities the forward
-    steps recorded instead of pulling the forward populations.  Against the
-    oracle's reverse sweep at 1e-10, and against the population-reading sweep
-    of the same run (the same arithmetic on the same velocity)."""
+    """Rate gradients off: the reverse sweep reads the step records the
+    forward steps wrote (velocity, link values; with Eq. (211) also the
+    advected f_ibar of the next step) instead of the forward states.  Against
+    the oracle's reverse sweep at 1e-10, and against the state-reading sweep
+    of the same run (the same arithmetic on the same values)."""
     name, mk_geom, mk_s, kw, obj, steps = case
     geom, s = mk_geom(), mk_s()
     print("case", name, flush=True)
@@ -181,13 +179,15 @@ def test_velocity_mode_matches_oracle_reverse(case):
     assert np.all(gu["s"] == 0.0)
 
 
+@pytest.mark.parametrize("case_name", ["d3q19_pdrop_seam", "d3q19_meanux_two_node_seam"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_velocity_mode_is_independent_of_the_checkpoints(precision):
-    """Velocities recorded at segment ends (checkpointed run) and by the
-    replay (other states) cover every step for any interval, and the sweep
-    in uneven pieces equals the whole sweep, bit for bit."""
+def test_velocity_mode_is_independent_of_the_checkpoints(precision, case_name):
+    """Records written at segment ends (checkpointed run) and by the replay
+    (other steps) cover every step for any interval -- with Eq. (211) also
+    the next step's f_ibar across segment ends and at the run's end -- and
+    the sweep in uneven pieces equals the whole sweep, bit for bit."""
     from paper_1712_08288_amd import binding
-    name, mk_geom, mk_s, kw, obj, steps = [c for c in CASES if c[0] == "d3q19_pdrop_seam"][0]
+    name, mk_geom, mk_s, kw, obj, steps = [c for c in CASES if c[0] == case_name][0]
     geom, s = mk_geom(), mk_s()
     df0 = states.random_deviation(19, geom.n_nodes, seed=6, amp=2e-3)
     out = []
@@ -199,7 +199,9 @@ def test_velocity_mode_is_independent_of_the_checkpoints(precision):
         assert J == out[0][0]
         for key in ("q", "wall_u", "g", "lam0"):
             assert np.array_equal(gr[key], out[0][1][key]), key
-    sv = binding.solver_for(geom, s, precision=precision, dp=kw["dp"], l_rule=kw["l_rule"])
+    sv = binding.solver_for(geom, s, precision=precision, g=kw.get("g"), dp=kw.get("dp", 0.0),
+                            l_rule=kw.get("l_rule", "min"), b=kw.get("b", 1.0),
+                            two_node=kw.get("two_node", False))
     sv.set_rate_gradient(False)
     sv.init_deviation(df0)
     sv.set_objective(obj.kind, obj.tag, obj.t0, obj.t1, planes=obj.planes)
