@@ -11,10 +11,9 @@ steps with a snapshot every `every` steps (sqrt(n) checkpointing when
 every ~ sqrt(n)); backward() replays each segment and runs the adjoint
 kernel backwards through it, returning dJ/dq, dJ/dwall_u, dJ/dg, dJ/ds.
 When s does not require a gradient, forward() turns the solver's rate
-gradients off (lbm_set_rate_gradient), so that with the single-node scheme
-the reverse sweep reads the forward step records instead of the states
-(every = 1 then keeps no snapshot at all); the returned gradient of s is
-then None.
+gradients off (lbm_set_rate_gradient), so that the reverse sweep reads the
+forward step records instead of the states (every = 1 then keeps no
+snapshot at all); the returned gradient of s is then None.
 """
 
 from dataclasses import dataclass, field

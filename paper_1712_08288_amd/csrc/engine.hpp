@@ -234,7 +234,7 @@ struct AdjointObjective {
 };
 // One reverse step: lambda(t) from lambda(t+1) with the forward states at t
 // (`fwd`) and t+1 (`next`), accumulating the gradients.  rec: the record of
-// forward step t (rate gradients off, single-node scheme; fwd and next are
+// forward step t (rate gradients off; fwd and next are
 // then not read and may be null), or null to read the states.
 hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* next,
                                const void* rec, const void* lam_in, void* lam_out,
