@@ -103,6 +103,39 @@ __device__ __forceinline__ void link_gradient_rec(const LinkGrad& lg, const T* _
     link_gradient(lg, k, ak, lk[k], lk[lg.L1 + k], lk[2 * lg.L1 + k], ws);
 }
 
+// Walk a node's cut links in direction order (links are sorted by node,
+// then direction, so the k-th set bit of the mask is link nl.base + k).  For
+// the wave's first 64 links the two LDS values of the link, st.v[A][k] and
+// st.v[B][k], are read one direction ahead of their use, with the index
+// clamped to the slab instead of a divergent branch around the access, so
+// that the reads overlap; own(I, va, vb, k) consumes them, direct(I, k)
+// handles a link past the 64th.
+template <class L, class T, int A, int B, class Own, class Direct>
+__device__ __forceinline__ void walk_links(const NodeLinks& nl, LinkStage<T>& st, Own&& own,
+                                           Direct&& direct) {
+    uint32_t k = nl.base;
+    uint32_t kk = k < 64u ? k : 63u;
+    T a_next = st.v[A][kk], b_next = st.v[B][kk];
+    unroll<L::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (i > 0) {
+            const uint32_t bit = (nl.mask >> i) & 1u;
+            const T va = a_next, vb = b_next;
+            const uint32_t k1 = k + bit;
+            if constexpr (i + 1 < L::Q) {
+                kk = k1 < 64u ? k1 : 63u;
+                a_next = st.v[A][kk];
+                b_next = st.v[B][kk];
+            }
+            if (bit) {
+                if (k < 64u) own(I, va, vb, k);
+                else direct(I, k);
+            }
+            k = k1;
+        }
+    });
+}
+
 template <int NC>
 __device__ __forceinline__ void block_accumulate(const double (&v)[NC], double* __restrict__ dst) {
     __shared__ double part[BX / 64][NC];
@@ -382,26 +415,20 @@ k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
             // goes back to the link lane (the gradients are taken per link)
             if constexpr (!PLAIN) {
                 if (nl.mask) {
-                    uint32_t k = nl.base;
-                    unroll<Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        constexpr int ib = TAB<L>.opp[i];
-                        if constexpr (i > 0) {
-                            const uint32_t bit = (nl.mask >> i) & 1u;
-                            if (bit) {
-                                if (k < 64u) {
-                                    mu[i] += st.v[0][k];
-                                    mu[ib] += st.v[1][k];
-                                    if constexpr (!UM) st.v[0][k] = f[ib];
-                                } else {
-                                    own_link_direct<L, T, i, UM>(wbase + k, lam_in, nxt, rec,
-                                                                 pos.n, lkcoef, lktag, lgr, p, a,
-                                                                 f, mu);
-                                }
-                            }
-                            k += bit;
-                        }
-                    });
+                    walk_links<L, T, 0, 1>(
+                        nl, st,
+                        [&](auto I, T va, T vb, uint32_t k) {
+                            constexpr int i = decltype(I)::value;
+                            constexpr int ib = TAB<L>.opp[i];
+                            mu[i] += va;
+                            mu[ib] += vb;
+                            if constexpr (!UM) st.v[0][k] = f[ib];
+                        },
+                        [&](auto I, uint32_t k) {
+                            constexpr int i = decltype(I)::value;
+                            own_link_direct<L, T, i, UM>(wbase + k, lam_in, nxt, rec, pos.n,
+                                                         lkcoef, lktag, lgr, p, a, f, mu);
+                        });
                 }
             }
 
@@ -436,24 +463,19 @@ k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
             // its moments are taken, so that they need no registers of their own
             if constexpr (!PLAIN) {
                 if (nl.mask) {
-                    uint32_t k = nl.base;
-                    unroll<Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        constexpr int ib = TAB<L>.opp[i];
-                        if constexpr (i > 0) {
-                            const uint32_t bit = (nl.mask >> i) & 1u;
-                            if (bit) {
-                                if (k < 64u) {
-                                    mu[i] += st.v[2][k];
-                                    mu[ib] += st.v[3][k];
-                                } else {
-                                    own_link_bypass<L, T, i>(wbase + k, lam_in, pos.n,
-                                                             lkcoef, lktag, p, a, mu);
-                                }
-                            }
-                            k += bit;
-                        }
-                    });
+                    walk_links<L, T, 2, 3>(
+                        nl, st,
+                        [&](auto I, T va, T vb, uint32_t) {
+                            constexpr int i = decltype(I)::value;
+                            constexpr int ib = TAB<L>.opp[i];
+                            mu[i] += va;
+                            mu[ib] += vb;
+                        },
+                        [&](auto I, uint32_t k) {
+                            constexpr int i = decltype(I)::value;
+                            own_link_bypass<L, T, i>(wbase + k, lam_in, pos.n, lkcoef, lktag, p,
+                                                     a, mu);
+                        });
                 }
             }
             T r[Q];
