@@ -372,14 +372,15 @@ def test_debug_poison_mode_leaves_the_adjoint_unchanged(monkeypatch, case, rates
         assert np.array_equal(res["0"][1][key], res["1"][1][key]), key
 
 
+@pytest.mark.parametrize("rates", [True, False], ids=["states", "records"])
 @pytest.mark.parametrize("case", [CASES[2], [c for c in CASES if c[0] == "d3q19_meanux_rows256_seam"][0]],
                          ids=["d3q19_meanux_seam", "d3q19_meanux_rows256_seam"])
-def test_fp32_adjoint_is_close_to_fp64(case):
+def test_fp32_adjoint_is_close_to_fp64(case, rates):
     name, mk_geom, mk_s, kw, obj, steps = case
     geom, s = mk_geom(), mk_s()
     df0 = states.random_deviation(19, geom.n_nodes, seed=3, amp=2e-3)
-    sv64, J64, g64 = _gpu_grad(geom, s, kw, obj, steps, 4, df0, "fp64")
-    sv32, J32, g32 = _gpu_grad(geom, s, kw, obj, steps, 4, df0, "fp32")
+    sv64, J64, g64 = _gpu_grad(geom, s, kw, obj, steps, 4, df0, "fp64", rates=rates)
+    sv32, J32, g32 = _gpu_grad(geom, s, kw, obj, steps, 4, df0, "fp32", rates=rates)
     assert abs(J32 - J64) <= 1e-4 * abs(J64)
     for key in ("q", "g"):
         scale = np.abs(g64[key]).max()
