@@ -6,7 +6,7 @@ Timed, each with inputs resident in HBM:
   * FP32 forward step (deviation storage): `value` = MLUPS over all N nodes,
     `ms_per_step` (median of windows of K steps), and the roofline of the
     step kernel from HIP events on the library's stream (algorithmic bytes
-    of the scope table / median launch time);
+    2*Q*s*N_fluid + 48*N_links + N_nodes / median launch time);
   * FP64 forward step: MLUPS and the FP32/FP64 speedup;
   * the velocity difference between FP32 and FP64 after the workload's
     configured 500 steps;
@@ -263,8 +263,8 @@ def pattern_rate(binding, torch, lattice, shape, prec, Q):
 
 def per_config_forward(binding, torch, windows=3):
     """The forward step of every workload in its benchmark precisions, from
-    rest: MLUPS over all nodes, the HBM fraction by the scope table's
-    algorithmic bytes, and the fraction of the step's own access pattern on
+    rest: MLUPS over all nodes, the HBM fraction by the algorithmic bytes
+    2*Q*s*N_fluid + 48*N_links + N_nodes, and the fraction of the step's own access pattern on
     the same grid (periodic, no arithmetic).  Medians over `windows` timed
     windows.  The 256^3 sphere packing is the headline line itself."""
     from workloads import configs
@@ -309,7 +309,7 @@ def next_rows_forward(binding, torch, geom, w, steps=100, windows=3):
     family Eq. (213) at b = 0.7, TRT through the MRT rates, and the D3Q15
     lattice on the same spheres; FP32 (and FP64 for D3Q15).  Kernel time
     from HIP events, medians over `windows` windows; the HBM fraction by the
-    scope table's bytes for the variant's Q."""
+    same algorithmic bytes for the variant's Q."""
     from workloads import configs
     from workloads import geometry as G
     out = {}
