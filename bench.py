@@ -50,9 +50,9 @@ def kernel_sources_hash():
 
 
 def algorithmic_bytes(Q, s, n_nodes, n_fluid, n_links):
-    """Bytes one forward step must move by the per-unit count of the scope
-    table: each fluid node reads and writes Q values (2 Q s), each cut link
-    moves 48 bytes of link data, and each node one byte of its type."""
+    """Algorithmic bytes of one forward step: each fluid node reads and
+    writes Q values (2 Q s), each cut link moves 48 bytes of link data, and
+    each node one byte of its type."""
     return 2 * Q * s * n_fluid + 48 * n_links + n_nodes
 
 
