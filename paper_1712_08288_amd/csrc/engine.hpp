@@ -49,7 +49,7 @@ struct Engine {
     int lattice = 0, precision = 0, Q = 0, D = 0;
     int device = 0;          // HIP device current at lbm_create
     int64_t nx = 0, ny = 0, nz = 0, N = 0;
-    int64_t S = 0;           // stride (values) between direction planes, >= N
+    int64_t S = 0;           // N rounded up to whole population blocks (velocity-plane stride)
     int graph_steps = 0;     // >0: replay captured graphs of this many steps
     bool poison = false;     // LBM_DEBUG: outputs filled with NaN before each step
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};   // by starting buffer
