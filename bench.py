@@ -266,12 +266,15 @@ def per_config_forward(binding, torch, windows=3):
     rest: MLUPS over all nodes, the HBM fraction by the algorithmic bytes
     2*Q*s*N_fluid + 48*N_links + N_nodes, and the fraction of the step's own access pattern on
     the same grid (periodic, no arithmetic).  Medians over `windows` timed
-    windows.  The 256^3 sphere packing is the headline line itself."""
+    windows.  The 256^3 sphere packing is the headline line itself; one
+    GPU's z-slab share of it (256x256x32) is measured here at its real
+    shape."""
     from workloads import configs
     plan = [("c1_couette_64", configs.c1_couette(64), ("fp64",), 640),
             ("c2_cylinders_2048", configs.c2_cylinders(), ("fp64", "fp32"), 200),
             ("c4_cylinder_1024x512", configs.c4_cylinder(), ("fp64", "fp32"), 200),
-            ("c5_porous_384x256x256", configs.c5_porous(), ("fp32",), 100)]
+            ("c5_porous_384x256x256", configs.c5_porous(), ("fp32",), 100),
+            ("c3_shard_256x256x32", configs.c3_shard(), ("fp32", "fp64"), 200)]
     out = {}
     for name, w, precs, steps in plan:
         geom = w.geometry()
@@ -298,6 +301,9 @@ def per_config_forward(binding, torch, windows=3):
             res["note"] = "0.6 MB working set, graph replay: launch-bound, not an HBM measurement"
         if name.startswith("c4"):
             res["note"] = "19-38 MB working set: runs partly from the 256 MB last-level cache"
+        if name.startswith("c3_shard"):
+            res["note"] = ("one of eight z-slabs of the 256^3 packing at its real shape "
+                           "(independent packing of the same density, periodic in z)")
         out[name] = res
         del geom
     return out

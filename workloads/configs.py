@@ -108,6 +108,22 @@ def c3_spheres(n=256, n_obst=120, seed=3, steps=500, rmin=10.0, rmax=20.0):
                     % (n, n_obst, rmin, rmax, steps))
 
 
+def c3_shard(nx=256, ny=256, nz=32, n_obst=15, seed=33, steps=500):
+    """One GPU's share of the 256^3 sphere packing split into eight z-slabs:
+    an independent 256x256x32 packing with the full-size density (120
+    spheres / 8 = 15, r~U[10,20]) and the same seam, so the step runs at a
+    shard's real shape (whole x rows, 2^21 nodes).  The slab is periodic in
+    z instead of exchanging halos."""
+    w = c3_spheres(n=nx, n_obst=n_obst, seed=seed, steps=steps)
+    w.name = "c3_shard_%dx%dx%d" % (nx, ny, nz)
+    w.shape = (nx, ny, nz)
+    w.make_geometry = lambda: G.random_spheres(nx, ny, nz, n_obst, 10.0, 20.0, seed,
+                                               x_bc="pressure")
+    w.description = ("D3Q19 MRT %dx%dx%d z-slab of sphere packing (%d spheres, r~U[10,20]), "
+                     "pressure-driven x (drho=1e-3), %d steps" % (nx, ny, nz, n_obst, steps))
+    return w
+
+
 def c4_cylinder(nx=1024, ny=512, steps=3000, u_in=0.05, radius=20.3,
                 center=(128.4, 256.2)):
     return Workload(
