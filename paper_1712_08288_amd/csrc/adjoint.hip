@@ -78,8 +78,10 @@ struct AdjArgs {
 
 // The per-link gradient sums of the sweep (see the header): gq at g[k] and
 // gs at g[L1 + k], with the gamma-derivatives of the coefficients they
-// need.  Pointers are few on purpose: every kernel argument the adjoint
-// keeps costs scalar registers, which bound its occupancy.
+// need.  In the kernel that reads step records g is instead the step's run
+// of a_k (one per link), summed later by k_link_sums.  Pointers are few on
+// purpose: every kernel argument the adjoint keeps costs scalar registers,
+// which bound its occupancy.
 struct LinkGrad {
     const LinkDeriv* deriv;
     double* g;
@@ -101,6 +103,37 @@ template <class T>
 __device__ __forceinline__ void link_gradient_rec(const LinkGrad& lg, const T* __restrict__ lk,
                                                   uint32_t k, double ak, double ws) {
     link_gradient(lg, k, ak, lk[k], lk[lg.L1 + k], lk[2 * lg.L1 + k], ws);
+}
+
+// The pending reverse steps on records: step j's a_k run at ak[j L1], the
+// link runs of its record at lk[j] and its wall-data factor ws[j], in the
+// order the steps were taken.
+template <class T>
+struct AkBatch {
+    const T* lk[kAkBatch];
+    double ws[kAkBatch];
+    int count;
+};
+
+// Their terms added to the two sums of every link, step by step in that
+// order (the same additions, in the same order, as one step at a time):
+// one thread per link, the sums and the coefficient derivatives read once.
+template <class T>
+__global__ void __launch_bounds__(BX)
+k_link_sums(const double* __restrict__ ak, AkBatch<T> b, LinkGrad lg, uint32_t L) {
+    const uint32_t k = blockIdx.x * BX + threadIdx.x;
+    if (k >= L) return;
+    const double d1 = lg.deriv[k].d1, d2 = lg.deriv[k].d2, d3 = lg.deriv[k].d3;
+    double gq = lg.g[k], gs = lg.g[lg.L1 + k];
+    for (int j = 0; j < b.count; ++j) {
+        const double a = ak[(size_t)j * lg.L1 + k];
+        const T* __restrict__ lk = b.lk[j];
+        gq += a * (d1 * (double)lk[k] + d2 * (double)lk[lg.L1 + k] +
+                   d3 * (double)lk[2 * lg.L1 + k]);
+        gs += a * b.ws[j];
+    }
+    lg.g[k] = gq;
+    lg.g[lg.L1 + k] = gs;
 }
 
 // Walk a node's cut links in direction order (links are sorted by node,
@@ -197,7 +230,7 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
     mu[i] += (T)(c.c2 * ak);
     mu[ib] += (T)(c.c3 * ak);
     if constexpr (UM)
-        link_gradient_rec(lgr, rec.fib, k, ak, p.wall_scale);
+        lgr.g[k] = ak;   // the step's a_k run; k_link_sums adds the terms
     else
         link_gradient(lgr, k, ak, f[ib], ldp<L::Q>(nxt, i, n), ldp<L::Q>(nxt, ib, n),
                       p.wall_scale);
@@ -581,10 +614,11 @@ k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
                 st.v[1][lane] = (T)(c.c3 * ak + dfx);
                 st.v[2][lane] = (T)(p.c0 * ak);
                 st.v[3][lane] = (T)(c.c1 * ak);
-                // the link's gradient sums: at once from the record (UM); else
+                // the link's gradient sums: with records a_k is stored into the
+                // step's run and k_link_sums adds the terms; else they are added
                 // once the node's lane has handed back f_ibar(y, t)
                 if constexpr (UM)
-                    link_gradient_rec(lgr, rec.fib, kl, ak, p.wall_scale);
+                    lgr.g[kl] = ak;
                 else
                     ak_park[wid][lane] = ak;
             }
@@ -774,7 +808,14 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* n
                                      : k_adjoint<L, T, XB, false, false, false>);
         const Params<L, T> prm = adj_params<L, T>(e);
         const StepRecord<T> r = um ? record_at<T>(e, rec) : StepRecord<T>{};
-        const LinkGrad lgr{e.d_lkderiv, e.d_gq, (uint32_t)std::max<int64_t>(e.n_links, 1)};
+        const size_t L1 = (size_t)std::max<int64_t>(e.n_links, 1);
+        if (um && !e.ak_buf) return hipErrorInvalidValue;
+        if (um && e.ak_pending == kAkBatch) {
+            const hipError_t fs = launch_link_sums(e);
+            if (fs != hipSuccess) return fs;
+        }
+        const LinkGrad lgr{e.d_lkderiv, um ? e.ak_buf + (size_t)e.ak_pending * L1 : e.d_gq,
+                           (uint32_t)L1};
         if (waves.count)
             hipLaunchKernelGGL(kern, dim3(wave_blocks(waves.count)), dim3(BX), 0, e.stream,
                                um ? nullptr : (const T*)fwd->f, r,
@@ -783,8 +824,38 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* n
                                NodeMeta{e.d_info, e.d_wave}, waves, e.d_lkcoef,
                                e.d_lktag, e.d_lkdir, e.d_lknode, lgr,
                                e.d_gglob, g, prm, a);
-        return hipGetLastError();
+        const hipError_t st = hipGetLastError();
+        if (st != hipSuccess || !um || !e.n_links) return st;
+        // a link with no fluid node in an active wave cannot exist, so every
+        // a_k of the run was written
+        e.ak_rec[e.ak_pending] = rec;
+        e.ak_ws[e.ak_pending] = e.wall_scale;
+        ++e.ak_pending;
+        // Eq. (211): the next step's deferred-c1 terms go into gq first
+        return e.two_node ? launch_link_sums(e) : hipSuccess;
     });
+}
+
+hipError_t launch_link_sums(Engine& e) {
+    if (e.ak_pending == 0) return hipSuccess;
+    const int count = e.ak_pending;
+    e.ak_pending = 0;
+    const uint32_t L1 = (uint32_t)std::max<int64_t>(e.n_links, 1);
+    const LinkGrad lgr{e.d_lkderiv, e.d_gq, L1};
+    const unsigned nb = (unsigned)((e.n_links + BX - 1) / BX);
+    auto go = [&](auto prec) -> hipError_t {
+        using T = decltype(prec);
+        AkBatch<T> b{};
+        for (int j = 0; j < count; ++j) {
+            b.lk[j] = record_at<T>(e, e.ak_rec[j]).fib;
+            b.ws[j] = e.ak_ws[j];
+        }
+        b.count = count;
+        hipLaunchKernelGGL((k_link_sums<T>), dim3(nb), dim3(BX), 0, e.stream, e.ak_buf, b, lgr,
+                           (uint32_t)e.n_links);
+        return hipGetLastError();
+    };
+    return e.precision == 1 ? go(float{}) : go(double{});
 }
 
 hipError_t launch_link_gradients(Engine& e, double* dq, double* dphi) {

@@ -408,6 +408,7 @@ int adjoint_begin(lbm_t* h) {
     if (!e.d_gq || e.gglob_len != nb || e.gq_len != (int64_t)L1) {
         free_dev(e.d_gq);
         free_dev(e.d_gglob);
+        free_dev(e.ak_buf);
         e.d_gs = nullptr;
         // the two per-link sums in one allocation: gq, then gs
         if (hipMalloc((void**)&e.d_gq, 2 * L1 * 8) != hipSuccess ||
@@ -417,6 +418,13 @@ int adjoint_begin(lbm_t* h) {
         e.gglob_len = nb;
         e.gq_len = (int64_t)L1;
     }
+    // on records: the a_k runs of the reverse steps whose link terms pend
+    if (e.adj_um && !e.ak_buf &&
+        hipMalloc((void**)&e.ak_buf, (size_t)lbe::kAkBatch * L1 * 8) != hipSuccess) {
+        e.ak_buf = nullptr;
+        return fail(h, LBM_ENOMEM, "device allocation of the link adjoint runs failed");
+    }
+    e.ak_pending = 0;
     if ((rc = zero(h, e.d_gq, 2 * L1 * 8))) return rc;
     if ((rc = zero(h, e.d_gglob, (size_t)nb * NC * 8))) return rc;
     if ((rc = zero(h, e.lam[0], lam_bytes))) return rc;
@@ -464,6 +472,12 @@ int adjoint_steps(lbm_t* h, int64_t n) {
                 }
             }
             if (um) {
+                // the pending link terms read the records about to be replaced
+                const hipError_t fs = len > 1 ? lbe::launch_link_sums(e) : hipSuccess;
+                if (fs != hipSuccess) {
+                    rc = fail(h, LBM_EDEVICE, std::string("link sums: ") + hipGetErrorString(fs));
+                    break;
+                }
                 // records of steps 0 .. len-2 (the run recorded step len-1)
                 for (int64_t k = 0; k + 1 < len; ++k) {
                     e.t = t_seg + k;
@@ -532,6 +546,12 @@ int adjoint_steps(lbm_t* h, int64_t n) {
     e.t = t_saved;
     // keep lambda at the sweep's current time in lam[0]
     if (lc != 0) std::swap(e.lam[0], e.lam[1]);
+    // the sums are complete between calls
+    if (rc == LBM_OK && um) {
+        const hipError_t fs = lbe::launch_link_sums(e);
+        if (fs != hipSuccess)
+            rc = fail(h, LBM_EDEVICE, std::string("link sums: ") + hipGetErrorString(fs));
+    }
     return rc;
 }
 
@@ -1367,6 +1387,7 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_gq);
     e.d_gs = nullptr;
     free_dev(e.d_gglob);
+    free_dev(e.ak_buf);
     free_dev(e.d_scratch);
     if (e.ev0) (void)hipEventDestroy(e.ev0);
     if (e.ev1) (void)hipEventDestroy(e.ev1);

@@ -14,6 +14,8 @@ constexpr int kWave = 64;
 // doubles of the fixed per-device scratch of the allocation-free entry points
 // (4 MiB)
 constexpr int64_t kNoAllocScratchDoubles = 1 << 19;
+// reverse steps on records whose link gradient terms are added in one pass
+constexpr int kAkBatch = 8;
 
 struct LinkCoef {        // per cut link, double: Eq. (213) coefficients
     double c1, c2, c3;   // on f_ibar(x_f,t), f'_i(x_f,t), f'_ibar(x_f,t)
@@ -132,6 +134,13 @@ struct Engine {
     double* d_gq = nullptr;             // per link: sum of a_k (dc1 f_ibar + dc2 f'_i + dc3 f'_ibar)
     double* d_gs = nullptr;             // per link: sum of a_k ws (the wall-data terms' factor);
                                         // d_gq + max(L, 1), same allocation
+    // reverse steps on records store a_k of every link (one run of max(L, 1)
+    // doubles per step, kAkBatch runs) and the terms of the pending steps
+    // are added to gq, gs in one pass, step by step in the order taken
+    double* ak_buf = nullptr;
+    int ak_pending = 0;
+    const void* ak_rec[kAkBatch] = {};  // the pending steps' records
+    double ak_ws[kAkBatch] = {};        // and their wall-data factors
     double* d_gglob = nullptr;          // per-block partials of dJ/dg (D) and dJ/ds (Q)
     int64_t gglob_len = 0;
     bool have_grad = false;
@@ -235,10 +244,15 @@ struct AdjointObjective {
 // One reverse step: lambda(t) from lambda(t+1) with the forward states at t
 // (`fwd`) and t+1 (`next`), accumulating the gradients.  rec: the record of
 // forward step t (rate gradients off; fwd and next are
-// then not read and may be null), or null to read the states.
+// then not read and may be null), or null to read the states.  With a
+// record the link gradient terms of the step stay pending (the record must
+// live until launch_link_sums); kAkBatch pending steps, or any step of an
+// Eq. (211) run, are summed at once.
 hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* next,
                                const void* rec, const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
+// the pending steps' link gradient terms into gq, gs (no-op if none pend)
+hipError_t launch_link_sums(Engine& e);
 hipError_t launch_adjoint_out(Engine& e, const void* lam, double* out);
 // per-link gradients from the sweep's sums, in the caller's link order, into
 // device buffers: dq (L doubles) and dphi (L*D, link-major); either may be

@@ -147,8 +147,9 @@ def test_velocity_mode_matches_oracle_reverse(case):
     """Rate gradients off: the reverse sweep reads the step records the
     forward steps wrote (velocity, link values; with Eq. (211) also the
     advected f_ibar of the next step) instead of the forward states.  Against
-    the oracle's reverse sweep at 1e-10, and against the state-reading sweep
-    of the same run (the same arithmetic on the same values)."""
+    the oracle's reverse sweep at 1e-10, against the state-reading sweep
+    of the same run (the same arithmetic on the same values), and with every
+    step recorded bit for bit against the run checkpointed every 3 steps."""
     name, mk_geom, mk_s, kw, obj, steps = case
     geom, s = mk_geom(), mk_s()
     print("case", name, flush=True)
@@ -166,6 +167,13 @@ def test_velocity_mode_matches_oracle_reverse(case):
     sv, J2, gf = _gpu_grad(geom, s, kw, obj, steps, 3, df0)
     sv.close()
     assert J == J2
+    # every step recorded: the link terms of up to eight steps are summed at
+    # once instead of three, in the same order, so the result is the same bits
+    sv, J1, g1 = _gpu_grad(geom, s, kw, obj, steps, 1, df0, rates=False)
+    sv.close()
+    assert J1 == J
+    for key in ("q", "wall_u", "g", "lam0"):
+        assert np.array_equal(g1[key], gu[key]), key
     fl = geom.solid == 0
     for key in ("q", "wall_u", "g"):
         if r[key].size == 0:
