@@ -261,6 +261,37 @@ def pattern_rate(binding, torch, lattice, shape, prec, Q):
     return 2 * Q * n * (4 if prec == "fp32" else 8) / (ms * 1e-3) / 1e9
 
 
+def fwd_rev(sv, steps, every, torch):
+    """Forward + adjoint of `steps` steps (checkpoint every `every`; the
+    mean-u_x objective over them, gradients in g and every q, rate gradients
+    off so the reverse sweep reads step records).  One untimed cycle
+    allocates the checkpoints, the replay pool and the adjoint arrays (kept);
+    the second is timed.  The per-link gradients end in device tensors, as
+    the autograd path returns them.  Returns J, the gradients and the
+    forward and reverse ms per step; the state is restored."""
+    sv.set_rate_gradient(False)
+    state0 = torch.empty(sv.state_bytes(), dtype=torch.uint8, device="cuda")
+    sv.get_state(state0)
+    t_start = sv.time
+    nl = sv.counts()[1]
+    dq_dev = torch.empty(nl, dtype=torch.float64, device="cuda")
+    du_dev = torch.empty((nl, 3), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        sv.set_state(state0, t_start)
+        sv.set_objective("mean_ux", 0, t_start, t_start + steps)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sv.run_checkpointed(steps, every)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        sv.adjoint()
+        gr = sv.grad_device(dq_dev, du_dev)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+    sv.set_state(state0, t_start)
+    return sv.objective(), gr, (b - a) * 1e3 / steps, (c - b) * 1e3 / steps
+
+
 def per_config_forward(binding, torch, windows=3):
     """The forward step of every workload in its benchmark precisions, from
     rest: MLUPS over all nodes, the HBM fraction by the algorithmic bytes
@@ -286,6 +317,13 @@ def per_config_forward(binding, torch, windows=3):
             sv.init()
             sv.step(20)
             walls, kers = timed_windows(sv, steps, windows)
+            rev = None
+            if name.startswith("c3_shard") and prec == "fp32":
+                # the reverse sweep at the shard's shape too: 64 steps, every
+                # step recorded
+                _, _, ms_f, ms_r = fwd_rev(sv, 64, 1, torch)
+                rev = {"ms_per_step_forward_recording": round(ms_f, 5),
+                       "ms_per_step_reverse": round(ms_r, 5)}
             sv.close()
             ms, kms = float(np.median(walls)), float(np.median(kers))
             by = algorithmic_bytes(Q, s, geom.n_nodes, geom.n_fluid, geom.n_links)
@@ -297,6 +335,8 @@ def per_config_forward(binding, torch, windows=3):
                          "hbm_frac": round(by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                          "pattern_ceiling_GBps": round(pat, 1),
                          "frac_of_pattern": round(by / (kms * 1e-3) / 1e9 / pat, 4)}
+            if rev:
+                res[prec]["adjoint_every_step_recorded"] = rev
         if name.startswith("c1"):
             res["note"] = "0.6 MB working set, graph replay: launch-bound, not an HBM measurement"
         if name.startswith("c4"):
@@ -691,41 +731,14 @@ def main():
     # precisions; mean u_x over the window, gradients in g and every q
     A = args.adjoint_steps
 
-    def fwd_rev(sv, every):
-        """One untimed forward + reverse cycle allocates the checkpoints, the
-        replay pool and the adjoint arrays (kept); the second is timed.  The
-        per-link gradients end in device tensors, as the autograd path
-        returns them."""
-        sv.set_rate_gradient(False)
-        state0 = torch.empty(sv.state_bytes(), dtype=torch.uint8, device="cuda")
-        sv.get_state(state0)
-        t_start = sv.time
-        nl = sv.counts()[1]
-        dq_dev = torch.empty(nl, dtype=torch.float64, device="cuda")
-        du_dev = torch.empty((nl, 3), dtype=torch.float64, device="cuda")
-        for _ in range(2):
-            sv.set_state(state0, t_start)
-            sv.set_objective("mean_ux", 0, t_start, t_start + A)
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            sv.run_checkpointed(A, every)
-            torch.cuda.synchronize()
-            b = time.perf_counter()
-            sv.adjoint()
-            gr = sv.grad_device(dq_dev, du_dev)
-            torch.cuda.synchronize()
-            c = time.perf_counter()
-        sv.set_state(state0, t_start)
-        return sv.objective(), gr, (b - a) * 1e3 / A, (c - b) * 1e3 / A
-
     _progress("FP64 forward + adjoint")
-    J64, g64, ms64_fwd_ckpt, ms64_adj = fwd_rev(sv64, args.every)
+    J64, g64, ms64_fwd_ckpt, ms64_adj = fwd_rev(sv64, A, args.every, torch)
     sv64.close()
     _progress("FP32 forward + adjoint")
-    J32, g32, ms_fwd_ckpt, ms_adj = fwd_rev(sv32, args.every)
+    J32, g32, ms_fwd_ckpt, ms_adj = fwd_rev(sv32, A, args.every, torch)
     # every step recorded (no snapshot, no replay): A step records of 3
     # values per node and 3 per link, 14 GB at 256^3 FP32 with A = 64
-    _, _, ms_fwd_all, ms_adj_all = fwd_rev(sv32, 1)
+    _, _, ms_fwd_all, ms_adj_all = fwd_rev(sv32, A, 1, torch)
     sv32.close()
     torch.cuda.empty_cache()
 
