@@ -58,9 +58,10 @@ def algorithmic_bytes(Q, s, n_nodes, n_fluid, n_links):
 
 def kernel_bytes(Q, s, n_nodes, n_fluid, n_links):
     """The same with what this step kernel actually has to move: a 4-byte
-    node word per node, and per cut link its direction byte, four double
-    coefficients, one link-slot read and one link-slot write."""
-    return 2 * Q * s * n_fluid + 4 * n_nodes + n_links * (1 + 32 + 2 * s)
+    node word per node, and per cut link its direction byte, four
+    coefficients in the populations' precision, one link-slot read and one
+    link-slot write (25 bytes in FP32, 49 in FP64)."""
+    return 2 * Q * s * n_fluid + 4 * n_nodes + n_links * (1 + 4 * s + 2 * s)
 
 
 def timed_windows(sv, steps, windows):

@@ -60,7 +60,8 @@ enum {
 enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q15 = 2 };
 
 /* precision: FP64 stores and computes delta f in double; FP32 stores and
- * computes delta f in float.  In both, the per-link coefficients, the
+ * computes delta f in float.  In both, the per-link coefficients are
+ * computed in double (and stored in the populations' precision), and the
  * boundary combination, reductions and gradient sums are double. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1 };
 

@@ -213,7 +213,7 @@ template <class L, class T, int i, bool UM>
 __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict__ lam_in,
                                                 const T* __restrict__ nxt,
                                                 const StepRecord<T>& rec, uint32_t n,
-                                                const LinkCoef* __restrict__ lkcoef,
+                                                const LinkCoefT<T>* __restrict__ lkcoef,
                                                 const int32_t* __restrict__ lktag,
                                                 const LinkGrad& lgr,
                                                 const Params<L, T>& p, const AdjArgs& a,
@@ -226,7 +226,7 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
         ak += dfx;
         mu[ib] += (T)dfx;
     }
-    const LinkCoef c = lkcoef[k];
+    const LinkCoefT<T> c = lkcoef[k];
     mu[i] += (T)(c.c2 * ak);
     mu[ib] += (T)(c.c3 * ak);
     if constexpr (UM)
@@ -242,7 +242,7 @@ __device__ __forceinline__ void own_link_direct(uint32_t k, const T* __restrict_
 template <class L, class T, int i>
 __device__ __forceinline__ void own_link_bypass(uint32_t k, const T* __restrict__ lam_in,
                                                 uint32_t n,
-                                                const LinkCoef* __restrict__ lkcoef,
+                                                const LinkCoefT<T>* __restrict__ lkcoef,
                                                 const int32_t* __restrict__ lktag,
                                                 const Params<L, T>& p, const AdjArgs& a,
                                                 T (&mu)[L::Q]) {
@@ -332,7 +332,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && UM ? 4 : 1)))
 k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
           const T* __restrict__ nxt,
           const T* __restrict__ lam_in, T* __restrict__ lam_out,
-          NodeMeta nm, WaveList wl, const LinkCoef* __restrict__ lkcoef,
+          NodeMeta nm, WaveList wl, const LinkCoefT<T>* __restrict__ lkcoef,
           const int32_t* __restrict__ lktag,
           const uint8_t* __restrict__ lkdir, const int32_t* __restrict__ lknode,
           LinkGrad lgr, double* __restrict__ gglob, Grid g, Params<L, T> p, AdjArgs a) {
@@ -583,7 +583,7 @@ k_adjoint(const T* __restrict__ A, StepRecord<T> rec, const T* __restrict__ wa,
             double lw = 0.0;
             double ak = 0.0;
             T fpi = T(0), fpib = T(0);
-            LinkCoef c{0.0, 0.0, 0.0, 0.0};
+            LinkCoefT<T> c{T(0), T(0), T(0), T(0)};
             if (link_lane) {
                 dir_data<L>(ld_dir, le, lw, lib);
                 c = lkcoef[kl];
@@ -821,7 +821,7 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* n
                                um ? nullptr : (const T*)fwd->f, r,
                                um ? nullptr : (const T*)fwd->wa, um ? nullptr : (const T*)next->f,
                                (const T*)lam_in, (T*)lam_out,
-                               NodeMeta{e.d_info, e.d_wave}, waves, e.d_lkcoef,
+                               NodeMeta{e.d_info, e.d_wave}, waves, coef_table<T>(e),
                                e.d_lktag, e.d_lkdir, e.d_lknode, lgr,
                                e.d_gglob, g, prm, a);
         const hipError_t st = hipGetLastError();

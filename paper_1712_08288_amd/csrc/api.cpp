@@ -247,7 +247,17 @@ int upload_coefficients(lbm_t* h) {
     std::vector<double> c4v, c1d, d1d;
     int rc = compute_coefficients(h, coef, der, c4v, c1d, d1d);
     if (rc) return rc;
-    if ((rc = upload(h, e.d_lkcoef, coef.data(), coef.size()))) return rc;
+    if (e.precision == LBM_FP32) {
+        std::vector<lbe::LinkCoefT<float>> cf(coef.size());
+        for (size_t k = 0; k < coef.size(); ++k)
+            cf[k] = {(float)coef[k].c1, (float)coef[k].c2, (float)coef[k].c3,
+                     (float)coef[k].wall};
+        // the upload is asynchronous: keep the host copy alive until the sync
+        if ((rc = upload(h, e.d_lkcoef_f, cf.data(), cf.size()))) return rc;
+        if ((rc = sync(h))) return rc;
+    } else if ((rc = upload(h, e.d_lkcoef, coef.data(), coef.size()))) {
+        return rc;
+    }
     if ((rc = upload(h, e.d_lkderiv, der.data(), der.size()))) return rc;
     if ((rc = upload(h, e.d_lkc4, c4v.data(), c4v.size()))) return rc;
     if ((rc = upload(h, e.d_lkc1d, c1d.data(), c1d.size()))) return rc;
@@ -1379,6 +1389,7 @@ int lbm_destroy(lbm_t* h) {
     free_dev(e.d_perm);
     free_dev(e.d_lktag);
     free_dev(e.d_lkcoef);
+    free_dev(e.d_lkcoef_f);
     free_dev(e.d_lkderiv);
     free_dev(e.d_lkc4);
     free_dev(e.d_lkc1d);

@@ -17,10 +17,15 @@ constexpr int64_t kNoAllocScratchDoubles = 1 << 19;
 // reverse steps on records whose link gradient terms are added in one pass
 constexpr int kAkBatch = 8;
 
-struct LinkCoef {        // per cut link, double: Eq. (213) coefficients
-    double c1, c2, c3;   // on f_ibar(x_f,t), f'_i(x_f,t), f'_ibar(x_f,t)
-    double wall;         // c4 * 3 w_i rho0 e_i.phi
+// per cut link: the Eq. (213) coefficients, computed in double on the host
+// and stored in the precision of the populations (an FP32 handle combines
+// them in double all the same)
+template <class T>
+struct LinkCoefT {
+    T c1, c2, c3;        // on f_ibar(x_f,t), f'_i(x_f,t), f'_ibar(x_f,t)
+    T wall;              // c4 * 3 w_i rho0 e_i.phi
 };
+using LinkCoef = LinkCoefT<double>;
 
 struct LinkDeriv {       // d/dgamma of c1, c2, c3 and of the wall term
     double d1, d2, d3, dwall;
@@ -83,7 +88,8 @@ struct Engine {
     int32_t* d_lknode = nullptr;
     int32_t* d_perm = nullptr;          // sorted link k -> caller index
     int32_t* d_lktag = nullptr;
-    LinkCoef* d_lkcoef = nullptr;
+    LinkCoefT<double>* d_lkcoef = nullptr;   // FP64 handles
+    LinkCoefT<float>* d_lkcoef_f = nullptr;  // FP32 handles
     LinkDeriv* d_lkderiv = nullptr;
     double* d_lkc4 = nullptr;           // c4 per link (for dJ/dphi)
     bool two_node = false;              // Eq. (211) instead of Eq. (210)
@@ -170,6 +176,15 @@ struct Engine {
 inline int64_t record_values(const Engine& e) {
     return (int64_t)e.D * e.S + 3 * (e.n_links > 0 ? e.n_links : 1);
 }
+// the coefficient table of a handle of precision T
+template <class T>
+const LinkCoefT<T>* coef_table(const Engine& e) {
+    if constexpr (sizeof(T) == 4)
+        return e.d_lkcoef_f;
+    else
+        return e.d_lkcoef;
+}
+
 template <class T>
 StepRecord<T> record_at(const Engine& e, const void* rec) {
     T* base = (T*)rec;

@@ -38,7 +38,7 @@ static_assert(BX == kBlock && BX % 64 == 0, "node launches use kBlock-thread blo
 template <class L, class T, bool REC>
 __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fpre)[L::Q],
                                                const T (&f)[L::Q],
-                                               const LinkCoef* __restrict__ lkcoef,
+                                               const LinkCoefT<T>* __restrict__ lkcoef,
                                                T* __restrict__ waB, double c0d, double ws,
                                                uint32_t wbase,
                                                uint32_t nlw, uint32_t lane, LinkStage<T>& st,
@@ -57,7 +57,7 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
                         st.v[2][k] = f[i];
                         st.v[3][k] = f[ib];
                     } else {
-                        const LinkCoef c = lkcoef[wbase + k];
+                        const LinkCoefT<T> c = lkcoef[wbase + k];
                         const double v = c0d * (double)fpre[i] + c.c1 * (double)fpre[ib] +
                                          c.c2 * (double)f[i] + c.c3 * (double)f[ib] + ws * c.wall;
                         waB[wbase + k] = (T)v;
@@ -74,7 +74,7 @@ __device__ __forceinline__ void wave_link_tail(const NodeLinks& nl, const T (&fp
     }
     wave_lds_sync();
     if (lane < nlw) {
-        const LinkCoef c = lkcoef[wbase + lane];
+        const LinkCoefT<T> c = lkcoef[wbase + lane];
         const double v = c0d * (double)st.v[0][lane] + c.c1 * (double)st.v[1][lane] +
                          c.c2 * (double)st.v[2][lane] + c.c3 * (double)st.v[3][lane] + ws * c.wall;
         waB[wbase + lane] = (T)v;
@@ -108,7 +108,7 @@ __device__ __forceinline__ double objective_term(const StepObjective& ob, uint32
 template <class L, class T, int XB, bool ROWS, bool REC>
 __global__ void __launch_bounds__(BX)
 k_step(const T* __restrict__ A, T* __restrict__ B, const T* __restrict__ waA,
-       T* __restrict__ waB, NodeMeta nm, const LinkCoef* __restrict__ lkcoef,
+       T* __restrict__ waB, NodeMeta nm, const LinkCoefT<T>* __restrict__ lkcoef,
        Grid g, Params<L, T> p, StepObjective ob, StepRecord<T> rec) {
     __shared__ LinkStage<T> stage[BX / 64];
     __shared__ double c1s[BX / 64][64];   // Eq. (211): c1 of the wave's links
@@ -526,7 +526,7 @@ hipError_t launch_step(Engine& e, const Snapshot& in, const Snapshot& out,
         const StepRecord<T> r = rec ? record_at<T>(e, rec) : StepRecord<T>{};
         hipLaunchKernelGGL(kern, dim3(launch_blocks(g)), dim3(BX), 0,
                            e.stream, (const T*)in.f, (T*)out.f, (const T*)in.wa,
-                           (T*)out.wa, meta(e), e.d_lkcoef, g,
+                           (T*)out.wa, meta(e), coef_table<T>(e), g,
                            make_params<L, T>(e), obj, r);
         return hipGetLastError();
     });
