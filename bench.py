@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per k_step<D3Q19, float> launch on this workload from rocprofv3
 # FETCH_SIZE/WRITE_SIZE (scaled by a copy of known size), valid for the
 # kernel sources with this hash (profiles/k_step_d3q19_fp32_spheres256.md).
-MEASURED_TRAFFIC = {"sources_sha256_16": "e5b6a029cea5adee", "bytes": 2628893433}
+MEASURED_TRAFFIC = {"sources_sha256_16": "1672476243682091", "bytes": 2600527467}
 KERNEL_SOURCES = ["paper_1712_08288_amd/csrc/forward.hip",
                   "paper_1712_08288_amd/csrc/kernels.hpp",
                   "paper_1712_08288_amd/csrc/lattice.hpp"]
