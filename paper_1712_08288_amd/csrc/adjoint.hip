@@ -118,14 +118,20 @@ struct AkBatch {
 // Their terms added to the two sums of every link, step by step in that
 // order (the same additions, in the same order, as one step at a time):
 // one thread per link, the sums and the coefficient derivatives read once.
+// tq (Eq. (211) runs, else null): the pre-pass's gq term of each step, in
+// the layout of ak.
 template <class T>
 __global__ void __launch_bounds__(BX)
-k_link_sums(const double* __restrict__ ak, AkBatch<T> b, LinkGrad lg, uint32_t L) {
+k_link_sums(const double* __restrict__ ak, const double* __restrict__ tq, AkBatch<T> b,
+            LinkGrad lg, uint32_t L) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     if (k >= L) return;
     const double d1 = lg.deriv[k].d1, d2 = lg.deriv[k].d2, d3 = lg.deriv[k].d3;
     double gq = lg.g[k], gs = lg.g[lg.L1 + k];
     for (int j = 0; j < b.count; ++j) {
+        // Eq. (211): the pre-pass's term of step j comes first, as when the
+        // pre-pass added it itself
+        if (tq) gq += tq[(size_t)j * lg.L1 + k];
         const double a = ak[(size_t)j * lg.L1 + k];
         const T* __restrict__ lk = b.lk[j];
         gq += a * (d1 * (double)lk[k] + d2 * (double)lk[lg.L1 + k] +
@@ -663,12 +669,15 @@ k_two_node_pre(const T* __restrict__ A_next, const T* __restrict__ fib_next,
                T* __restrict__ lam_in,
                const int32_t* __restrict__ lknode, const uint8_t* __restrict__ lkdir,
                const int32_t* __restrict__ lktag, const double* __restrict__ c1d,
-               const double* __restrict__ d1d, double* __restrict__ gq,
+               const double* __restrict__ d1d, double* __restrict__ gq, int store,
                uint32_t n_links, Grid g, Params<L, T> p, AdjArgs a) {
     const uint32_t k = blockIdx.x * BX + threadIdx.x;
     if (k >= n_links) return;
     const double c = c1d[k];
-    if (c == 0.0) return;
+    if (c == 0.0) {
+        if (store) gq[k] = 0.0;
+        return;
+    }
     const int i = lkdir[k];
     const uint32_t n = (uint32_t)lknode[k];
     int ib = 0, ex = 0;
@@ -684,7 +693,11 @@ k_two_node_pre(const T* __restrict__ A_next, const T* __restrict__ fib_next,
     T* dst = lam_in + pop_at<L::Q>(ib, n);
     *dst = (T)((double)*dst + c * ak);
     const T fib = fib_next ? fib_next[k] : pull_one<L, T, XB>(A_next, g, p, n, ib);
-    gq[k] += ak * d1d[k] * (double)fib;
+    // store: the step's run of terms that k_link_sums adds (record sweeps)
+    if (store)
+        gq[k] = ak * d1d[k] * (double)fib;
+    else
+        gq[k] += ak * d1d[k] * (double)fib;
 }
 
 // The value f_ibar(x_f, t) that the pull of the opposite direction reads at
@@ -831,8 +844,7 @@ hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* n
         e.ak_rec[e.ak_pending] = rec;
         e.ak_ws[e.ak_pending] = e.wall_scale;
         ++e.ak_pending;
-        // Eq. (211): the next step's deferred-c1 terms go into gq first
-        return e.two_node ? launch_link_sums(e) : hipSuccess;
+        return hipSuccess;
     });
 }
 
@@ -851,7 +863,8 @@ hipError_t launch_link_sums(Engine& e) {
             b.ws[j] = e.ak_ws[j];
         }
         b.count = count;
-        hipLaunchKernelGGL((k_link_sums<T>), dim3(nb), dim3(BX), 0, e.stream, e.ak_buf, b, lgr,
+        hipLaunchKernelGGL((k_link_sums<T>), dim3(nb), dim3(BX), 0, e.stream, e.ak_buf,
+                           e.two_node ? (const double*)e.tq_buf : nullptr, b, lgr,
                            (uint32_t)e.n_links);
         return hipGetLastError();
     };
@@ -885,6 +898,16 @@ hipError_t launch_two_node_adjoint(Engine& e, const Snapshot* next, const void* 
     a.x_in = a.x_out = 0u;
     a.a_in = a.a_out = 0.0;
     const unsigned nb = (unsigned)((e.n_links + BX - 1) / BX);
+    // on records (fib_next given) the term goes into the step's run of
+    // tq_buf, the run the following launch_adjoint_step fills in ak_buf
+    const bool store = fib_next != nullptr;
+    if (store && !e.tq_buf) return hipErrorInvalidValue;
+    if (store && e.ak_pending == kAkBatch) {
+        const hipError_t fs = launch_link_sums(e);
+        if (fs != hipSuccess) return fs;
+    }
+    double* gq = store ? e.tq_buf + (size_t)e.ak_pending * (size_t)std::max<int64_t>(e.n_links, 1)
+                       : e.d_gq;
     return adj_dispatch(e, [&](auto lat, auto prec, auto xb) -> hipError_t {
         using L = decltype(lat);
         using T = decltype(prec);
@@ -892,7 +915,7 @@ hipError_t launch_two_node_adjoint(Engine& e, const Snapshot* next, const void* 
         hipLaunchKernelGGL((k_two_node_pre<L, T, XB>), dim3(nb), dim3(BX), 0, e.stream,
                            next ? (const T*)next->f : nullptr, (const T*)fib_next,
                            (T*)lam_in, e.d_lknode, e.d_lkdir, e.d_lktag,
-                           e.d_lkc1d, e.d_lkd1d, e.d_gq, (uint32_t)e.n_links, g,
+                           e.d_lkc1d, e.d_lkd1d, gq, store ? 1 : 0, (uint32_t)e.n_links, g,
                            adj_params<L, T>(e), a);
         return hipGetLastError();
     });

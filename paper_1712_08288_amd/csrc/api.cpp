@@ -419,6 +419,7 @@ int adjoint_begin(lbm_t* h) {
         free_dev(e.d_gq);
         free_dev(e.d_gglob);
         free_dev(e.ak_buf);
+        free_dev(e.tq_buf);
         e.d_gs = nullptr;
         // the two per-link sums in one allocation: gq, then gs
         if (hipMalloc((void**)&e.d_gq, 2 * L1 * 8) != hipSuccess ||
@@ -432,6 +433,11 @@ int adjoint_begin(lbm_t* h) {
     if (e.adj_um && !e.ak_buf &&
         hipMalloc((void**)&e.ak_buf, (size_t)lbe::kAkBatch * L1 * 8) != hipSuccess) {
         e.ak_buf = nullptr;
+        return fail(h, LBM_ENOMEM, "device allocation of the link adjoint runs failed");
+    }
+    if (e.adj_um && e.two_node && !e.tq_buf &&
+        hipMalloc((void**)&e.tq_buf, (size_t)lbe::kAkBatch * L1 * 8) != hipSuccess) {
+        e.tq_buf = nullptr;
         return fail(h, LBM_ENOMEM, "device allocation of the link adjoint runs failed");
     }
     e.ak_pending = 0;
@@ -1399,6 +1405,7 @@ int lbm_destroy(lbm_t* h) {
     e.d_gs = nullptr;
     free_dev(e.d_gglob);
     free_dev(e.ak_buf);
+    free_dev(e.tq_buf);
     free_dev(e.d_scratch);
     if (e.ev0) (void)hipEventDestroy(e.ev0);
     if (e.ev1) (void)hipEventDestroy(e.ev1);

@@ -144,6 +144,9 @@ struct Engine {
     // doubles per step, kAkBatch runs) and the terms of the pending steps
     // are added to gq, gs in one pass, step by step in the order taken
     double* ak_buf = nullptr;
+    // Eq. (211) on records: the pre-pass's gq term of each pending step
+    // (same layout), added just before that step's own terms
+    double* tq_buf = nullptr;
     int ak_pending = 0;
     const void* ak_rec[kAkBatch] = {};  // the pending steps' records
     double ak_ws[kAkBatch] = {};        // and their wall-data factors
@@ -261,8 +264,7 @@ struct AdjointObjective {
 // forward step t (rate gradients off; fwd and next are
 // then not read and may be null), or null to read the states.  With a
 // record the link gradient terms of the step stay pending (the record must
-// live until launch_link_sums); kAkBatch pending steps, or any step of an
-// Eq. (211) run, are summed at once.
+// live until launch_link_sums); kAkBatch pending steps are summed at once.
 hipError_t launch_adjoint_step(Engine& e, const Snapshot* fwd, const Snapshot* next,
                                const void* rec, const void* lam_in, void* lam_out,
                                const AdjointObjective& obj);
@@ -277,7 +279,9 @@ hipError_t launch_link_gradients(Engine& e, double* dq, double* dphi);
 // f_ibar(x_f, t+1) and add the gamma-derivative of that term, with
 // f_ibar(x_f, t+1) pulled from the forward state at t+1 (`next`) or read
 // from fib_next (L values of T: the link run of the record of step t+1);
-// exactly one of the two is given.
+// exactly one of the two is given.  With fib_next (a sweep on records) the
+// gamma-derivative term stays pending with the step that launch_adjoint_step
+// takes next.
 hipError_t launch_two_node_adjoint(Engine& e, const Snapshot* next, const void* fib_next,
                                    void* lam_in, const AdjointObjective& obj);
 // out[k] = f_ibar(x_f, t) as the pull of the opposite direction at link k's
